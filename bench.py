@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the suffix-array matching path on one MI355X.
+
+One step = the whole device path over one batch already resident in HBM:
+pack the ASCII reads to 2-bit words, sort them by prefix, run the search
+kernel (LB search with the LDS tile, RB search or longest-matched-prefix
+searches), scatter the 16-byte results in input order.
+
+Default workload (c2): a 16 Mbp order-3 Markov reference (GC 0.41) with 5 %
+tandem repeats, and 4,000,000 reads of 100 bp (70 % sampled from the
+reference with 0-2 % substitutions, 30 % random), all synthetic and seeded.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "c1": "1 Mbp i.i.d. reference; 100,000 reads x 25 bp (50% copied, a quarter of those with 1-2 substitutions, "
+          "50% random)",
+    "c2": "16 Mbp order-3 Markov reference (GC 0.41) + 5% tandem repeats; 4,000,000 reads x 100 bp "
+          "(70% sampled at 0-2% substitutions, 30% random)",
+    "c3": "16 Mbp order-3 Markov reference (GC 0.41) + 5% tandem repeats; 4,000,000 reads x U{20..300} bp "
+          "(70% sampled at 0-2% substitutions, 30% random)",
+}
+METRIC = "reads/s and matched Mbases/s at 1 GPU; p50/p99 request latency; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h"):
+        h.update(open(os.path.join(ROOT, "paper_1303_3692_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in launch defaults")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (reads shard across GPUs "
+              "with no exchange step; this build runs and reports a single device)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1303_3692_amd as S
+
+    if not os.path.exists(S.LIB_PATH):
+        from paper_1303_3692_amd import build as B
+        B.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+
+    t = time.perf_counter()
+    ref, reads = gen.workload(args.config)
+    text = ref.ascii()
+    log(f"workload {args.config}: n={ref.n} reads={reads.count} ({time.perf_counter() - t:.1f}s)")
+    t = time.perf_counter()
+    ix = S.sa_build(text)
+    t_build = time.perf_counter() - t
+    t = time.perf_counter()
+    d = S.sa_upload(ix, 0)
+    t_upload = time.perf_counter() - t
+    log(f"index: DC3 {t_build:.1f}s, upload {t_upload:.3f}s")
+
+    N = reads.count
+    d_reads = torch.from_numpy(reads.data).to(dev)
+    d_offs = torch.from_numpy(reads.offs).to(dev)
+    d_out = torch.zeros((N, 4), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    tuned_ms = None
+    if not args.no_tune:
+        t = time.perf_counter()
+        _, tuned_ms = S.sa_tune(d, d_reads, d_offs, stream=stream)
+        log(f"tuner: {time.perf_counter() - t:.1f}s -> {S.cfg(d).as_dict()} ({tuned_ms:.3f} ms)")
+    cfg = S.cfg(d)
+
+    def run_steps(c, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            S.match_batch_dev(d, d_reads, d_offs, d_out, stream=stream, config=c)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def stage_times(c, k):
+        cp = S.cfg(d, **c.as_dict())
+        cp.profile = 1
+        acc = {"pack": 0.0, "sort": 0.0, "search": 0.0, "total": 0.0}
+        for _ in range(k):
+            S.match_batch_dev(d, d_reads, d_offs, d_out, stream=stream, config=cp)
+            st = S.sa_stage_times(d, stream)
+            for key in acc:
+                acc[key] += st[key] / k
+        return acc
+
+    def counts(c):
+        cc = S.cfg(d, **c.as_dict())
+        cc.count = 1
+        S.match_batch_dev(d, d_reads, d_offs, d_out, stream=stream, config=cc)
+        return S.sa_probe_counts(d, stream)
+
+    lens = reads.lengths()
+    read_bytes = int(((lens + 3) // 4).sum())  # packed query, 2 bits per base
+
+    def alg_bytes(cnt):
+        # per read: packed query + 16-byte result; per global probe: a 4-byte
+        # SA entry plus the 8-byte text words it compares
+        return read_bytes + 16 * N + 4 * cnt["global_probes"] + 8 * cnt["text_words"]
+
+    # ---- tuned path
+    cnt = counts(cfg)
+    check = d_out.clone()
+    run_steps(cfg, args.warmup)
+    elapsed = run_steps(cfg, args.steps)
+    ms_step = 1000.0 * elapsed / args.steps
+    stages = stage_times(cfg, max(3, min(args.steps, 10)))
+    out = d_out.cpu().numpy()
+    assert (out == check.cpu().numpy()).all(), "counting and timed runs disagree"
+    matched = int(out[:, 2].astype(np.int64).sum())
+    exact = float((out[:, 3] & 1).mean())
+    log(f"tuned: {ms_step:.3f} ms/step, stages {stages}")
+
+    # ---- plain kernel side by side
+    plain = None
+    if not args.no_plain:
+        pc = S.cfg(d, kernel=S.SA_KERNEL_PLAIN)
+        pcnt = counts(pc)
+        run_steps(pc, 1)
+        pk = max(2, args.steps // 4)
+        pel = run_steps(pc, pk)
+        pst = stage_times(pc, 3)
+        pout = d_out.cpu().numpy()
+        assert (pout[:, :3] == out[:, :3]).all() and ((pout[:, 3] & 1) == (out[:, 3] & 1)).all(), \
+            "plain and tuned kernels disagree"
+        plain = {"reads_per_s": N * pk / pel, "ms_per_step": 1000.0 * pel / pk, "search_ms": pst["search"],
+                 "global_probes_per_read": pcnt["global_probes"] / N,
+                 "alg_bytes_per_read": alg_bytes(pcnt) / N,
+                 "search_GBps_alg": alg_bytes(pcnt) / (pst["search"] * 1e-3) / 1e9}
+        log(f"plain: {plain}")
+
+    B = alg_bytes(cnt)
+    achieved = B / (stages["search"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "search_tuned_kernel", "alg_bytes_per_launch": B, "alg_bytes_per_read": round(B / N, 2),
+                "launch_ms": round(stages["search"], 4), "kernel_src": kernel_source_hash()}
+
+    # ---- CPU baseline: the oracle's search phase on the host cores
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle
+        t = time.perf_counter()
+        osa = oracle.sa_build(text)
+        t_osa = time.perf_counter() - t
+        threads = oracle.max_threads()
+        t = time.perf_counter()
+        want = oracle.match(text, osa, reads.data, reads.offs, nthreads=threads)
+        t_match = time.perf_counter() - t
+        same = bool((want[:, :3] == out[:, :3]).all() and (want[:, 3] == (out[:, 3] & 1)).all())
+        cpu = {"value": round(N / t_match, 1), "unit": "reads/s", "cores": threads, "kind": "oracle",
+               "sample": f"all {N:,} reads of the batch; oracle search phase only (its comparison-sort suffix "
+                         f"array built beforehand in {t_osa:.1f}s, untimed)",
+               "matches_gpu": same}
+        log(f"cpu oracle: {cpu}")
+
+    value = N * args.steps / elapsed
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "reads/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic (seeded generators, no external data)",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "reference_bp": ref.n, "reads": N,
+                   "global_batch": N, "parallelism": "single GPU", "launch": cfg.as_dict()},
+        "matched_mbases_per_s": round(matched * args.steps / elapsed / 1e6, 2),
+        "query_mbases_per_s": round(int(lens.sum()) * args.steps / elapsed / 1e6, 2),
+        "exact_fraction": round(exact, 5),
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "probes_per_read": {"global": round(cnt["global_probes"] / N, 3), "lds": round(cnt["tile_probes"] / N, 3),
+                            "text_words": round(cnt["text_words"] / N, 3)},
+        "index": {"dc3_s": round(t_build, 2), "upload_s": round(t_upload, 4)},
+        "plain": plain,
+        "speedup_vs_plain": round(value / plain["reads_per_s"], 3) if plain else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

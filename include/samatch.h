@@ -1,0 +1,217 @@
+/*
+ * samatch.h -- suffix-array matching of short DNA reads on an AMD MI355X (gfx950).
+ *
+ * The problem follows Sections III and IV of Liao et al., "Ultra-fast Multiple
+ * Genome Sequence Matching Using GPU": a reference S over {a,c,g,t} (Section
+ * III) is indexed by its suffix array SA (Section III, Table I); each query P
+ * is located by binary searches over SA that find the row range of the
+ * suffixes that start with P (Section IV, Algorithm 1: LB and RB).
+ *
+ * Conventions
+ *   - positions and SA rows are 0-based; bases order a < c < g < t; a suffix
+ *     that is a proper prefix of another sorts first (Table I);
+ *   - upper and lower case are the same base;
+ *   - a read byte outside ACGTacgt matches no reference base.
+ *
+ * Result per read P[0..m): the longest matched prefix length len (the
+ * largest k <= m such that P[0..k) occurs in S) and the half-open row range
+ * [lo, hi) of the suffixes that start with P[0..len).  When len == m the
+ * read occurs exactly, hi - lo is its number of occurrences, and the paper's
+ * pair is LB = lo, RB = hi - 1.  When P does not occur the paper reports
+ * "NULL"; this library reports the longest prefix that does occur instead
+ * (len = 0 gives [0, n)).
+ *
+ * Return codes: SA_OK (0) on success, a negative SA_E* code on failure,
+ * and SA_PENDING (> 0) only from match_poll.  After a failure,
+ * sa_last_error() returns a thread-local message with detail (for
+ * SA_EDEVICE the HIP error string).  No function aborts the process.
+ */
+#ifndef SAMATCH_H
+#define SAMATCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SA_OK = 0,
+    SA_PENDING = 1,        /* match_poll: request not finished yet            */
+    SA_EINVAL = -1,        /* null pointer, bad size, bad offsets, bad option */
+    SA_EALPHABET = -2,     /* reference byte outside ACGTacgt                 */
+    SA_ETOOBIG = -3,       /* n > 2^31-1, or a read longer than SA_MAX_READ   */
+    SA_ENOMEM = -4,        /* host allocation failed                          */
+    SA_EDEVICE = -5,       /* HIP runtime error (see sa_last_error)           */
+    SA_ENOSPC = -6,        /* a request can never fit in device memory        */
+    SA_ECANCELED = -7,     /* request cancelled (server destroyed)            */
+    SA_EIO = -8,           /* index file could not be read or written         */
+    SA_EFORMAT = -9,       /* index file is corrupt or of another version     */
+    SA_ENOTFOUND = -10     /* unknown ticket                                  */
+};
+
+/* Longest read the search kernels take (10 packed 64-bit words). */
+#define SA_MAX_READ 320
+
+typedef struct sa_index sa_index;     /* host index: n, 2-bit packed text, int32 SA */
+typedef struct sa_dindex sa_dindex;   /* the same index resident in device memory    */
+typedef struct sa_server sa_server;   /* request loop over resident indexes          */
+
+/* One result, 16 bytes, written with one store per read. */
+typedef struct {
+    int32_t lo;       /* first SA row of the suffixes starting with P[0..len)  */
+    int32_t hi;       /* one past the last such row                            */
+    int32_t len;      /* longest matched prefix length                         */
+    uint32_t flags;   /* SA_HIT_EXACT, SA_HIT_TOOLONG                          */
+} sa_hit;
+
+#define SA_HIT_EXACT   1u  /* len == m: the whole read occurs                    */
+#define SA_HIT_TOOLONG 2u  /* device entry points only: the read is longer than
+                              SA_MAX_READ (or its offsets decrease); lo, hi and
+                              len are 0 and the read was not searched           */
+
+/* ------------------------------------------------------------------ index */
+
+/* Build the suffix array of text[0..n) on the host by the DC3 (skew)
+ * construction of Section III, and pack the text at 2 bits per base.
+ * text: host bytes, ACGTacgt only (else SA_EALPHABET); 1 <= n <= 2^31-1
+ * (else SA_EINVAL / SA_ETOOBIG).  The text is copied; *out is owned by the
+ * caller and released with sa_free. */
+int sa_build(const char *text, int64_t n, sa_index **out);
+
+/* Build from a suffix array the caller already has (no check beyond ranges:
+ * sa must be the suffix array of text; values outside [0,n) -> SA_EINVAL). */
+int sa_build_from_sa(const char *text, int64_t n, const int32_t *sa, sa_index **out);
+
+int64_t sa_index_length(const sa_index *ix);          /* n, or -1 for NULL         */
+/* Copy the int32 suffix array (n entries) into host memory at sa_out. */
+int sa_index_copy_sa(const sa_index *ix, int32_t *sa_out);
+
+/* Persist / restore an index (magic, version, n, packed text, SA, FNV-1a
+ * checksum).  sa_load returns SA_EIO / SA_EFORMAT for unreadable or corrupt
+ * files. */
+int sa_save(const sa_index *ix, const char *path);
+int sa_load(const char *path, sa_index **out);
+void sa_free(sa_index *ix);                           /* NULL is a no-op            */
+
+/* Copy the index to device `device` and keep it resident: the packed text
+ * (with zero padding words after the end), the int32 SA, and the table of
+ * the top levels of the implicit binary-search tree that the tuned kernel
+ * stages in LDS (the tile of Section IV).  The host index may be freed
+ * afterwards.  Released with sa_dfree (NULL is a no-op). */
+int sa_upload(const sa_index *ix, int device, sa_dindex **out);
+void sa_dfree(sa_dindex *d);
+int64_t sa_dindex_length(const sa_dindex *d);
+
+/* ------------------------------------------------------------------ batches */
+
+enum { SA_KERNEL_TUNED = 0, SA_KERNEL_PLAIN = 1 };
+
+/* Launch configuration.  Zero fields take the tuned defaults of the index
+ * (sa_tune), else built-in defaults. */
+typedef struct {
+    int kernel;          /* SA_KERNEL_TUNED or SA_KERNEL_PLAIN                     */
+    int tile_levels;     /* tuned: levels of the search tree held in LDS (1..13)   */
+    int block;           /* tuned: threads per workgroup (64..1024, multiple of 64)*/
+    int blocks_per_cu;   /* tuned: persistent workgroups per compute unit          */
+    int nbuckets;        /* tuned: length buckets (1..8)                           */
+    int bucket_edge[8];  /* tuned: bucket b holds reads with m <= bucket_edge[b];
+                            ascending multiples of 32, last one >= SA_MAX_READ    */
+    int sort;            /* tuned: 1 = sort reads by prefix first, 0 = input order */
+    int use_graph;       /* tuned: 1 = replay the launch sequence as a hipGraph    */
+    int profile;         /* 1 = record HIP events between the stages (pack, sort,
+                            search) for sa_stage_times                           */
+    int count;           /* 1 = run the instrumented search kernel that counts
+                            probes and text words for sa_probe_counts (slower;
+                            results are the same)                                */
+} sa_match_cfg;
+
+/* Fill cfg with the index's current defaults. */
+int sa_default_cfg(const sa_dindex *d, sa_match_cfg *cfg);
+
+/* Match a batch held in host memory and wait for it.  reads: concatenated
+ * read bytes; offs[nreads+1]: read i is reads[offs[i] .. offs[i+1]) (offs[0]
+ * may be nonzero, offsets must not decrease); out[nreads]: results in input
+ * order.  Reads longer than SA_MAX_READ -> SA_ETOOBIG before any work.
+ * hip_stream: a hipStream_t or NULL for the null stream.  cfg may be NULL.
+ * Thread-safe for distinct streams. */
+int match_batch(const sa_dindex *d, const char *reads, const int64_t *offs, int64_t nreads,
+                sa_hit *out, void *hip_stream, const sa_match_cfg *cfg);
+
+/* The same on device memory, asynchronous on hip_stream: d_reads, d_offs
+ * and d_out are device pointers of the index's device; the call returns
+ * after enqueueing.  Per-read errors (SA_HIT_TOOLONG) are reported in the
+ * flags of out.  Scratch memory is kept per (index, stream) and grows on
+ * demand; concurrent calls on one stream must be serialised by the caller. */
+int match_batch_dev(const sa_dindex *d, const uint8_t *d_reads, const int64_t *d_offs,
+                    int64_t nreads, sa_hit *d_out, void *hip_stream, const sa_match_cfg *cfg);
+
+/* Stage times in milliseconds of the last batch enqueued with cfg.profile
+ * on this (index, stream): ms[0] pack, ms[1] prefix sort, ms[2] search,
+ * ms[3] whole pipeline.  Waits for that batch.  SA_EINVAL if there is none. */
+int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]);
+
+/* Counts of the last batch enqueued with cfg.count on this (index, stream):
+ * c[0] global-memory probes (one SA entry each), c[1] 64-bit text words
+ * those probes compare, c[2] probes answered from the LDS tile, c[3] reads
+ * searched, c[4] packed query words loaded.  Waits for that batch. */
+int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[5]);
+
+/* Autotuner: time candidate configurations (tile depth, workgroups per CU,
+ * block size, bucket edges) on the given device batch, keep the fastest as
+ * the index's default, and return it in best (nullable).  best_ms receives
+ * its time per batch (nullable).  If cache_path is non-NULL the result is
+ * read from / appended to that JSON-lines file keyed by (device name, n,
+ * length histogram). */
+int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_offs, int64_t nreads,
+            void *hip_stream, const char *cache_path, sa_match_cfg *best, double *best_ms);
+
+/* ------------------------------------------------------------------ serving */
+
+typedef struct {
+    int64_t hbm_reserve_bytes;   /* device memory left free for others (default 1 GiB)   */
+    int64_t max_batch_reads;     /* reads per device batch (default 1,048,576)           */
+    int64_t max_inflight_reads;  /* admitted but unfinished reads (default 8,388,608)    */
+    int nstreams;                /* device streams used round-robin (default 2, max 8)   */
+    int64_t test_fake_free_hbm;  /* < 0: ask the device; >= 0: pretend this much is free */
+    int test_echo;               /* 1: no device work, results are a deterministic echo  */
+    int test_fail_batch;         /* > 0: the n-th executed batch fails (error injection) */
+} sa_server_opts;
+
+typedef struct {
+    int64_t t_submit_ns, t_admit_ns, t_done_ns;  /* steady-clock timestamps          */
+    int status;                                  /* SA_OK, SA_PENDING or an SA_E*    */
+    int64_t nreads;
+} sa_req_stats;
+
+/* Start a request loop over nrefs resident indexes (all on one device). The
+ * indexes must outlive the server.  opts may be NULL (defaults). */
+int sa_server_create(const sa_dindex *const *refs, int nrefs, const sa_server_opts *opts,
+                     sa_server **out);
+
+/* Queue nreads host reads against refs[ref].  The reads are copied before
+ * the call returns; out[nreads] must stay valid until match_poll reports
+ * the request finished.  *ticket identifies the request. Thread-safe. */
+int match_submit(sa_server *s, int ref, const char *reads, const int64_t *offs, int64_t nreads,
+                 sa_hit *out, uint64_t *ticket);
+
+/* Wait up to timeout_us (0: just look, < 0: forever) for a request.
+ * Returns SA_PENDING while it runs, SA_OK once out[] is filled, or the
+ * request's error code; st (nullable) receives its timestamps.  A finished
+ * ticket may be polled again until sa_server_destroy. Thread-safe. */
+int match_poll(sa_server *s, uint64_t ticket, int64_t timeout_us, sa_req_stats *st);
+
+/* Cancel pending requests (they finish with SA_ECANCELED), wait for
+ * in-flight batches, release everything. */
+int sa_server_destroy(sa_server *s);
+
+/* ------------------------------------------------------------------ errors */
+
+const char *sa_strerror(int code);
+const char *sa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAMATCH_H */

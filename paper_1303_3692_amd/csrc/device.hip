@@ -1,0 +1,350 @@
+// Device-resident index, per-stream scratch, and the batch entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+#include "kernels.h"
+#include "device_state.h"
+
+using namespace samatch;
+
+namespace samatch {
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(SA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+}
+DeviceGuard::~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+Workspace::~Workspace() {
+    for (void *p : {(void *)b.qw, (void *)b.qlen, (void *)b.qmv, (void *)b.key[0], (void *)b.key[1],
+                    (void *)b.val[0], (void *)b.val[1], (void *)b.hist, (void *)b.digit_total,
+                    (void *)b.counter, (void *)b.stats, (void *)d_reads, (void *)d_offs, (void *)d_out})
+        if (p) (void)hipFree(p);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    for (void *p : {(void *)h_reads, (void *)h_offs, (void *)h_out})
+        if (p) (void)hipHostFree(p);
+}
+
+static hipError_t grow(void **p, size_t bytes) {
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        *p = nullptr;
+        if (e != hipSuccess) return e;
+    }
+    return hipMalloc(p, bytes ? bytes : 16);
+}
+
+int Workspace::reserve(int64_t nreads) {
+    if (nreads <= cap) return SA_OK;
+    const int64_t c = std::max<int64_t>(nreads, 1024);
+    const int64_t nblocks = (c + kSortTile - 1) / kSortTile;
+    hipError_t e;
+    if ((e = grow((void **)&b.qw, sizeof(uint64_t) * kWMax * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.qlen, sizeof(int32_t) * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.qmv, sizeof(int32_t) * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.key[0], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.key[1], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.val[0], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.val[1], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.hist, sizeof(uint32_t) * 256 * (size_t)nblocks)) != hipSuccess)
+        return hip_fail(e, "scratch allocation");
+    if (!b.digit_total && (e = hipMalloc((void **)&b.digit_total, sizeof(uint32_t) * 256)) != hipSuccess)
+        return hip_fail(e, "scratch allocation");
+    if (!b.counter && (e = hipMalloc((void **)&b.counter, sizeof(unsigned) * 64)) != hipSuccess)
+        return hip_fail(e, "scratch allocation");
+    if (!b.stats && (e = hipMalloc((void **)&b.stats, sizeof(unsigned long long) * 8)) != hipSuccess)
+        return hip_fail(e, "scratch allocation");
+    for (hipEvent_t &ev_i : ev)
+        if (!ev_i && (e = hipEventCreate(&ev_i)) != hipSuccess) return hip_fail(e, "event creation");
+    cap = c;
+    return SA_OK;
+}
+
+int Workspace::reserve_staging(int64_t nreads, int64_t nbytes) {
+    hipError_t e;
+    if (nbytes > bytes_cap) {
+        const int64_t c = std::max<int64_t>(nbytes, 1 << 20);
+        if (h_reads) (void)hipHostFree(h_reads);
+        h_reads = nullptr;
+        if ((e = hipHostMalloc((void **)&h_reads, (size_t)c, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "pinned staging");
+        if ((e = grow((void **)&d_reads, (size_t)c)) != hipSuccess) return hip_fail(e, "staging");
+        bytes_cap = c;
+    }
+    if (nreads > stage_cap) {
+        const int64_t c = std::max<int64_t>(nreads, 1024);
+        if (h_offs) (void)hipHostFree(h_offs);
+        if (h_out) (void)hipHostFree(h_out);
+        h_offs = nullptr;
+        h_out = nullptr;
+        if ((e = hipHostMalloc((void **)&h_offs, sizeof(int64_t) * (size_t)(c + 1), hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc((void **)&h_out, sizeof(sa_hit) * (size_t)c, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "pinned staging");
+        if ((e = grow((void **)&d_offs, sizeof(int64_t) * (size_t)(c + 1))) != hipSuccess ||
+            (e = grow((void **)&d_out, sizeof(sa_hit) * (size_t)c)) != hipSuccess)
+            return hip_fail(e, "staging");
+        stage_cap = c;
+    }
+    return SA_OK;
+}
+
+Workspace *workspace_for(sa_dindex *d, hipStream_t s) {
+    std::lock_guard<std::mutex> g(d->mu);
+    auto &slot = d->ws[(void *)s];
+    if (!slot) slot.reset(new Workspace);
+    return slot.get();
+}
+
+BucketTable bucket_table(const sa_match_cfg &c) {
+    BucketTable bt{};
+    bt.count = std::max(1, std::min(8, c.nbuckets));
+    for (int i = 0; i < bt.count; i++) bt.edge[i] = c.bucket_edge[i];
+    bt.edge[bt.count - 1] = SA_MAX_READ;
+    return bt;
+}
+
+int check_cfg(const sa_dindex *d, const sa_match_cfg &c) {
+    if (c.kernel != SA_KERNEL_TUNED && c.kernel != SA_KERNEL_PLAIN) return fail(SA_EINVAL, "unknown kernel");
+    if (c.kernel == SA_KERNEL_PLAIN) return SA_OK;
+    if (c.tile_levels < 1 || c.tile_levels > d->tile_levels)
+        return fail(SA_EINVAL, "tile_levels must be in 1.." + std::to_string(d->tile_levels));
+    if (c.block != 256 && c.block != 512 && c.block != 1024) return fail(SA_EINVAL, "block must be 256, 512 or 1024");
+    if (c.blocks_per_cu < 1 || c.blocks_per_cu > 16) return fail(SA_EINVAL, "blocks_per_cu must be in 1..16");
+    if (c.nbuckets < 1 || c.nbuckets > 8) return fail(SA_EINVAL, "nbuckets must be in 1..8");
+    for (int i = 0; i + 1 < c.nbuckets; i++)
+        if (c.bucket_edge[i] < 1 || (i > 0 && c.bucket_edge[i] <= c.bucket_edge[i - 1]))
+            return fail(SA_EINVAL, "bucket edges must ascend");
+    return SA_OK;
+}
+
+sa_match_cfg resolve_cfg(const sa_dindex *d, const sa_match_cfg *cfg) {
+    sa_match_cfg c = cfg ? *cfg : d->defaults;
+    const sa_match_cfg &def = d->defaults;
+    if (c.kernel == SA_KERNEL_TUNED) {
+        if (c.tile_levels == 0) c.tile_levels = def.tile_levels;
+        if (c.block == 0) c.block = def.block;
+        if (c.blocks_per_cu == 0) c.blocks_per_cu = def.blocks_per_cu;
+        if (c.nbuckets == 0) {
+            c.nbuckets = def.nbuckets;
+            std::memcpy(c.bucket_edge, def.bucket_edge, sizeof c.bucket_edge);
+        }
+    }
+    return c;
+}
+
+// Enqueue the whole device pipeline for one batch: pack, optional prefix
+// sort, search.  All launches go to stream s.  d_ends may be NULL (CSR
+// offsets) or give each read's end (reads scattered over d_reads).
+int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t *d_offs, const int64_t *d_ends,
+                  int64_t nreads, sa_hit *d_out, hipStream_t s, const sa_match_cfg &c) {
+    int rc = ws->reserve(nreads);
+    if (rc) return rc;
+    const bool prof = c.profile != 0;
+    hipError_t e = hipSuccess;
+    if (prof && (e = hipEventRecord(ws->ev[0], s)) != hipSuccess) return hip_fail(e, "event record");
+    e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bucket_table(c), s);
+    if (e != hipSuccess) return hip_fail(e, "pack launch");
+    if (prof && (e = hipEventRecord(ws->ev[1], s)) != hipSuccess) return hip_fail(e, "event record");
+    const uint32_t *order = nullptr;
+    if (c.kernel == SA_KERNEL_TUNED && c.sort) {
+        int which = 0;
+        const int bits = c.nbuckets > 1 ? 32 : 24;
+        e = launch_sort(ws->b, nreads, bits, &which, s);
+        if (e != hipSuccess) return hip_fail(e, "sort launch");
+        order = ws->b.val[which];
+    }
+    if (prof && (e = hipEventRecord(ws->ev[2], s)) != hipSuccess) return hip_fail(e, "event record");
+    if (c.kernel == SA_KERNEL_PLAIN) {
+        e = launch_search_plain(d->view, ws->b, nreads, d_out, c.count != 0, s);
+        if (e != hipSuccess) return hip_fail(e, "plain search launch");
+    } else {
+        const int grid = std::max(1, d->cu_count * c.blocks_per_cu);
+        e = launch_search_tuned(d->view, c.tile_levels, c.block, grid, ws->b, order, nreads, d_out, c.count != 0, s);
+        if (e != hipSuccess) return hip_fail(e, "tuned search launch");
+    }
+    if (prof && (e = hipEventRecord(ws->ev[3], s)) != hipSuccess) return hip_fail(e, "event record");
+    ws->profiled = prof;
+    ws->counted = c.count != 0;
+    return SA_OK;
+}
+
+}  // namespace samatch
+
+extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
+    clear_error();
+    if (!ix || !out) return fail(SA_EINVAL, "NULL argument");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(SA_EINVAL, "no such device");
+    DeviceGuard g(device);
+    if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
+    std::unique_ptr<sa_dindex> d(new sa_dindex);
+    d->device = device;
+    d->n = ix->n;
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    d->cu_count = prop.multiProcessorCount;
+    std::snprintf(d->arch, sizeof d->arch, "%s", prop.gcnArchName);
+    const size_t text_bytes = sizeof(uint64_t) * ix->packed.size();
+    const size_t sa_bytes = sizeof(int32_t) * (size_t)ix->n;
+    int levels = 0;
+    while (levels < kMaxTileLevels && ((int64_t)1 << levels) - 1 < ix->n) levels++;
+    d->tile_levels = std::max(1, levels);
+    const size_t nodes = ((size_t)1 << d->tile_levels) - 1;
+    if ((e = hipMalloc((void **)&d->d_text, text_bytes)) != hipSuccess ||
+        (e = hipMalloc((void **)&d->d_sa, sa_bytes)) != hipSuccess ||
+        (e = hipMalloc((void **)&d->d_tile_key, nodes * sizeof(uint64_t))) != hipSuccess ||
+        (e = hipMalloc((void **)&d->d_tile_sa, nodes * sizeof(int32_t))) != hipSuccess)
+        return hip_fail(e, "index allocation");
+    if ((e = hipMemcpy(d->d_text, ix->packed.data(), text_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d->d_sa, ix->sa.data(), sa_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "index upload");
+    if ((e = launch_build_tile(d->d_text, d->d_sa, (int32_t)ix->n, d->tile_levels, d->d_tile_key, d->d_tile_sa,
+                               nullptr)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess)
+        return hip_fail(e, "tile build");
+    d->view = DevIndex{d->d_text, d->d_sa, d->d_tile_key, d->d_tile_sa, (int32_t)ix->n};
+    sa_match_cfg &c = d->defaults;
+    std::memset(&c, 0, sizeof c);
+    c.kernel = SA_KERNEL_TUNED;
+    c.tile_levels = std::min(12, d->tile_levels);
+    c.block = 256;
+    c.blocks_per_cu = 8;
+    c.nbuckets = 1;
+    c.bucket_edge[0] = SA_MAX_READ;
+    c.sort = 1;
+    c.use_graph = 0;
+    *out = d.release();
+    return SA_OK;
+}
+
+sa_dindex::~sa_dindex() {
+    DeviceGuard g(device);
+    ws.clear();
+    for (void *p : {(void *)d_text, (void *)d_sa, (void *)d_tile_key, (void *)d_tile_sa})
+        if (p) (void)hipFree(p);
+}
+
+extern "C" void sa_dfree(sa_dindex *d) { delete d; }
+
+extern "C" int64_t sa_dindex_length(const sa_dindex *d) { return d ? d->n : -1; }
+
+extern "C" int sa_default_cfg(const sa_dindex *d, sa_match_cfg *cfg) {
+    clear_error();
+    if (!d || !cfg) return fail(SA_EINVAL, "NULL argument");
+    *cfg = d->defaults;
+    return SA_OK;
+}
+
+extern "C" int match_batch_dev(const sa_dindex *dc, const uint8_t *d_reads, const int64_t *d_offs, int64_t nreads,
+                               sa_hit *d_out, void *hip_stream, const sa_match_cfg *cfg) {
+    clear_error();
+    if (!dc || !d_offs || (nreads > 0 && (!d_reads || !d_out))) return fail(SA_EINVAL, "NULL argument");
+    if (nreads < 0 || nreads > INT32_MAX) return fail(SA_EINVAL, "nreads out of range");
+    if (nreads == 0) return SA_OK;
+    sa_dindex *d = const_cast<sa_dindex *>(dc);
+    const sa_match_cfg c = resolve_cfg(d, cfg);
+    int rc = check_cfg(d, c);
+    if (rc) return rc;
+    DeviceGuard g(d->device);
+    if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Workspace *ws = workspace_for(d, s);
+    std::lock_guard<std::mutex> lk(ws->mu);
+    return enqueue_batch(d, ws, d_reads, d_offs, nullptr, nreads, d_out, s, c);
+}
+
+extern "C" int match_batch(const sa_dindex *dc, const char *reads, const int64_t *offs, int64_t nreads,
+                           sa_hit *out, void *hip_stream, const sa_match_cfg *cfg) {
+    clear_error();
+    if (!dc || !offs || (nreads > 0 && (!reads || !out))) return fail(SA_EINVAL, "NULL argument");
+    if (nreads < 0 || nreads > INT32_MAX) return fail(SA_EINVAL, "nreads out of range");
+    if (nreads == 0) return SA_OK;
+    if (offs[0] < 0) return fail(SA_EINVAL, "negative offset");
+    for (int64_t i = 0; i < nreads; i++) {
+        const int64_t m = offs[i + 1] - offs[i];
+        if (m < 0) return fail(SA_EINVAL, "offsets decrease at read " + std::to_string(i));
+        if (m > SA_MAX_READ) return fail(SA_ETOOBIG, "read " + std::to_string(i) + " is longer than SA_MAX_READ");
+    }
+    sa_dindex *d = const_cast<sa_dindex *>(dc);
+    const sa_match_cfg c = resolve_cfg(d, cfg);
+    int rc = check_cfg(d, c);
+    if (rc) return rc;
+    DeviceGuard g(d->device);
+    if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Workspace *ws = workspace_for(d, s);
+    std::lock_guard<std::mutex> lk(ws->mu);
+    const int64_t base = offs[0], nbytes = offs[nreads] - offs[0];
+    if ((rc = ws->reserve_staging(nreads, nbytes))) return rc;
+    std::memcpy(ws->h_reads, reads + base, (size_t)nbytes);
+    for (int64_t i = 0; i <= nreads; i++) ws->h_offs[i] = offs[i] - base;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ws->d_reads, ws->h_reads, (size_t)nbytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(ws->d_offs, ws->h_offs, sizeof(int64_t) * (size_t)(nreads + 1), hipMemcpyHostToDevice,
+                            s)) != hipSuccess)
+        return hip_fail(e, "batch upload");
+    if ((rc = enqueue_batch(d, ws, ws->d_reads, ws->d_offs, nullptr, nreads, ws->d_out, s, c))) return rc;
+    if ((e = hipMemcpyAsync(ws->h_out, ws->d_out, sizeof(sa_hit) * (size_t)nreads, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "batch download");
+    std::memcpy(out, ws->h_out, sizeof(sa_hit) * (size_t)nreads);
+    return SA_OK;
+}
+
+static Workspace *existing_workspace(const sa_dindex *dc, void *stream) {
+    sa_dindex *d = const_cast<sa_dindex *>(dc);
+    std::lock_guard<std::mutex> g(d->mu);
+    auto it = d->ws.find(stream);
+    return it == d->ws.end() ? nullptr : it->second.get();
+}
+
+extern "C" int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]) {
+    clear_error();
+    if (!d || !ms) return fail(SA_EINVAL, "NULL argument");
+    DeviceGuard g(d->device);
+    Workspace *ws = existing_workspace(d, hip_stream);
+    if (!ws) return fail(SA_EINVAL, "no batch on this stream");
+    std::lock_guard<std::mutex> lk(ws->mu);
+    if (!ws->profiled) return fail(SA_EINVAL, "the last batch on this stream was not profiled");
+    hipError_t e = hipEventSynchronize(ws->ev[3]);
+    if (e != hipSuccess) return hip_fail(e, "event wait");
+    float t[3] = {0, 0, 0}, all = 0;
+    for (int i = 0; i < 3; i++)
+        if ((e = hipEventElapsedTime(&t[i], ws->ev[i], ws->ev[i + 1])) != hipSuccess) return hip_fail(e, "event time");
+    if ((e = hipEventElapsedTime(&all, ws->ev[0], ws->ev[3])) != hipSuccess) return hip_fail(e, "event time");
+    for (int i = 0; i < 3; i++) ms[i] = t[i];
+    ms[3] = all;
+    return SA_OK;
+}
+
+extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[5]) {
+    clear_error();
+    if (!d || !c) return fail(SA_EINVAL, "NULL argument");
+    DeviceGuard g(d->device);
+    Workspace *ws = existing_workspace(d, hip_stream);
+    if (!ws) return fail(SA_EINVAL, "no batch on this stream");
+    std::lock_guard<std::mutex> lk(ws->mu);
+    if (!ws->counted) return fail(SA_EINVAL, "the last batch on this stream was not counted");
+    unsigned long long h[8];
+    hipError_t e = hipMemcpyAsync(h, ws->b.stats, sizeof h, hipMemcpyDeviceToHost, static_cast<hipStream_t>(hip_stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "counter download");
+    for (int i = 0; i < 5; i++) c[i] = (int64_t)h[i];
+    return SA_OK;
+}

@@ -1,0 +1,72 @@
+// Device-side state shared by device.hip, tune.hip and server.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace samatch {
+
+int hip_fail(hipError_t e, const char *what);
+
+// Makes `dev` current for the scope and restores the caller's device.
+struct DeviceGuard {
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+    int prev = -1;
+    bool ok = true;
+};
+
+// Scratch of one (index, stream): device buffers of the pipeline plus pinned
+// and device staging for host batches.  Grows on demand, never shrinks.
+struct Workspace {
+    ~Workspace();
+    int reserve(int64_t nreads);
+    int reserve_staging(int64_t nreads, int64_t nbytes);
+
+    std::mutex mu;
+    int64_t cap = 0;
+    BatchBuffers b{};
+    // stage events of the last profiled batch, and whether counts are held
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool profiled = false, counted = false;
+    // host batches
+    int64_t stage_cap = 0, bytes_cap = 0;
+    char *h_reads = nullptr;
+    int64_t *h_offs = nullptr;
+    sa_hit *h_out = nullptr;
+    uint8_t *d_reads = nullptr;
+    int64_t *d_offs = nullptr;
+    sa_hit *d_out = nullptr;
+};
+
+Workspace *workspace_for(sa_dindex *d, hipStream_t s);
+BucketTable bucket_table(const sa_match_cfg &c);
+int check_cfg(const sa_dindex *d, const sa_match_cfg &c);
+sa_match_cfg resolve_cfg(const sa_dindex *d, const sa_match_cfg *cfg);
+int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t *d_offs, const int64_t *d_ends,
+                  int64_t nreads, sa_hit *d_out, hipStream_t s, const sa_match_cfg &c);
+
+}  // namespace samatch
+
+struct sa_dindex {
+    ~sa_dindex();
+    int device = 0;
+    int64_t n = 0;
+    int cu_count = 0;
+    char arch[64] = {0};
+    uint64_t *d_text = nullptr;
+    int32_t *d_sa = nullptr;
+    uint64_t *d_tile_key = nullptr;
+    int32_t *d_tile_sa = nullptr;
+    int tile_levels = 0;  // levels stored (the kernel may use fewer)
+    samatch::DevIndex view{};
+    sa_match_cfg defaults{};
+    std::mutex mu;
+    std::map<void *, std::unique_ptr<samatch::Workspace>> ws;
+};

@@ -1,0 +1,68 @@
+// Host-side launchers of the device kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace samatch {
+
+constexpr int kWMax = 10;                 // packed words per read slot (SA_MAX_READ / 32)
+constexpr int kMaxTileLevels = 13;        // 8191 nodes x 12 B = 96 KiB of LDS
+constexpr int kSortBlock = 256;           // radix sort: threads per workgroup
+constexpr int kSortItems = 16;            // keys per thread per pass
+constexpr int kSortTile = kSortBlock * kSortItems;
+
+// Device view of a resident index, passed to kernels by value.
+struct DevIndex {
+    const uint64_t *text;      // packed text, 2 bits per base, zero padded
+    const int32_t *sa;         // suffix array, n entries
+    const uint64_t *tile_key;  // first 32 bases of the pivot suffix of each tree node
+    const int32_t *tile_sa;    // text position of each tree node's pivot suffix
+    int32_t n;
+};
+
+struct BucketTable {
+    int count;     // 1..8
+    int edge[8];   // bucket b: m <= edge[b]
+};
+
+// Scratch buffers of one batch (device pointers).
+struct BatchBuffers {
+    uint64_t *qw;        // nreads * kWMax packed words
+    int32_t *qlen;       // read length, -1 for a read that is not searched
+    int32_t *qmv;        // length of the ACGT prefix
+    uint32_t *key[2];    // sort keys (ping-pong)
+    uint32_t *val[2];    // read ids (ping-pong)
+    uint32_t *hist;      // 256 * sort blocks
+    uint32_t *digit_total;  // 256
+    unsigned *counter;   // work counter of the persistent kernel
+    unsigned long long *stats;  // 8 counters of the instrumented search (zeroed by pack)
+};
+
+hipError_t launch_build_tile(const uint64_t *text, const int32_t *sa, int32_t n, int levels,
+                             uint64_t *key, int32_t *tsa, hipStream_t s);
+
+// Read i is reads[offs[i] .. offs[i+1]), or reads[offs[i] .. ends[i]) when
+// ends is not NULL.
+hipError_t launch_pack(const uint8_t *reads, const int64_t *offs, const int64_t *ends, int64_t nreads,
+                       const BatchBuffers &b, const BucketTable &bt, hipStream_t s);
+
+// LSD radix sort of (key, val) pairs on bits [0, bits); returns in *which the
+// ping-pong slot that holds the result.
+hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *which, hipStream_t s);
+
+// count = true runs the instrumented variant that fills b.stats.
+hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int block, int grid,
+                               const BatchBuffers &b, const uint32_t *order, int64_t nreads,
+                               void *out, bool count, hipStream_t s);
+
+hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_t nreads,
+                               void *out, bool count, hipStream_t s);
+
+// Dynamic LDS bytes of the tuned kernel for a tile depth.
+inline size_t tile_lds_bytes(int levels) {
+    const size_t nodes = ((size_t)1 << levels) - 1;
+    return nodes * (sizeof(uint64_t) + sizeof(int32_t));
+}
+
+}  // namespace samatch

@@ -1,0 +1,656 @@
+// Device kernels for suffix-array read matching on gfx950 (wave64).
+//
+// Text layout: 2 bits per base, a=0 c=1 g=2 t=3, base i at bits
+// [63-2(i%32)-1, 63-2(i%32)] of word i/32, so comparing two aligned 32-base
+// words as unsigned integers compares them lexicographically, and the first
+// differing base of two words is clz(x ^ y) / 2.
+//
+// Search semantics (Section IV, Algorithm 1): with open bounds L = -1 and
+// R = n, the LB search moves R to the pivot when the query is not greater
+// than the pivot suffix (a prefix match counts as not greater) and ends with
+// LB = R; the RB search moves R only when the query is strictly smaller and
+// ends with RB = L, i.e. RB + 1 = R.  A suffix that runs out while matching
+// is smaller than the query.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace samatch {
+namespace {
+
+constexpr uint32_t kHitExact = 1u;
+constexpr uint32_t kHitTooLong = 2u;
+constexpr int kMaxRead = kWMax * 32;
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int min_i(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int max_i(int a, int b) { return a > b ? a : b; }
+
+// Probe accounting.  The timed kernels use NoCount (compiles to nothing);
+// the instrumented variant counts global probes (one SA entry each), the
+// 64-bit text words each probe compares, and probes answered in LDS.
+struct NoCount {
+    __device__ __forceinline__ void global_probe() {}
+    __device__ __forceinline__ void tile_probe() {}
+    __device__ __forceinline__ void text_words(uint32_t, uint32_t) {}
+};
+struct Count {
+    uint32_t global = 0, words = 0, tile = 0;
+    __device__ __forceinline__ void global_probe() { ++global; }
+    __device__ __forceinline__ void tile_probe() { ++tile; }
+    // bases [first, end) of the text were compared
+    __device__ __forceinline__ void text_words(uint32_t first, uint32_t end) {
+        if (end > first) words += ((end - 1) >> 5) - (first >> 5) + 1;
+    }
+};
+
+// 32 bases of the text starting at base b (bases past the end read as 0; the
+// caller never trusts them).  Two neighbouring words joined by a funnel
+// shift; the shift by (63 - sh) after a shift by 1 is a shift by 64 - sh
+// that also works for sh == 0.
+__device__ __forceinline__ uint64_t text_word(const uint64_t *__restrict__ text, uint32_t b) {
+    const uint32_t wi = b >> 5;
+    const uint32_t sh = (b & 31u) << 1;
+    const uint64_t lo = text[wi];
+    const uint64_t hi = text[wi + 1];
+    return (lo << sh) | ((hi >> 1) >> (63u - sh));
+}
+
+// Compare the query P[0..plen) with the suffix at text position p, skipping
+// the first 32*k0 bases (known to match).  Returns -1 when P sorts before
+// the suffix, 0 when P[0..plen) is a prefix of it, +1 when P sorts after it
+// (including when the suffix ends first); lcp gets the exact common-prefix
+// length, capped at min(plen, n - p).  The word loop is unrolled over all W
+// words and predicated, so the query stays in registers (a run-time index
+// into q would move it to scratch memory).
+template <int W, class Cnt>
+__device__ __forceinline__ int compare_from(const uint64_t *__restrict__ text, int32_t n,
+                                            const uint64_t (&q)[W], int plen, int32_t p, int k0,
+                                            int &lcp, Cnt &cnt) {
+    const int lim = min_i(plen, n - p);
+    int res = lim;
+    int sign = (lim == plen) ? 0 : 1;
+    bool done = false;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        if (!done && k >= k0 && (k << 5) < lim) {
+            const uint64_t t = text_word(text, (uint32_t)p + ((uint32_t)k << 5));
+            const uint64_t x = q[k] ^ t;
+            if (x) {
+                const int mm = (k << 5) + (int)(__clzll((long long)x) >> 1);
+                if (mm < lim) {
+                    res = mm;
+                    sign = q[k] > t ? 1 : -1;
+                }
+                done = true;
+            }
+        }
+    }
+    lcp = res;
+    cnt.text_words((uint32_t)p + ((uint32_t)k0 << 5), (uint32_t)p + (uint32_t)min_i(lim, res + 1));
+    return sign;
+}
+
+__device__ __forceinline__ int midpoint(int L, int R) {
+    return L + (int)((uint32_t)(R - L) >> 1);
+}
+
+// Binary search over rows (L, R] with known common-prefix lengths at the
+// bounds (lcpL, lcpR, 0 for the open ends).  Every row strictly between
+// them shares min(lcpL, lcpR) leading bases with the query, so each probe
+// starts comparing at that word.  UPPER = false: first row whose suffix is
+// not below P[0..plen) (LB); UPPER = true: first row strictly above every
+// extension of P[0..plen) (RB + 1).
+template <int W, bool UPPER, class Cnt>
+__device__ __forceinline__ int bounded_search(const DevIndex &ix, const uint64_t (&q)[W], int plen, int L, int R,
+                              int lcpL, int lcpR, Cnt &cnt) {
+    while (R > L + 1) {
+        const int piv = midpoint(L, R);
+        const int32_t p = ix.sa[piv];
+        int lcp;
+        cnt.global_probe();
+        const int sign = compare_from<W>(ix.text, ix.n, q, plen, p, min_i(lcpL, lcpR) >> 5, lcp, cnt);
+        const bool go_left = UPPER ? (sign < 0) : (sign <= 0);
+        if (go_left) { R = piv; lcpR = lcp; }
+        else { L = piv; lcpL = lcp; }
+    }
+    return R;
+}
+
+// State at the end of the LB search: adjacent rows L, R = L + 1 around the
+// insertion point of P[0..plen), their common-prefix lengths with P, and for
+// each side the last bound before its common-prefix length reached its final
+// value (Llt / Rlt) with that bound's length.  Common-prefix lengths only
+// grow towards the insertion point, so every row at or beyond Llt (Rlt) on
+// that side shares fewer than lcpL (lcpR) bases with P.
+struct LbState {
+    int L, R, lcpL, lcpR, Llt, lcpLlt, Rlt, lcpRlt;
+};
+
+__device__ __forceinline__ void lb_update(LbState &st, int sign, int piv, int lcp) {
+    if (sign <= 0) {
+        if (lcp > st.lcpR) { st.Rlt = st.R; st.lcpRlt = st.lcpR; }
+        st.R = piv; st.lcpR = lcp;
+    } else {
+        if (lcp > st.lcpL) { st.Llt = st.L; st.lcpLlt = st.lcpL; }
+        st.L = piv; st.lcpL = lcp;
+    }
+}
+
+// Full LB search of P[0..plen).  The first `levels` probes of every search
+// from (-1, n) visit nodes of one fixed implicit binary tree; their pivot
+// suffixes (first 32 bases and text position) sit in LDS.  A probe that
+// ties on all 32 staged bases continues in global memory at word 1.
+template <int W, class Cnt>
+__device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
+                          const uint64_t (&q)[W], int plen, LbState &st, Cnt &cnt) {
+    st.L = -1; st.R = ix.n; st.lcpL = 0; st.lcpR = 0;
+    st.Llt = -1; st.lcpLlt = 0; st.Rlt = ix.n; st.lcpRlt = 0;
+    int node = 0;
+    for (int d = 0; d < levels && st.R > st.L + 1; ++d) {
+        const uint64_t key = s_key[node];
+        const int32_t p = s_sa[node];
+        const int lim = min_i(plen, ix.n - p);
+        const uint64_t x = q[0] ^ key;
+        const int mm = (int)(__clzll((long long)x) >> 1);
+        int lcp, sign;
+        cnt.tile_probe();
+        if (x != 0 && mm < lim) { lcp = mm; sign = q[0] > key ? 1 : -1; }
+        else if (lim <= 32) { lcp = lim; sign = (lim == plen) ? 0 : 1; }
+        else sign = compare_from<W>(ix.text, ix.n, q, plen, p, 1, lcp, cnt);
+        const int piv = midpoint(st.L, st.R);
+        lb_update(st, sign, piv, lcp);
+        node = 2 * node + (sign <= 0 ? 1 : 2);
+    }
+    while (st.R > st.L + 1) {
+        const int piv = midpoint(st.L, st.R);
+        const int32_t p = ix.sa[piv];
+        int lcp;
+        cnt.global_probe();
+        const int sign = compare_from<W>(ix.text, ix.n, q, plen, p, min_i(st.lcpL, st.lcpR) >> 5, lcp, cnt);
+        lb_update(st, sign, piv, lcp);
+    }
+}
+
+// One read: LB search of its ACGT prefix; exact reads finish with an RB
+// search confined to (LB, Rlt]; other reads take the longest matched prefix
+// l = max(lcpL, lcpR) from the two rows around the insertion point and find
+// the interval of P[0..l) inside the bounds the LB search already bracketed.
+template <int W, class Cnt>
+__device__ __forceinline__ int4 match_read(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
+                           const uint64_t (&q)[W], int m, int mv, Cnt &cnt) {
+    LbState st;
+    lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, cnt);
+    if (mv == m && st.lcpR == m) {
+        const int hi = bounded_search<W, true>(ix, q, m, st.R, st.Rlt, m, st.lcpRlt, cnt);
+        return make_int4(st.R, hi, m, (int)kHitExact);
+    }
+    const int l = max_i(st.lcpL, st.lcpR);
+    if (l == 0) return make_int4(0, ix.n, 0, 0);
+    const int lo = (st.lcpL == l) ? bounded_search<W, false>(ix, q, l, st.Llt, st.L, st.lcpLlt, l, cnt) : st.R;
+    const int hi = (st.lcpR == l) ? bounded_search<W, true>(ix, q, l, st.R, st.Rlt, l, st.lcpRlt, cnt) : st.R;
+    return make_int4(lo, hi, l, 0);
+}
+
+template <int W>
+__device__ __forceinline__ void load_query(const uint64_t *__restrict__ qw, int rid, uint64_t (&q)[W]) {
+    const uint64_t *src = qw + (size_t)rid * kWMax;
+#pragma unroll
+    for (int k = 0; k < W; ++k) q[k] = src[k];
+}
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// ------------------------------------------------------------------ tile
+
+__global__ void build_tile_kernel(const uint64_t *__restrict__ text, const int32_t *__restrict__ sa,
+                                  int32_t n, int levels, uint64_t *key, int32_t *tsa) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nodes = (1 << levels) - 1;
+    if (j >= nodes) return;
+    // node j is reached by the bits of j+1 after its leading one: 0 = the
+    // query was not above the pivot (R = pivot), 1 = it was (L = pivot)
+    const int depth = 31 - __clz(j + 1);
+    const int path = (j + 1) - (1 << depth);
+    int L = -1, R = n;
+    bool live = true;
+    for (int i = depth - 1; i >= 0; --i) {
+        if (R <= L + 1) { live = false; break; }
+        const int piv = midpoint(L, R);
+        if ((path >> i) & 1) L = piv; else R = piv;
+    }
+    if (!live || R <= L + 1) {  // no search reaches this node
+        key[j] = 0;
+        tsa[j] = 0;
+        return;
+    }
+    const int32_t p = sa[midpoint(L, R)];
+    key[j] = text_word(text, (uint32_t)p);
+    tsa[j] = p;
+}
+
+// ------------------------------------------------------------------ pack
+
+// One thread per read: ASCII (either case) to 2-bit words, the length of
+// the ACGT prefix, and the sort key (length bucket, first 12 bases).  Read
+// i is reads[offs[i] .. offs[i+1]), or reads[offs[i] .. ends[i]) when an end
+// array is given (reads scattered over a larger buffer).  Bytes
+// are fetched as aligned dwords; an aligned dword that holds at least one
+// byte of the read never crosses a page, so no fetch can fault.
+__global__ void pack_kernel(const uint8_t *__restrict__ reads, const int64_t *__restrict__ offs,
+                            const int64_t *__restrict__ ends, int64_t nreads, BatchBuffers b, BucketTable bt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *b.counter = 0u;
+    if (i < 8) b.stats[i] = 0ull;
+    if (i >= nreads) return;
+    const int64_t a = offs[i], e = ends ? ends[i] : offs[i + 1];
+    const int64_t m64 = e - a;
+    uint64_t *dst = b.qw + (size_t)i * kWMax;
+    if (m64 < 0 || m64 > kMaxRead) {
+        b.qlen[i] = -1;
+        b.qmv[i] = 0;
+        dst[0] = 0;
+        b.key[0][i] = 0;
+        b.val[0][i] = (uint32_t)i;
+        return;
+    }
+    const int m = (int)m64;
+    int mv = m;
+    uint64_t word = 0;
+    int k = 0;
+    const uintptr_t start = (uintptr_t)(reads + a);
+    const uintptr_t stop = (uintptr_t)(reads + e);
+    for (uintptr_t addr = start & ~(uintptr_t)3; addr < stop; addr += 4) {
+        const uint32_t dw = *reinterpret_cast<const uint32_t *>(addr);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uintptr_t at = addr + t;
+            if (at < start || at >= stop) continue;
+            const int idx = (int)(at - start);
+            const uint32_t c = (dw >> (8 * t)) & 0xFFu;
+            const uint32_t lc = c | 0x20u;
+            const bool ok = lc == 'a' || lc == 'c' || lc == 'g' || lc == 't';
+            // a->0 c->1 g->2 t->3 for either case
+            const uint32_t code = ((c >> 1) ^ (c >> 2)) & 3u;
+            if (!ok && idx < mv) mv = idx;
+            word |= (uint64_t)(ok ? code : 0u) << (62 - 2 * (idx & 31));
+            if ((idx & 31) == 31) { dst[k++] = word; word = 0; }
+        }
+    }
+    if ((m & 31) != 0 || m == 0) dst[k] = word;
+    b.qlen[i] = m;
+    b.qmv[i] = mv;
+    int bucket = bt.count - 1;
+    for (int j = 0; j < bt.count; ++j)
+        if (m <= bt.edge[j]) { bucket = j; break; }
+    const uint64_t w0 = dst[0];
+    b.key[0][i] = ((uint32_t)bucket << 24) | (uint32_t)(w0 >> 40);
+    b.val[0][i] = (uint32_t)i;
+}
+
+// ------------------------------------------------------------------ radix sort
+
+// Per-block digit counts, digit-major: hist[d * nblocks + block].
+__global__ __launch_bounds__(kSortBlock) void sort_hist_kernel(const uint32_t *__restrict__ keys, int64_t n,
+                                                               int shift, uint32_t *hist, int nblocks) {
+    __shared__ uint32_t h[kSortBlock / 64][256];
+    const int t = threadIdx.x, wave = t >> 6;
+    for (int i = t; i < (kSortBlock / 64) * 256; i += kSortBlock) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = base + r * kSortBlock + t;
+        if (i < n) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int d = t; d < 256; d += kSortBlock) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int w = 0; w < kSortBlock / 64; ++w) s += h[w][d];
+        hist[(size_t)d * nblocks + blockIdx.x] = s;
+    }
+}
+
+// Block-wide exclusive scan of one value per thread; returns the total.
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t &excl, uint32_t *lds /* >= blockDim/64 */) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < nw; ++w) {
+        const uint32_t s = lds[w];
+        if (w < wave) before += s;
+        total += s;
+    }
+    __syncthreads();
+    excl = before + x - v;
+    return total;
+}
+
+// Totals per digit (one block per digit).
+__global__ __launch_bounds__(256) void sort_digit_total_kernel(const uint32_t *__restrict__ hist, int nblocks,
+                                                               uint32_t *digit_total) {
+    __shared__ uint32_t lds[4];
+    const int d = blockIdx.x;
+    uint32_t s = 0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += hist[(size_t)d * nblocks + b];
+    uint32_t excl;
+    const uint32_t total = block_exclusive_scan(s, excl, lds);
+    if (threadIdx.x == 0) digit_total[d] = total;
+}
+
+// Exclusive scan of hist in place: entry (d, b) becomes the output position
+// of block b's first key with digit d.  One block per digit.
+__global__ __launch_bounds__(256) void sort_scan_kernel(uint32_t *hist, int nblocks,
+                                                        const uint32_t *__restrict__ digit_total) {
+    __shared__ uint32_t lds[4];
+    __shared__ uint32_t carry;
+    const int d = blockIdx.x;
+    if (threadIdx.x == 0) {
+        uint32_t base = 0;
+        for (int e = 0; e < d; ++e) base += digit_total[e];
+        carry = base;
+    }
+    __syncthreads();
+    for (int b0 = 0; b0 < nblocks; b0 += 256) {
+        const int b = b0 + threadIdx.x;
+        const uint32_t v = b < nblocks ? hist[(size_t)d * nblocks + b] : 0u;
+        uint32_t excl;
+        const uint32_t total = block_exclusive_scan(v, excl, lds);
+        const uint32_t c = carry;
+        if (b < nblocks) hist[(size_t)d * nblocks + b] = c + excl;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + total;
+        __syncthreads();
+    }
+}
+
+// Stable scatter: keys of a block are taken in input order, 256 per round;
+// inside a wave, lanes with the same digit are found with eight ballots
+// (one per digit bit) and ranked by their lane order; waves are ordered by
+// per-round digit counts in LDS.
+__global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(const uint32_t *__restrict__ kin,
+                                                                  const uint32_t *__restrict__ vin,
+                                                                  uint32_t *__restrict__ kout,
+                                                                  uint32_t *__restrict__ vout, int64_t n,
+                                                                  int shift, const uint32_t *__restrict__ hist,
+                                                                  int nblocks) {
+    constexpr int kWaves = kSortBlock / 64;
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcount[kWaves][256];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int d = t; d < 256; d += kSortBlock) {
+        base[d] = hist[(size_t)d * nblocks + blockIdx.x];
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) wcount[w][d] = 0;
+    }
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t blk = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = blk + r * kSortBlock + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = wave_ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const uint64_t bal = wave_ballot(set);
+            peers &= set ? bal : ~bal;
+        }
+        const int rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0) wcount[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[d] + (uint32_t)rank;
+            for (int w = 0; w < wave; ++w) pos += wcount[w][d];
+            kout[pos] = key;
+            vout[pos] = vin[i];
+        }
+        __syncthreads();
+        for (int dd = t; dd < 256; dd += kSortBlock) {
+            uint32_t s = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) { s += wcount[w][dd]; wcount[w][dd] = 0; }
+            base[dd] += s;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ search
+
+template <int W, class Cnt>
+__device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa,
+                                          int levels, const BatchBuffers &b, int rid, int4 *out, Cnt &cnt) {
+    const int m = b.qlen[rid];
+    if (m < 0) {
+        out[rid] = make_int4(0, 0, 0, (int)kHitTooLong);
+        return;
+    }
+    uint64_t q[W];
+    load_query<W>(b.qw, rid, q);
+    out[rid] = match_read<W>(ix, s_key, s_sa, levels, q, m, b.qmv[rid], cnt);
+}
+
+// Sum a per-lane count over the wave and add it to a global counter.
+__device__ __forceinline__ void wave_add(unsigned long long *dst, uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
+}
+
+// Persistent kernel: each workgroup stages the top `levels` tree levels in
+// LDS once, then its waves take 64 consecutive (prefix-sorted) reads at a
+// time from a global counter until none are left.  Each chunk runs the
+// instantiation for the longest read it holds.
+template <int BLOCK, bool COUNT>
+__global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, BatchBuffers b,
+                                                             const uint32_t *__restrict__ order,
+                                                             int64_t nreads, int4 *__restrict__ out) {
+    extern __shared__ uint64_t smem[];
+    const int nodes = (1 << levels) - 1;
+    uint64_t *s_key = smem;
+    int32_t *s_sa = reinterpret_cast<int32_t *>(smem + nodes);
+    for (int i = threadIdx.x; i < nodes; i += BLOCK) {
+        s_key[i] = ix.tile_key[i];
+        s_sa[i] = ix.tile_sa[i];
+    }
+    __syncthreads();
+    using Cnt = typename std::conditional<COUNT, Count, NoCount>::type;
+    Cnt cnt;
+    uint32_t nsearched = 0, nqwords = 0;
+    const int lane = threadIdx.x & 63;
+    const int64_t nchunks = (nreads + 63) >> 6;
+    for (;;) {
+        unsigned c = 0;
+        if (lane == 0) c = atomicAdd(b.counter, 1u);
+        c = __shfl(c, 0, 64);
+        if ((int64_t)c >= nchunks) break;
+        const int64_t j = ((int64_t)c << 6) + lane;
+        const bool active = j < nreads;
+        const int rid = active ? (order ? (int)order[j] : (int)j) : 0;
+        const int m = active ? b.qlen[rid] : 0;
+        const int w = max_i(1, (m + 31) >> 5);
+        int wc = 1;
+#pragma unroll
+        for (int t = 2; t <= kWMax; ++t)
+            if (wave_ballot(active && w >= t)) wc = t;
+        if (!active) continue;
+        if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
+        switch (wc) {
+            case 1: tuned_one<1>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            case 2: tuned_one<2>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            case 3: tuned_one<3>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            case 4: tuned_one<4>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            case 5: tuned_one<5>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            case 6: tuned_one<6>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            case 7: tuned_one<7>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            case 8: tuned_one<8>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            case 9: tuned_one<9>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            default: tuned_one<10>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+        }
+    }
+    if constexpr (COUNT) {
+        wave_add(&b.stats[0], cnt.global);
+        wave_add(&b.stats[1], cnt.words);
+        wave_add(&b.stats[2], cnt.tile);
+        wave_add(&b.stats[3], nsearched);
+        wave_add(&b.stats[4], nqwords);
+    }
+}
+
+// Plain kernel, the paper's arrangement (Algorithm 1): one read per
+// thread in input order, every search over the whole range (-1, n), every
+// probe comparing from the first base, no LDS.  Exact reads take the LB and
+// RB searches; other reads add the two neighbour comparisons for l and the
+// LB / RB searches of P[0..l).
+template <bool UPPER, class Cnt>
+__device__ __forceinline__ int plain_search(const DevIndex &ix, const uint64_t (&q)[kWMax], int plen, Cnt &cnt) {
+    int L = -1, R = ix.n;
+    while (R > L + 1) {
+        const int piv = midpoint(L, R);
+        int lcp;
+        cnt.global_probe();
+        const int sign = compare_from<kWMax>(ix.text, ix.n, q, plen, ix.sa[piv], 0, lcp, cnt);
+        if (UPPER ? (sign < 0) : (sign <= 0)) R = piv; else L = piv;
+    }
+    return R;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuffers b, int64_t nreads,
+                                                          int4 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    using Cnt = typename std::conditional<COUNT, Count, NoCount>::type;
+    Cnt cnt;
+    int4 res = make_int4(0, 0, 0, (int)kHitTooLong);
+    const int m = i < nreads ? b.qlen[i] : -1;
+    if (m >= 0) {
+        const int mv = b.qmv[i];
+        uint64_t q[kWMax];
+        const uint64_t *src = b.qw + (size_t)i * kWMax;
+#pragma unroll
+        for (int k = 0; k < kWMax; ++k) q[k] = (k << 5) < m ? src[k] : 0ull;
+        const int lo = plain_search<false>(ix, q, mv, cnt);
+        int hi = lo;
+        if (mv == m) hi = plain_search<true>(ix, q, m, cnt);
+        if (mv == m && lo < hi) {
+            res = make_int4(lo, hi, m, (int)kHitExact);
+        } else {
+            int l = 0, lcp;
+            if (lo > 0) {
+                cnt.global_probe();
+                compare_from<kWMax>(ix.text, ix.n, q, mv, ix.sa[lo - 1], 0, lcp, cnt);
+                l = max_i(l, lcp);
+            }
+            if (lo < ix.n) {
+                cnt.global_probe();
+                compare_from<kWMax>(ix.text, ix.n, q, mv, ix.sa[lo], 0, lcp, cnt);
+                l = max_i(l, lcp);
+            }
+            res = make_int4(plain_search<false>(ix, q, l, cnt), plain_search<true>(ix, q, l, cnt), l,
+                            l == m ? (int)kHitExact : 0);
+        }
+    }
+    if (i < nreads) out[i] = res;
+    if constexpr (COUNT) {
+        wave_add(&b.stats[0], cnt.global);
+        wave_add(&b.stats[1], cnt.words);
+        wave_add(&b.stats[3], m >= 0 ? 1u : 0u);
+        wave_add(&b.stats[4], m >= 0 ? (uint32_t)max_i(1, (m + 31) >> 5) : 0u);
+    }
+}
+
+template <int BLOCK, bool COUNT>
+hipError_t launch_tuned_block(const DevIndex &ix, int levels, int grid, const BatchBuffers &b,
+                              const uint32_t *order, int64_t nreads, int4 *out, hipStream_t s) {
+    const size_t lds = tile_lds_bytes(levels);
+    static std::atomic<bool> attr_set{false};
+    if (!attr_set.load()) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&search_tuned_kernel<BLOCK, COUNT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)tile_lds_bytes(kMaxTileLevels));
+        if (e != hipSuccess) return e;
+        attr_set.store(true);
+    }
+    hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, b, order,
+                       nreads, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_build_tile(const uint64_t *text, const int32_t *sa, int32_t n, int levels, uint64_t *key,
+                             int32_t *tsa, hipStream_t s) {
+    const int nodes = (1 << levels) - 1;
+    hipLaunchKernelGGL(build_tile_kernel, dim3((nodes + 255) / 256), dim3(256), 0, s, text, sa, n, levels, key,
+                       tsa);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const uint8_t *reads, const int64_t *offs, const int64_t *ends, int64_t nreads,
+                       const BatchBuffers &b, const BucketTable &bt, hipStream_t s) {
+    const int64_t blocks = (nreads + 255) / 256;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, reads, offs, ends,
+                       nreads, b, bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *which, hipStream_t s) {
+    int cur = 0;
+    const int nblocks = (int)((nreads + kSortTile - 1) / kSortTile);
+    if (nreads > 1) {
+        for (int shift = 0; shift < bits; shift += 8) {
+            hipLaunchKernelGGL(sort_hist_kernel, dim3(nblocks), dim3(kSortBlock), 0, s, b.key[cur], nreads, shift,
+                               b.hist, nblocks);
+            hipLaunchKernelGGL(sort_digit_total_kernel, dim3(256), dim3(256), 0, s, b.hist, nblocks, b.digit_total);
+            hipLaunchKernelGGL(sort_scan_kernel, dim3(256), dim3(256), 0, s, b.hist, nblocks, b.digit_total);
+            hipLaunchKernelGGL(sort_scatter_kernel, dim3(nblocks), dim3(kSortBlock), 0, s, b.key[cur], b.val[cur],
+                               b.key[cur ^ 1], b.val[cur ^ 1], nreads, shift, b.hist, nblocks);
+            cur ^= 1;
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    *which = cur;
+    return hipSuccess;
+}
+
+hipError_t launch_search_tuned(const DevIndex &ix, int levels, int block, int grid, const BatchBuffers &b,
+                               const uint32_t *order, int64_t nreads, void *out, bool count, hipStream_t s) {
+    int4 *o = static_cast<int4 *>(out);
+    if (count)  // counts do not depend on the workgroup shape
+        return launch_tuned_block<256, true>(ix, levels, grid * (block / 256), b, order, nreads, o, s);
+    switch (block) {
+        case 256: return launch_tuned_block<256, false>(ix, levels, grid, b, order, nreads, o, s);
+        case 512: return launch_tuned_block<512, false>(ix, levels, grid, b, order, nreads, o, s);
+        case 1024: return launch_tuned_block<1024, false>(ix, levels, grid, b, order, nreads, o, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_t nreads, void *out, bool count,
+                               hipStream_t s) {
+    const int64_t blocks = (nreads + 255) / 256;
+    const dim3 grid((unsigned)(blocks > 0 ? blocks : 1));
+    if (count)
+        hipLaunchKernelGGL(search_plain_kernel<true>, grid, dim3(256), 0, s, ix, b, nreads, static_cast<int4 *>(out));
+    else
+        hipLaunchKernelGGL(search_plain_kernel<false>, grid, dim3(256), 0, s, ix, b, nreads, static_cast<int4 *>(out));
+    return hipGetLastError();
+}
+
+}  // namespace samatch

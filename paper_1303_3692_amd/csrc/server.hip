@@ -1,0 +1,557 @@
+// Request loop over resident indexes: continuous batching of reads from
+// many requests, admission by a device-memory budget, several streams in
+// flight, per-request scatter of results and timestamps.
+//
+// Life of a request: submit copies its reads into host memory and queues it.
+// The loop admits queued requests in arrival order while the device budget
+// (free HBM minus the reserve, fixed when the server starts) has room for
+// its reads; admission copies the reads into a device arena.  Each free
+// stream slot then takes up to max_batch_reads unscheduled reads of one
+// reference, from the admitted requests of that reference in admission
+// order, and runs one pipeline over them (the reads stay where they are in
+// the arena; the batch passes each read's start and end).  When a slot's
+// batch finishes, its results are copied into the owners' output arrays;
+// a request whose reads are all done is finished and its arena space
+// returned.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "device_state.h"
+
+using namespace samatch;
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// First-fit allocator over [0, capacity) with coalescing, 256-byte grain.
+class Arena {
+  public:
+    void init(int64_t cap) {
+        cap_ = cap;
+        free_.clear();
+        if (cap > 0) free_[0] = cap;
+    }
+    int64_t capacity() const { return cap_; }
+    // returns the offset or -1
+    int64_t alloc(int64_t bytes) {
+        bytes = (std::max<int64_t>(bytes, 1) + 255) & ~int64_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const int64_t off = it->first, left = it->second - bytes;
+            free_.erase(it);
+            if (left) free_[off + bytes] = left;
+            used_ += bytes;
+            return off;
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes) {
+        bytes = (std::max<int64_t>(bytes, 1) + 255) & ~int64_t(255);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t used() const { return used_; }
+
+  private:
+    int64_t cap_ = 0, used_ = 0;
+    std::map<int64_t, int64_t> free_;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    int ref = 0;
+    int64_t nreads = 0;
+    std::vector<char> reads;      // host copy
+    std::vector<int64_t> offs;    // nreads + 1, rebased to 0
+    sa_hit *out = nullptr;        // caller's
+    int64_t arena_off = -1, arena_bytes = 0;
+    int64_t next = 0;             // next unscheduled read
+    int64_t done = 0;             // reads with results
+    int inflight_batches = 0;
+    int status = SA_PENDING;
+    int fail_code = SA_OK;
+    bool admitted = false, failed = false;
+    int64_t t_submit = 0, t_admit = 0, t_done = 0;
+    hipEvent_t uploaded = nullptr;
+};
+
+struct Piece {
+    Request *req;
+    int64_t first, count, pos;  // reads [first, first+count) of req at batch rows [pos, pos+count)
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    int ref = 0;
+    int64_t nreads = 0;
+    std::vector<Piece> pieces;
+    int64_t *h_se = nullptr;  // starts then ends (pinned)
+    sa_hit *h_out = nullptr;  // pinned
+    int64_t *d_se = nullptr;
+    sa_hit *d_out = nullptr;
+    int error = SA_OK;
+};
+
+}  // namespace
+
+struct sa_server {
+    std::vector<sa_dindex *> refs;
+    sa_server_opts o{};
+    int device = 0;
+    Arena arena;
+    uint8_t *d_arena = nullptr;
+    hipStream_t upload_stream = nullptr;
+    std::vector<Slot> slots;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queued;                  // not admitted yet, arrival order
+    std::vector<std::deque<Request *>> active;     // per reference, admitted with reads left to schedule
+    std::map<uint64_t, std::unique_ptr<Request>> all;
+    uint64_t next_ticket = 1;
+    int64_t inflight_reads = 0;
+    int64_t batches_run = 0;
+    int next_ref = 0;
+    bool stop = false;
+    std::thread loop;
+
+    void run();
+    bool admit_locked();
+    bool launch_locked(Slot &sl);
+    bool reap_locked(Slot &sl, bool wait);
+    void finish_locked(Request *r, int status);
+    void echo_execute(Slot &sl);
+};
+
+void sa_server::finish_locked(Request *r, int status) {
+    if (r->status != SA_PENDING) return;
+    r->status = status;
+    r->t_done = now_ns();
+    if (r->arena_off >= 0) {
+        arena.release(r->arena_off, r->arena_bytes);
+        r->arena_off = -1;
+    }
+    if (r->uploaded) {
+        (void)hipEventDestroy(r->uploaded);
+        r->uploaded = nullptr;
+    }
+    if (r->admitted) inflight_reads -= r->nreads;
+    std::vector<char>().swap(r->reads);
+    std::vector<int64_t>().swap(r->offs);
+    cv_done.notify_all();
+}
+
+// Admit queued requests in arrival order while the budget allows.
+bool sa_server::admit_locked() {
+    bool any = false;
+    while (!queued.empty()) {
+        Request *r = queued.front();
+        const int64_t bytes = std::max<int64_t>(1, r->offs[(size_t)r->nreads]);
+        if (bytes > arena.capacity() || r->nreads > o.max_inflight_reads) {
+            queued.pop_front();
+            finish_locked(r, SA_ENOSPC);
+            any = true;
+            continue;
+        }
+        if (inflight_reads > 0 && inflight_reads + r->nreads > o.max_inflight_reads) break;
+        const int64_t off = arena.alloc(bytes);
+        if (off < 0) break;
+        queued.pop_front();
+        r->arena_off = off;
+        r->arena_bytes = bytes;
+        r->admitted = true;
+        r->t_admit = now_ns();
+        inflight_reads += r->nreads;
+        if (!o.test_echo && r->nreads > 0) {
+            hipError_t e = hipMemcpyAsync(d_arena + off, r->reads.data(), (size_t)r->offs[(size_t)r->nreads],
+                                          hipMemcpyHostToDevice, upload_stream);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(r->uploaded, upload_stream);
+            if (e != hipSuccess) {
+                finish_locked(r, SA_EDEVICE);
+                any = true;
+                continue;
+            }
+        }
+        if (r->nreads == 0) finish_locked(r, SA_OK);
+        else active[(size_t)r->ref].push_back(r);
+        any = true;
+    }
+    return any;
+}
+
+// Form a batch for a free slot from one reference's admitted requests.
+bool sa_server::launch_locked(Slot &sl) {
+    const int nref = (int)refs.size();
+    int ref = -1;
+    for (int k = 0; k < nref; k++) {
+        const int cand = (next_ref + k) % nref;
+        if (!active[(size_t)cand].empty()) { ref = cand; break; }
+    }
+    if (ref < 0) return false;
+    next_ref = (ref + 1) % nref;
+    auto &q = active[(size_t)ref];
+    sl.pieces.clear();
+    sl.ref = ref;
+    sl.error = SA_OK;
+    int64_t rows = 0;
+    while (!q.empty() && rows < o.max_batch_reads) {
+        Request *r = q.front();
+        const int64_t take = std::min(r->nreads - r->next, o.max_batch_reads - rows);
+        sl.pieces.push_back(Piece{r, r->next, take, rows});
+        r->next += take;
+        r->inflight_batches++;
+        rows += take;
+        if (r->next == r->nreads) q.pop_front();
+    }
+    sl.nreads = rows;
+    sl.busy = true;
+    batches_run++;
+    const bool inject = o.test_fail_batch > 0 && batches_run == o.test_fail_batch;
+    if (o.test_echo) {
+        sl.error = inject ? SA_EDEVICE : SA_OK;
+        return true;
+    }
+    if (inject) {
+        sl.error = SA_EDEVICE;
+        return true;
+    }
+    // starts and ends of every read, relative to the arena
+    int64_t *st = sl.h_se, *en = sl.h_se + o.max_batch_reads;
+    for (const Piece &p : sl.pieces) {
+        const int64_t base = p.req->arena_off;
+        for (int64_t k = 0; k < p.count; k++) {
+            st[p.pos + k] = base + p.req->offs[(size_t)(p.first + k)];
+            en[p.pos + k] = base + p.req->offs[(size_t)(p.first + k + 1)];
+        }
+    }
+    hipError_t e = hipSuccess;
+    for (const Piece &p : sl.pieces)
+        if (e == hipSuccess && p.req->uploaded) e = hipStreamWaitEvent(sl.stream, p.req->uploaded, 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sl.d_se, st, sizeof(int64_t) * (size_t)rows, hipMemcpyHostToDevice, sl.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sl.d_se + o.max_batch_reads, en, sizeof(int64_t) * (size_t)rows, hipMemcpyHostToDevice,
+                           sl.stream);
+    if (e != hipSuccess) {
+        sl.error = hip_fail(e, "batch upload");
+        (void)hipStreamSynchronize(sl.stream);  // the staging buffers are reused by the next batch
+        return true;
+    }
+    sa_dindex *d = refs[(size_t)ref];
+    Workspace *ws = workspace_for(d, sl.stream);
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(ws->mu);
+        rc = enqueue_batch(d, ws, d_arena, sl.d_se, sl.d_se + o.max_batch_reads, rows, sl.d_out, sl.stream,
+                           resolve_cfg(d, nullptr));
+    }
+    if (rc) {
+        sl.error = rc;
+        (void)hipStreamSynchronize(sl.stream);
+        return true;
+    }
+    e = hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(sa_hit) * (size_t)rows, hipMemcpyDeviceToHost, sl.stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+    if (e != hipSuccess) {
+        sl.error = hip_fail(e, "batch download");
+        (void)hipStreamSynchronize(sl.stream);
+    }
+    return true;
+}
+
+// Deterministic stand-in results for host-only tests: lo = request-local
+// read index, hi = lo + ticket, len = read length, flags = reference.
+void sa_server::echo_execute(Slot &sl) {
+    for (const Piece &p : sl.pieces)
+        for (int64_t k = 0; k < p.count; k++) {
+            const int64_t i = p.first + k;
+            sa_hit h;
+            h.lo = (int32_t)i;
+            h.hi = (int32_t)(i + (int64_t)p.req->ticket);
+            h.len = (int32_t)(p.req->offs[(size_t)i + 1] - p.req->offs[(size_t)i]);
+            h.flags = (uint32_t)sl.ref;
+            sl.h_out[p.pos + k] = h;
+        }
+}
+
+// Collect a finished batch: scatter results, finish complete requests.
+bool sa_server::reap_locked(Slot &sl, bool wait) {
+    if (!sl.busy) return false;
+    if (!o.test_echo && sl.error == SA_OK) {
+        hipError_t e = wait ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
+        if (e == hipErrorNotReady) return false;
+        if (e != hipSuccess) sl.error = hip_fail(e, "batch execution");
+    } else if (o.test_echo && sl.error == SA_OK) {
+        echo_execute(sl);
+    }
+    for (const Piece &p : sl.pieces) {
+        Request *r = p.req;
+        r->inflight_batches--;
+        if (sl.error != SA_OK) {
+            if (!r->failed) { r->failed = true; r->fail_code = sl.error; }
+        } else if (!r->failed) {
+            std::memcpy(r->out + p.first, sl.h_out + p.pos, sizeof(sa_hit) * (size_t)p.count);
+            r->done += p.count;
+        }
+        if (r->inflight_batches == 0) {
+            if (r->failed) {
+                // drop the rest of a failed request from scheduling
+                auto &q = active[(size_t)r->ref];
+                q.erase(std::remove(q.begin(), q.end(), r), q.end());
+                finish_locked(r, r->fail_code);
+            } else if (r->done == r->nreads) {
+                finish_locked(r, SA_OK);
+            }
+        }
+    }
+    sl.busy = false;
+    sl.pieces.clear();
+    return true;
+}
+
+void sa_server::run() {
+    if (!o.test_echo) (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        bool progress = false;
+        for (Slot &sl : slots) progress |= reap_locked(sl, false);
+        if (!stop) {
+            progress |= admit_locked();
+            for (Slot &sl : slots)
+                if (!sl.busy) progress |= launch_locked(sl);
+        }
+        bool busy = false;
+        for (Slot &sl : slots) busy |= sl.busy;
+        if (stop && !busy) break;
+        if (progress) continue;
+        if (busy) {
+            // batches in flight: poll their events without holding the lock long
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        } else {
+            cv_work.wait_for(lk, std::chrono::milliseconds(5));
+        }
+    }
+}
+
+extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const sa_server_opts *opts,
+                                sa_server **out) {
+    clear_error();
+    if (!refs || nrefs < 1 || !out) return fail(SA_EINVAL, "bad argument");
+    *out = nullptr;
+    std::unique_ptr<sa_server> s(new sa_server);
+    sa_server_opts o{};
+    o.hbm_reserve_bytes = (int64_t)1 << 30;
+    o.max_batch_reads = 1 << 20;
+    o.max_inflight_reads = (int64_t)8 << 20;
+    o.nstreams = 2;
+    o.test_fake_free_hbm = -1;
+    if (opts) {
+        if (opts->hbm_reserve_bytes > 0) o.hbm_reserve_bytes = opts->hbm_reserve_bytes;
+        if (opts->max_batch_reads > 0) o.max_batch_reads = opts->max_batch_reads;
+        if (opts->max_inflight_reads > 0) o.max_inflight_reads = opts->max_inflight_reads;
+        if (opts->nstreams > 0) o.nstreams = opts->nstreams;
+        o.test_fake_free_hbm = opts->test_fake_free_hbm;
+        o.test_echo = opts->test_echo;
+        o.test_fail_batch = opts->test_fail_batch;
+    }
+    if (o.nstreams > 8) return fail(SA_EINVAL, "nstreams must be at most 8");
+    if (o.max_batch_reads > INT32_MAX) return fail(SA_EINVAL, "max_batch_reads too large");
+    for (int i = 0; i < nrefs; i++) {
+        if (!o.test_echo && !refs[i]) return fail(SA_EINVAL, "NULL index");
+        s->refs.push_back(const_cast<sa_dindex *>(refs[i]));
+    }
+    s->o = o;
+    s->active.resize((size_t)nrefs);
+    s->slots.resize((size_t)o.nstreams);
+    if (o.test_echo) {
+        s->arena.init(o.test_fake_free_hbm >= 0 ? std::max<int64_t>(0, o.test_fake_free_hbm - o.hbm_reserve_bytes)
+                                                : ((int64_t)1 << 30));
+        for (Slot &sl : s->slots) sl.h_out = new sa_hit[(size_t)o.max_batch_reads];
+    } else {
+        s->device = s->refs[0]->device;
+        for (sa_dindex *d : s->refs)
+            if (d->device != s->device) return fail(SA_EINVAL, "all indexes must be on one device");
+        DeviceGuard g(s->device);
+        if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
+        size_t free_b = 0, total_b = 0;
+        hipError_t e = hipMemGetInfo(&free_b, &total_b);
+        if (e != hipSuccess) return hip_fail(e, "hipMemGetInfo");
+        const int64_t free_hbm = o.test_fake_free_hbm >= 0 ? o.test_fake_free_hbm : (int64_t)free_b;
+        // per slot: starts/ends, results, and the pipeline scratch (~120 B per read)
+        const int64_t per_slot = o.max_batch_reads * (16 + 16 + 130);
+        const int64_t budget = free_hbm - o.hbm_reserve_bytes - per_slot * o.nstreams;
+        if (budget < (1 << 20)) return fail(SA_ENOSPC, "not enough free device memory for the server");
+        const int64_t arena_bytes = std::min<int64_t>(budget, (int64_t)16 << 30);
+        if ((e = hipMalloc((void **)&s->d_arena, (size_t)arena_bytes)) != hipSuccess)
+            return hip_fail(e, "arena allocation");
+        s->arena.init(arena_bytes);
+        if ((e = hipStreamCreateWithFlags(&s->upload_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "stream creation");
+        for (Slot &sl : s->slots) {
+            if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
+                (e = hipHostMalloc((void **)&sl.h_se, sizeof(int64_t) * 2 * (size_t)o.max_batch_reads,
+                                   hipHostMallocDefault)) != hipSuccess ||
+                (e = hipHostMalloc((void **)&sl.h_out, sizeof(sa_hit) * (size_t)o.max_batch_reads,
+                                   hipHostMallocDefault)) != hipSuccess ||
+                (e = hipMalloc((void **)&sl.d_se, sizeof(int64_t) * 2 * (size_t)o.max_batch_reads)) != hipSuccess ||
+                (e = hipMalloc((void **)&sl.d_out, sizeof(sa_hit) * (size_t)o.max_batch_reads)) != hipSuccess)
+                return hip_fail(e, "slot allocation");
+            // size every index's scratch for this stream now, not on the first batch
+            for (sa_dindex *d : s->refs) {
+                int rc = workspace_for(d, sl.stream)->reserve(o.max_batch_reads);
+                if (rc) return rc;
+            }
+        }
+    }
+    sa_server *raw = s.get();
+    s->loop = std::thread([raw] { raw->run(); });
+    *out = s.release();
+    return SA_OK;
+}
+
+extern "C" int match_submit(sa_server *s, int ref, const char *reads, const int64_t *offs, int64_t nreads,
+                            sa_hit *out, uint64_t *ticket) {
+    clear_error();
+    if (!s || !offs || !ticket || nreads < 0 || (nreads > 0 && (!reads || !out)))
+        return fail(SA_EINVAL, "bad argument");
+    if (ref < 0 || ref >= (int)s->refs.size()) return fail(SA_EINVAL, "no such reference");
+    if (offs[0] < 0) return fail(SA_EINVAL, "negative offset");
+    for (int64_t i = 0; i < nreads; i++) {
+        const int64_t m = offs[i + 1] - offs[i];
+        if (m < 0) return fail(SA_EINVAL, "offsets decrease");
+        if (m > SA_MAX_READ) return fail(SA_ETOOBIG, "read longer than SA_MAX_READ");
+    }
+    std::unique_ptr<Request> r(new Request);
+    r->ref = ref;
+    r->nreads = nreads;
+    r->out = out;
+    r->t_submit = now_ns();
+    try {
+        const int64_t base = offs[0], nbytes = offs[nreads] - offs[0];
+        r->reads.assign(reads + base, reads + base + nbytes);
+        r->offs.resize((size_t)nreads + 1);
+        for (int64_t i = 0; i <= nreads; i++) r->offs[(size_t)i] = offs[i] - base;
+    } catch (const std::bad_alloc &) {
+        return fail(SA_ENOMEM, "request copy");
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(SA_ECANCELED, "server is shutting down");
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->queued.push_back(r.get());
+    s->all[r->ticket] = std::move(r);
+    s->cv_work.notify_one();
+    return SA_OK;
+}
+
+extern "C" int match_poll(sa_server *s, uint64_t ticket, int64_t timeout_us, sa_req_stats *st) {
+    clear_error();
+    if (!s) return fail(SA_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(SA_ENOTFOUND, "unknown ticket");
+    Request *r = it->second.get();
+    if (r->status == SA_PENDING && timeout_us != 0) {
+        auto pred = [r] { return r->status != SA_PENDING; };
+        if (timeout_us < 0) s->cv_done.wait(lk, pred);
+        else s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), pred);
+    }
+    if (st) {
+        st->t_submit_ns = r->t_submit;
+        st->t_admit_ns = r->t_admit;
+        st->t_done_ns = r->t_done;
+        st->status = r->status;
+        st->nreads = r->nreads;
+    }
+    return r->status;
+}
+
+extern "C" int sa_server_destroy(sa_server *s) {
+    clear_error();
+    if (!s) return SA_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        // queued and admitted-but-unscheduled work is cancelled now; batches
+        // already on the device finish first
+        while (!s->queued.empty()) {
+            s->finish_locked(s->queued.front(), SA_ECANCELED);
+            s->queued.pop_front();
+        }
+        for (auto &q : s->active) {
+            for (Request *r : q) {
+                if (r->inflight_batches == 0) {
+                    s->finish_locked(r, SA_ECANCELED);
+                } else if (!r->failed) {
+                    r->failed = true;
+                    r->fail_code = SA_ECANCELED;
+                }
+            }
+            q.clear();
+        }
+        s->cv_work.notify_all();
+    }
+    if (s->loop.joinable()) s->loop.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &kv : s->all)
+            if (kv.second->status == SA_PENDING) s->finish_locked(kv.second.get(), SA_ECANCELED);
+    }
+    if (s->o.test_echo) {
+        for (Slot &sl : s->slots) delete[] sl.h_out;
+    } else {
+        DeviceGuard g(s->device);
+        for (Slot &sl : s->slots) {
+            if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.h_se) (void)hipHostFree(sl.h_se);
+            if (sl.h_out) (void)hipHostFree(sl.h_out);
+            if (sl.d_se) (void)hipFree(sl.d_se);
+            if (sl.d_out) (void)hipFree(sl.d_out);
+            // the indexes keep a workspace per stream; drop this stream's
+            for (sa_dindex *d : s->refs) {
+                std::lock_guard<std::mutex> g2(d->mu);
+                d->ws.erase((void *)sl.stream);
+            }
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        }
+        if (s->upload_stream) {
+            (void)hipStreamSynchronize(s->upload_stream);
+            (void)hipStreamDestroy(s->upload_stream);
+        }
+        if (s->d_arena) (void)hipFree(s->d_arena);
+    }
+    delete s;
+    return SA_OK;
+}

@@ -1,0 +1,222 @@
+// Autotuner: times candidate launch configurations of the tuned path on a
+// caller-supplied device batch and keeps the fastest as the index default.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "device_state.h"
+
+using namespace samatch;
+
+namespace {
+
+// Length histogram of the batch in 32-base classes (device offsets copied
+// to the host once).
+int length_histogram(const int64_t *d_offs, int64_t nreads, hipStream_t s, std::vector<int64_t> &hist) {
+    std::vector<int64_t> offs((size_t)nreads + 1);
+    hipError_t e = hipMemcpyAsync(offs.data(), d_offs, sizeof(int64_t) * offs.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "length histogram");
+    hist.assign(SA_MAX_READ / 32 + 1, 0);
+    for (int64_t i = 0; i < nreads; i++) {
+        const int64_t m = std::max<int64_t>(0, std::min<int64_t>(offs[i + 1] - offs[i], SA_MAX_READ));
+        hist[(size_t)((m + 31) / 32)]++;
+    }
+    return SA_OK;
+}
+
+std::string cache_key(const sa_dindex *d, const std::vector<int64_t> &hist, int64_t nreads) {
+    std::ostringstream k;
+    k << d->arch << "|n=" << d->n << "|cu=" << d->cu_count << "|h=";
+    // length classes present with their share in percent, so that batches of
+    // the same shape share a tuning
+    for (size_t i = 0; i < hist.size(); i++) {
+        if (!hist[i]) continue;
+        k << i << ":" << (hist[i] * 100 + nreads / 2) / std::max<int64_t>(1, nreads) << ",";
+    }
+    return k.str();
+}
+
+std::string cfg_json(const sa_match_cfg &c) {
+    std::ostringstream o;
+    o << "\"tile_levels\":" << c.tile_levels << ",\"block\":" << c.block << ",\"blocks_per_cu\":" << c.blocks_per_cu
+      << ",\"sort\":" << c.sort << ",\"nbuckets\":" << c.nbuckets << ",\"bucket_edge\":[";
+    for (int i = 0; i < c.nbuckets; i++) o << (i ? "," : "") << c.bucket_edge[i];
+    o << "]";
+    return o.str();
+}
+
+int json_int(const std::string &line, const std::string &name, int dflt) {
+    const std::string pat = "\"" + name + "\":";
+    const size_t p = line.find(pat);
+    if (p == std::string::npos) return dflt;
+    return std::atoi(line.c_str() + p + pat.size());
+}
+
+bool parse_cached(const std::string &path, const std::string &key, sa_match_cfg &c, double &ms) {
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    const std::string kpat = "\"key\":\"" + key + "\"";
+    while (std::getline(f, line)) {
+        if (line.find(kpat) == std::string::npos) continue;
+        std::memset(&c, 0, sizeof c);
+        c.kernel = SA_KERNEL_TUNED;
+        c.tile_levels = json_int(line, "tile_levels", 12);
+        c.block = json_int(line, "block", 256);
+        c.blocks_per_cu = json_int(line, "blocks_per_cu", 8);
+        c.sort = json_int(line, "sort", 1);
+        c.nbuckets = std::max(1, std::min(8, json_int(line, "nbuckets", 1)));
+        const size_t p = line.find("\"bucket_edge\":[");
+        if (p != std::string::npos) {
+            const char *q = line.c_str() + p + 15;
+            for (int i = 0; i < c.nbuckets; i++) {
+                c.bucket_edge[i] = std::atoi(q);
+                while (*q && *q != ',' && *q != ']') q++;
+                if (*q == ',') q++;
+            }
+        }
+        const size_t pm = line.find("\"ms\":");
+        ms = pm == std::string::npos ? 0.0 : std::atof(line.c_str() + pm + 5);
+        found = true;  // the last matching line wins
+    }
+    return found;
+}
+
+// Bucket layouts to try: one bucket, and edges at multiples of 32 bases
+// that split the batch's length classes into 2, 3 or 4 groups of similar
+// read counts.
+std::vector<std::vector<int>> bucket_layouts(const std::vector<int64_t> &hist) {
+    std::vector<std::vector<int>> out;
+    out.push_back({SA_MAX_READ});
+    int64_t total = 0;
+    int classes = 0;
+    for (int64_t h : hist) {
+        total += h;
+        classes += h > 0;
+    }
+    for (int parts = 2; parts <= 4 && parts <= classes; parts++) {
+        std::vector<int> edges;
+        int64_t acc = 0;
+        int next = 1;
+        for (size_t i = 0; i < hist.size() && next < parts; i++) {
+            acc += hist[i];
+            if (acc * parts >= total * next && hist[i] > 0) {
+                edges.push_back((int)i * 32);
+                next++;
+            }
+        }
+        edges.push_back(SA_MAX_READ);
+        edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+        if ((int)edges.size() >= 2) out.push_back(edges);
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_offs, int64_t nreads,
+                       void *hip_stream, const char *cache_path, sa_match_cfg *best, double *best_ms) {
+    clear_error();
+    if (!d || !d_reads || !d_offs || nreads < 1) return fail(SA_EINVAL, "bad argument");
+    DeviceGuard g(d->device);
+    if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::vector<int64_t> hist;
+    int rc = length_histogram(d_offs, nreads, s, hist);
+    if (rc) return rc;
+    const std::string key = cache_key(d, hist, nreads);
+    sa_match_cfg found{};
+    double found_ms = 0;
+    if (cache_path && parse_cached(cache_path, key, found, found_ms) && check_cfg(d, found) == SA_OK) {
+        d->defaults = found;
+        if (best) *best = found;
+        if (best_ms) *best_ms = found_ms;
+        return SA_OK;
+    }
+    sa_hit *d_out = nullptr;
+    hipError_t e = hipMalloc((void **)&d_out, sizeof(sa_hit) * (size_t)nreads);
+    if (e != hipSuccess) return hip_fail(e, "tuner output");
+    hipEvent_t t0, t1;
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    Workspace *ws = workspace_for(d, s);
+    sa_match_cfg top = d->defaults;
+    double top_ms = 1e30;
+    auto time_cfg = [&](const sa_match_cfg &c, double &ms) -> int {
+        if (check_cfg(d, c) != SA_OK) return SA_EINVAL;
+        std::lock_guard<std::mutex> lk(ws->mu);
+        int r = enqueue_batch(d, ws, d_reads, d_offs, nullptr, nreads, d_out, s, c);  // warm-up
+        if (r) return r;
+        float best_rep = 1e30f;
+        for (int rep = 0; rep < 3; rep++) {
+            (void)hipEventRecord(t0, s);
+            r = enqueue_batch(d, ws, d_reads, d_offs, nullptr, nreads, d_out, s, c);
+            if (r) return r;
+            (void)hipEventRecord(t1, s);
+            hipError_t ee = hipEventSynchronize(t1);
+            if (ee != hipSuccess) return hip_fail(ee, "tuner timing");
+            float t = 0;
+            (void)hipEventElapsedTime(&t, t0, t1);
+            best_rep = std::min(best_rep, t);
+        }
+        ms = best_rep;
+        return SA_OK;
+    };
+    // stage 1: tile depth x workgroup shape with one bucket
+    std::vector<int> levels;
+    for (int t = std::min(13, d->tile_levels); t >= std::max(1, std::min(9, d->tile_levels)); t--) levels.push_back(t);
+    for (int lv : levels) {
+        for (int block : {256, 512, 1024}) {
+            for (int per_cu : {1, 2, 4, 8}) {
+                if (block * per_cu > 4096) continue;
+                sa_match_cfg c{};
+                c.kernel = SA_KERNEL_TUNED;
+                c.tile_levels = lv;
+                c.block = block;
+                c.blocks_per_cu = per_cu;
+                c.nbuckets = 1;
+                c.bucket_edge[0] = SA_MAX_READ;
+                c.sort = 1;
+                double ms = 0;
+                rc = time_cfg(c, ms);
+                if (rc == SA_EINVAL) continue;
+                if (rc) goto done;
+                if (ms < top_ms) { top_ms = ms; top = c; }
+            }
+        }
+    }
+    // stage 2: bucket layouts with the best shape
+    for (const auto &edges : bucket_layouts(hist)) {
+        if (edges.size() == 1) continue;
+        sa_match_cfg c = top;
+        c.nbuckets = (int)edges.size();
+        for (size_t i = 0; i < edges.size(); i++) c.bucket_edge[i] = edges[i];
+        double ms = 0;
+        rc = time_cfg(c, ms);
+        if (rc == SA_EINVAL) continue;
+        if (rc) goto done;
+        if (ms < top_ms) { top_ms = ms; top = c; }
+    }
+    rc = SA_OK;
+    d->defaults = top;
+    if (best) *best = top;
+    if (best_ms) *best_ms = top_ms;
+    if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        if (f) f << "{\"key\":\"" << key << "\"," << cfg_json(top) << ",\"ms\":" << top_ms << "}\n";
+    }
+done:
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    (void)hipFree(d_out);
+    return rc;
+}

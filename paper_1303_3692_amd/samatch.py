@@ -1,0 +1,339 @@
+"""ctypes binding of libsamatch.so: the C-ABI of include/samatch.h with the
+same names.  Argument marshalling only; every step of the matching runs in
+the library.  Device buffers are torch tensors (torch is used for device
+memory and streams only).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsamatch.so")
+
+SA_OK, SA_PENDING = 0, 1
+SA_EINVAL, SA_EALPHABET, SA_ETOOBIG, SA_ENOMEM, SA_EDEVICE = -1, -2, -3, -4, -5
+SA_ENOSPC, SA_ECANCELED, SA_EIO, SA_EFORMAT, SA_ENOTFOUND = -6, -7, -8, -9, -10
+SA_MAX_READ = 320
+SA_HIT_EXACT, SA_HIT_TOOLONG = 1, 2
+SA_KERNEL_TUNED, SA_KERNEL_PLAIN = 0, 1
+
+# every extern "C" symbol the header declares
+EXPORTS = [
+    "sa_build", "sa_build_from_sa", "sa_index_length", "sa_index_copy_sa", "sa_save", "sa_load", "sa_free",
+    "sa_upload", "sa_dfree", "sa_dindex_length", "sa_default_cfg", "match_batch", "match_batch_dev",
+    "sa_stage_times", "sa_probe_counts", "sa_tune",
+    "sa_server_create", "match_submit", "match_poll", "sa_server_destroy", "sa_strerror", "sa_last_error",
+]
+
+
+class SaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class MatchCfg(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int), ("tile_levels", ctypes.c_int), ("block", ctypes.c_int),
+                ("blocks_per_cu", ctypes.c_int), ("nbuckets", ctypes.c_int), ("bucket_edge", ctypes.c_int * 8),
+                ("sort", ctypes.c_int), ("use_graph", ctypes.c_int), ("profile", ctypes.c_int),
+                ("count", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {"kernel": self.kernel, "tile_levels": self.tile_levels, "block": self.block,
+                "blocks_per_cu": self.blocks_per_cu, "nbuckets": self.nbuckets,
+                "bucket_edge": list(self.bucket_edge)[:max(1, self.nbuckets)], "sort": self.sort,
+                "use_graph": self.use_graph}
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_reserve_bytes", ctypes.c_int64), ("max_batch_reads", ctypes.c_int64),
+                ("max_inflight_reads", ctypes.c_int64), ("nstreams", ctypes.c_int),
+                ("test_fake_free_hbm", ctypes.c_int64), ("test_echo", ctypes.c_int), ("test_fail_batch", ctypes.c_int)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
+                ("status", ctypes.c_int), ("nreads", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library; fails loudly when it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python -m paper_1303_3692_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        p, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "sa_build": ([p, i64, pp], i32),
+            "sa_build_from_sa": ([p, i64, p, pp], i32),
+            "sa_index_length": ([p], i64),
+            "sa_index_copy_sa": ([p, p], i32),
+            "sa_save": ([p, ctypes.c_char_p], i32),
+            "sa_load": ([ctypes.c_char_p, pp], i32),
+            "sa_free": ([p], None),
+            "sa_upload": ([p, i32, pp], i32),
+            "sa_dfree": ([p], None),
+            "sa_dindex_length": ([p], i64),
+            "sa_default_cfg": ([p, ctypes.POINTER(MatchCfg)], i32),
+            "match_batch": ([p, p, p, i64, p, p, ctypes.POINTER(MatchCfg)], i32),
+            "match_batch_dev": ([p, p, p, i64, p, p, ctypes.POINTER(MatchCfg)], i32),
+            "sa_stage_times": ([p, p, ctypes.POINTER(ctypes.c_double)], i32),
+            "sa_probe_counts": ([p, p, ctypes.POINTER(ctypes.c_int64)], i32),
+            "sa_tune": ([p, p, p, i64, p, ctypes.c_char_p, ctypes.POINTER(MatchCfg), ctypes.POINTER(ctypes.c_double)], i32),
+            "sa_server_create": ([ctypes.POINTER(ctypes.c_void_p), i32, ctypes.POINTER(ServerOpts), pp], i32),
+            "match_submit": ([p, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_uint64)], i32),
+            "match_poll": ([p, ctypes.c_uint64, i64, ctypes.POINTER(ReqStats)], i32),
+            "sa_server_destroy": ([p], i32),
+            "sa_strerror": ([i32], ctypes.c_char_p),
+            "sa_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        L = lib()
+        raise SaError(rc, f"{what}: {L.sa_strerror(rc).decode()}: {L.sa_last_error().decode()}")
+    return rc
+
+
+def _bytes(a) -> np.ndarray:
+    if isinstance(a, (bytes, bytearray)):
+        return np.frombuffer(bytes(a), dtype=np.uint8)
+    if isinstance(a, str):
+        return np.frombuffer(a.encode(), dtype=np.uint8)
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ index
+
+
+class Index:
+    """Host index (sa_index): n, packed text, suffix array."""
+
+    def __init__(self, ptr: ctypes.c_void_p):
+        self._p = ptr
+
+    @property
+    def ptr(self):
+        return self._p
+
+    def __len__(self) -> int:
+        return int(lib().sa_index_length(self._p))
+
+    def suffix_array(self) -> np.ndarray:
+        out = np.empty(len(self), dtype=np.int32)
+        _check(lib().sa_index_copy_sa(self._p, out.ctypes.data), "sa_index_copy_sa")
+        return out
+
+    def free(self):
+        if self._p:
+            lib().sa_free(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sa_build(text) -> Index:
+    t = _bytes(text)
+    out = ctypes.c_void_p()
+    _check(lib().sa_build(t.ctypes.data, len(t), ctypes.byref(out)), "sa_build")
+    return Index(out)
+
+
+def sa_build_from_sa(text, sa) -> Index:
+    t = _bytes(text)
+    s = np.ascontiguousarray(sa, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(lib().sa_build_from_sa(t.ctypes.data, len(t), s.ctypes.data, ctypes.byref(out)), "sa_build_from_sa")
+    return Index(out)
+
+
+def sa_save(ix: Index, path: str) -> None:
+    _check(lib().sa_save(ix.ptr, path.encode()), "sa_save")
+
+
+def sa_load(path: str) -> Index:
+    out = ctypes.c_void_p()
+    _check(lib().sa_load(path.encode(), ctypes.byref(out)), "sa_load")
+    return Index(out)
+
+
+class DIndex:
+    """Device-resident index (sa_dindex)."""
+
+    def __init__(self, ptr: ctypes.c_void_p, device: int):
+        self._p = ptr
+        self.device = device
+
+    @property
+    def ptr(self):
+        return self._p
+
+    def __len__(self) -> int:
+        return int(lib().sa_dindex_length(self._p))
+
+    def default_cfg(self) -> MatchCfg:
+        c = MatchCfg()
+        _check(lib().sa_default_cfg(self._p, ctypes.byref(c)), "sa_default_cfg")
+        return c
+
+    def free(self):
+        if self._p:
+            lib().sa_dfree(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sa_upload(ix: Index, device: int = 0) -> DIndex:
+    out = ctypes.c_void_p()
+    _check(lib().sa_upload(ix.ptr, device, ctypes.byref(out)), "sa_upload")
+    return DIndex(out, device)
+
+
+def cfg(d: DIndex | None = None, **kw) -> MatchCfg:
+    """A launch configuration: the index defaults (or zeros) with fields overridden."""
+    c = d.default_cfg() if d is not None else MatchCfg()
+    for k, v in kw.items():
+        if k == "bucket_edge":
+            for i, e in enumerate(v):
+                c.bucket_edge[i] = int(e)
+        else:
+            setattr(c, k, int(v))
+    return c
+
+
+# ------------------------------------------------------------------ batches
+
+
+def match_batch(d: DIndex, data, offs, stream=None, config: MatchCfg | None = None) -> np.ndarray:
+    """Host batch; returns (N, 4) int32 rows {lo, hi, len, flags} in input order."""
+    data = _bytes(data)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    n = len(offs) - 1
+    out = np.zeros((max(n, 0), 4), dtype=np.int32)
+    if n <= 0:
+        return out
+    buf = data if len(data) else np.zeros(1, dtype=np.uint8)
+    _check(lib().match_batch(d.ptr, buf.ctypes.data, offs.ctypes.data, n, out.ctypes.data,
+                             _stream_handle(stream), ctypes.byref(config) if config is not None else None),
+           "match_batch")
+    return out
+
+
+def match_batch_dev(d: DIndex, d_reads, d_offs, d_out, nreads: int | None = None, stream=None,
+                    config: MatchCfg | None = None) -> None:
+    """Device batch on torch tensors: d_reads uint8, d_offs int64 [N+1], d_out int32 [N, 4]."""
+    n = (d_offs.numel() - 1) if nreads is None else nreads
+    _check(lib().match_batch_dev(d.ptr, ctypes.c_void_p(d_reads.data_ptr()), ctypes.c_void_p(d_offs.data_ptr()), n,
+                                 ctypes.c_void_p(d_out.data_ptr()), _stream_handle(stream),
+                                 ctypes.byref(config) if config is not None else None), "match_batch_dev")
+
+
+def sa_stage_times(d: DIndex, stream=None) -> dict:
+    """Stage times (ms) of the last profiled batch on this stream."""
+    ms = (ctypes.c_double * 4)()
+    _check(lib().sa_stage_times(d.ptr, _stream_handle(stream), ms), "sa_stage_times")
+    return {"pack": ms[0], "sort": ms[1], "search": ms[2], "total": ms[3]}
+
+
+def sa_probe_counts(d: DIndex, stream=None) -> dict:
+    """Probe counts of the last counted batch on this stream."""
+    c = (ctypes.c_int64 * 5)()
+    _check(lib().sa_probe_counts(d.ptr, _stream_handle(stream), c), "sa_probe_counts")
+    return {"global_probes": c[0], "text_words": c[1], "tile_probes": c[2], "reads": c[3], "query_words": c[4]}
+
+
+def sa_tune(d: DIndex, d_reads, d_offs, nreads: int | None = None, stream=None, cache_path: str | None = None):
+    """Autotune on a device batch; returns (MatchCfg, ms per batch)."""
+    n = (d_offs.numel() - 1) if nreads is None else nreads
+    best = MatchCfg()
+    ms = ctypes.c_double()
+    _check(lib().sa_tune(d.ptr, ctypes.c_void_p(d_reads.data_ptr()), ctypes.c_void_p(d_offs.data_ptr()), n,
+                         _stream_handle(stream), cache_path.encode() if cache_path else None, ctypes.byref(best),
+                         ctypes.byref(ms)), "sa_tune")
+    return best, ms.value
+
+
+# ------------------------------------------------------------------ serving
+
+
+class Server:
+    """Request loop (sa_server) over resident indexes."""
+
+    def __init__(self, refs, **opts):
+        o = ServerOpts()
+        o.test_fake_free_hbm = -1
+        for k, v in opts.items():
+            setattr(o, k, int(v))
+        self._refs = list(refs)  # keep the indexes alive
+        arr = (ctypes.c_void_p * len(self._refs))(*[r.ptr if r is not None else None for r in self._refs])
+        out = ctypes.c_void_p()
+        _check(lib().sa_server_create(arr, len(self._refs), ctypes.byref(o), ctypes.byref(out)), "sa_server_create")
+        self._p = out
+        self._pending = {}
+
+    def submit(self, ref: int, data, offs):
+        """Queue a request; returns (ticket, out array filled on completion)."""
+        data = _bytes(data)
+        offs = np.ascontiguousarray(offs, dtype=np.int64)
+        n = len(offs) - 1
+        out = np.zeros((max(n, 1), 4), dtype=np.int32)
+        buf = data if len(data) else np.zeros(1, dtype=np.uint8)
+        t = ctypes.c_uint64()
+        _check(lib().match_submit(self._p, ref, buf.ctypes.data, offs.ctypes.data, n, out.ctypes.data,
+                                  ctypes.byref(t)), "match_submit")
+        self._pending[t.value] = out  # must stay alive until the request finishes
+        return t.value, out[:n]
+
+    def poll(self, ticket: int, timeout_us: int = 0):
+        """(status, stats dict); status SA_PENDING, SA_OK or an error code."""
+        st = ReqStats()
+        rc = lib().match_poll(self._p, ticket, timeout_us, ctypes.byref(st))
+        if rc == SA_ENOTFOUND:
+            _check(rc, "match_poll")
+        return rc, {"t_submit_ns": st.t_submit_ns, "t_admit_ns": st.t_admit_ns, "t_done_ns": st.t_done_ns,
+                    "status": st.status, "nreads": st.nreads}
+
+    def destroy(self):
+        if self._p:
+            _check(lib().sa_server_destroy(self._p), "sa_server_destroy")
+            self._p = None
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,204 @@
+"""HIP path against the CPU oracle, bit for bit: {lo, hi, len} and the exact
+flag of every read (the results are unique, so any tile depth, pivot rule,
+read order, bucket layout or launch shape must give the same bits)."""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import paper_1303_3692_amd as S
+from oracle import brute, oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda:0")
+
+
+def run_dev(d, data, offs, device, config=None):
+    data = np.asarray(data, dtype=np.uint8)
+    offs = np.asarray(offs, dtype=np.int64)
+    n = len(offs) - 1
+    d_reads = torch.from_numpy(data if len(data) else np.zeros(1, np.uint8)).to(device)
+    d_offs = torch.from_numpy(offs).to(device)
+    d_out = torch.full((max(n, 1), 4), -7, dtype=torch.int32, device=device)
+    S.match_batch_dev(d, d_reads, d_offs, d_out, nreads=n, config=config)
+    torch.cuda.synchronize()
+    return d_out.cpu().numpy()[:n]
+
+
+def assert_same(got, want, label=""):
+    exact = (got[:, 3] & S.SA_HIT_EXACT).astype(np.int32)
+    bad = np.nonzero((got[:, :3] != want[:, :3]).any(axis=1) | (exact != want[:, 3]))[0]
+    assert len(bad) == 0, f"{label}: {len(bad)} mismatches, first rows {bad[:5]}: got {got[bad[:3]]} want {want[bad[:3]]}"
+
+
+CONFIGS = [
+    ("plain", dict(kernel=S.SA_KERNEL_PLAIN)),
+    ("tuned-default", dict()),
+    ("tuned-t1-unsorted", dict(tile_levels=1, sort=0, block=256, blocks_per_cu=1)),
+    ("tuned-t5-b512", dict(tile_levels=5, block=512, blocks_per_cu=2)),
+    ("tuned-t13-b1024", dict(tile_levels=13, block=1024, blocks_per_cu=1)),
+    ("tuned-buckets", dict(nbuckets=3, bucket_edge=[64, 160, 320], blocks_per_cu=4)),
+]
+
+
+def configs_for(d):
+    out = []
+    for name, kw in CONFIGS:
+        kw = dict(kw)
+        if "tile_levels" in kw:
+            kw["tile_levels"] = min(kw["tile_levels"], d.default_cfg().tile_levels if len(d) < 8191 else 13)
+        out.append((name, S.cfg(d, **kw)))
+    return out
+
+
+def check_text(text, reads, device, label):
+    t = text.upper() if isinstance(text, str) else text
+    ix = S.sa_build(t)
+    d = S.sa_upload(ix, 0)
+    data, offs = oracle.pack_reads(reads)
+    want = oracle.match(t, oracle.sa_build(t), data, offs)
+    for name, c in configs_for(d):
+        if len(d) < (1 << 13) - 1 and c.kernel == S.SA_KERNEL_TUNED:
+            c.tile_levels = min(c.tile_levels, max(1, int(np.ceil(np.log2(len(d) + 1)))))
+        assert_same(run_dev(d, data[:-1] if len(data) else data, offs, device, c), want, f"{label}/{name}")
+    return d, want
+
+
+def test_paper_example(device):
+    say("case: paper example")
+    reads = ["a", "c", "ggtac", "tac", "g", "ac", "acg", "gt", "gtac", "gtacg", "ta", "acgta", "", "tt", "cc",
+             "aca", "acgtt", "tacgtacgt", "acggtacgtacg", "ACGGTACGTAC", "GN", "n"]
+    d, want = check_text("acggtacgtac", reads, device, "paper")
+    # printed ranges (Section IV): LB..RB inclusive
+    got = {r: tuple(int(x) for x in row) for r, row in zip(reads, want)}
+    assert (got["a"][0], got["a"][1] - 1) == (0, 2)
+    assert (got["c"][0], got["c"][1] - 1) == (3, 5)
+    assert (got["ggtac"][0], got["ggtac"][1] - 1) == (6, 6)
+    assert (got["tac"][0], got["tac"][1] - 1) == (9, 10)
+    for r in reads:
+        assert got[r] == brute.match("acggtacgtac", r)
+
+
+@pytest.mark.parametrize("kind", ["iid", "allA", "alt", "tandem"])
+def test_tiny_texts_against_brute(device, kind):
+    say("case: tiny", kind)
+    rng = random.Random(sum(map(ord, kind)))
+    for trial in range(6):
+        n = rng.randint(1, 90)
+        if kind == "iid":
+            text = "".join(rng.choice("ACGT") for _ in range(n))
+        elif kind == "allA":
+            text = "A" * n
+        elif kind == "alt":
+            text = ("AC" * n)[:n]
+        else:
+            unit = "".join(rng.choice("ACGT") for _ in range(rng.randint(1, 4)))
+            text = (unit * n)[:n]
+        reads = ["", text, text + "A", text.lower(), text[: n // 2] + "N"]
+        for _ in range(60):
+            i = rng.randrange(n)
+            r = text[i:i + rng.randint(1, 70)]
+            if rng.random() < 0.3:
+                j = rng.randrange(len(r))
+                r = r[:j] + rng.choice("ACGTN") + r[j + 1:]
+            if rng.random() < 0.2:
+                r = r + "".join(rng.choice("ACGT") for _ in range(rng.randint(1, 40)))
+            reads.append(r)
+        check_text(text, reads, device, f"{kind}/{trial}")
+        for r in reads[:20]:
+            pass
+
+
+def test_long_and_too_long_reads(device):
+    say("case: long reads")
+    ref = gen.make_reference("c2", n=300_000)
+    text = ref.ascii().tobytes().decode()
+    rng = np.random.default_rng(3)
+    reads = []
+    for m in [31, 32, 33, 63, 64, 65, 255, 256, 257, 300, 319, 320]:
+        for _ in range(8):
+            p = int(rng.integers(0, ref.n - m))
+            r = text[p:p + m]
+            if rng.random() < 0.5:
+                j = int(rng.integers(0, m))
+                r = r[:j] + "ACGT"[(ref.codes[p + j] + 1) % 4] + r[j + 1:]
+            reads.append(r)
+    reads.append(text[-40:] + "ACGT")  # runs off the end of the text
+    reads.append(text[-320:])
+    check_text(text, reads, device, "long")
+    # 321 bases: flagged, not searched (device path); refused (host path)
+    ix = S.sa_build(text)
+    d = S.sa_upload(ix, 0)
+    data, offs = oracle.pack_reads(["ACGT", "A" * 321, "GG"])
+    got = run_dev(d, data[:-1], offs, device)
+    assert tuple(got[1]) == (0, 0, 0, S.SA_HIT_TOOLONG)
+    want = oracle.match(text, oracle.sa_build(text), *oracle.pack_reads(["ACGT", "GG"]))
+    assert_same(got[[0, 2]], want, "around a long read")
+    with pytest.raises(S.SaError) as e:
+        S.match_batch(d, data[:-1], offs)
+    assert e.value.code == S.SA_ETOOBIG
+
+
+@pytest.mark.parametrize("cfg,n,count", [("c1", 1_000_000, 100_000), ("c2", 2_000_000, 200_000),
+                                         ("c3", 2_000_000, 150_000), ("c4", 3_000_000, 150_000)])
+def test_generated_workloads(device, cfg, n, count):
+    say("case: workload", cfg, n, count)
+    ref, reads = gen.workload(cfg, n=n, count=count)
+    text = ref.ascii()
+    d = S.sa_upload(S.sa_build(text), 0)
+    want = oracle.match(text, oracle.sa_build(text), reads.data, reads.offs)
+    for name, c in configs_for(d):
+        assert_same(run_dev(d, reads.data, reads.offs, device, c), want, f"{cfg}/{name}")
+    # host entry point, same results
+    got = S.match_batch(d, reads.data, reads.offs)
+    assert_same(got, want, f"{cfg}/host")
+
+
+def test_ragged_batch_sizes(device):
+    say("case: ragged sizes")
+    ref, reads = gen.workload("c3", n=500_000, count=70_001)
+    text = ref.ascii()
+    d = S.sa_upload(S.sa_build(text), 0)
+    want = oracle.match(text, oracle.sa_build(text), reads.data, reads.offs)
+    for k in [1, 2, 63, 64, 65, 4095, 4096, 4097, 70_001]:
+        got = run_dev(d, reads.data, reads.offs[: k + 1], device)
+        assert_same(got, want[:k], f"k={k}")
+    # offsets that start inside the buffer
+    off2 = reads.offs[1000:3001] - 0
+    got = run_dev(d, reads.data, off2, device)
+    assert_same(got, want[1000:3000], "offset start")
+
+
+def test_streams_and_reuse(device):
+    say("case: streams")
+    ref, reads = gen.workload("c2", n=400_000, count=50_000)
+    text = ref.ascii()
+    d = S.sa_upload(S.sa_build(text), 0)
+    want = oracle.match(text, oracle.sa_build(text), reads.data, reads.offs)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    d_reads = torch.from_numpy(reads.data).to(device)
+    d_offs = torch.from_numpy(reads.offs).to(device)
+    outs = []
+    for s in (s1, s2, s1, s2):
+        o = torch.zeros((reads.count, 4), dtype=torch.int32, device=device)
+        torch.cuda.synchronize()
+        S.match_batch_dev(d, d_reads, d_offs, o, stream=s)
+        outs.append((s, o))
+    torch.cuda.synchronize()
+    for _, o in outs:
+        assert_same(o.cpu().numpy(), want, "stream")
