@@ -235,35 +235,59 @@ __global__ void build_tile_kernel(const uint64_t *__restrict__ text, const int32
 
 // ------------------------------------------------------------------ pack
 
-// One thread per read: ASCII (either case) to 2-bit words, the length of
-// the ACGT prefix, and the sort key (length bucket, first 12 bases).  Read
-// i is reads[offs[i] .. offs[i+1]), or reads[offs[i] .. ends[i]) when an end
-// array is given (reads scattered over a larger buffer).  Bytes
-// are fetched as aligned dwords; an aligned dword that holds at least one
-// byte of the read never crosses a page, so no fetch can fault.
-__global__ void pack_kernel(const uint8_t *__restrict__ reads, const int64_t *__restrict__ offs,
-                            const int64_t *__restrict__ ends, int64_t nreads, BatchBuffers b, BucketTable bt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *b.counter = 0u;
-    if (i < 8) b.stats[i] = 0ull;
-    if (i >= nreads) return;
-    const int64_t a = offs[i], e = ends ? ends[i] : offs[i + 1];
-    const int64_t m64 = e - a;
-    uint64_t *dst = b.qw + (size_t)i * kWMax;
-    if (m64 < 0 || m64 > kMaxRead) {
-        b.qlen[i] = -1;
-        b.qmv[i] = 0;
-        dst[0] = 0;
-        b.key[0][i] = 0;
-        b.val[0][i] = (uint32_t)i;
-        return;
-    }
-    const int m = (int)m64;
-    int mv = m;
+// Per-byte flags (0x80 in each byte) of the four bytes of x that are not
+// one of a, c, g, t after forcing lower case: a byte is nonzero after
+// xor-ing with a letter unless it is that letter.
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t v) {
+    return (((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
+}
+__device__ __forceinline__ uint32_t invalid_bytes(uint32_t dw) {
+    const uint32_t lc = dw | 0x20202020u;
+    return nonzero_bytes(lc ^ 0x61616161u) & nonzero_bytes(lc ^ 0x63636363u) & nonzero_bytes(lc ^ 0x67676767u) &
+           nonzero_bytes(lc ^ 0x74747474u);
+}
+
+// Four bases (little-endian bytes of dw, the first base in the low byte) to
+// 8 bits, first base in the top two bits; `keep` masks the bytes that
+// belong to the read.  a->0 c->1 g->2 t->3 for either case, anything else
+// becomes 0 and is reported in *bad (0x80 per byte).
+__device__ __forceinline__ uint32_t pack4(uint32_t dw, uint32_t keep, uint32_t &bad) {
+    bad = invalid_bytes(dw) & keep;
+    const uint32_t zero = (bad >> 7) * 0xFFu;  // 0xFF in each flagged byte
+    const uint32_t codes = ((dw >> 1) ^ (dw >> 2)) & 0x03030303u & keep & ~zero;
+    return ((codes & 3u) << 6) | ((codes >> 4) & 0x30u) | ((codes >> 14) & 0x0Cu) | ((codes >> 24) & 3u);
+}
+
+// Shared tail of both pack paths: length, ACGT-prefix length, sort key.
+__device__ __forceinline__ void pack_finish(const BatchBuffers &b, const BucketTable &bt, int64_t i, int m, int mv,
+                                            uint64_t w0) {
+    b.qlen[i] = m;
+    b.qmv[i] = mv;
+    int bucket = bt.count - 1;
+    for (int j = 0; j < bt.count; ++j)
+        if (m <= bt.edge[j]) { bucket = j; break; }
+    b.key[0][i] = ((uint32_t)bucket << 24) | (uint32_t)(w0 >> 40);
+    b.val[0][i] = (uint32_t)i;
+}
+
+__device__ __forceinline__ void pack_reject(const BatchBuffers &b, int64_t i) {
+    b.qlen[i] = -1;
+    b.qmv[i] = 0;
+    b.qw[(size_t)i * kWMax] = 0;
+    b.key[0][i] = 0;
+    b.val[0][i] = (uint32_t)i;
+}
+
+// Pack one read from global memory, fetching aligned dwords; an aligned
+// dword that holds at least one byte of the read never crosses a page, so
+// no fetch can fault.
+__device__ void pack_from_global(const uint8_t *__restrict__ reads, int64_t a, int m, uint64_t *dst, int &mv,
+                                 uint64_t &w0) {
+    mv = m;
     uint64_t word = 0;
     int k = 0;
     const uintptr_t start = (uintptr_t)(reads + a);
-    const uintptr_t stop = (uintptr_t)(reads + e);
+    const uintptr_t stop = start + (uintptr_t)m;
     for (uintptr_t addr = start & ~(uintptr_t)3; addr < stop; addr += 4) {
         const uint32_t dw = *reinterpret_cast<const uint32_t *>(addr);
 #pragma unroll
@@ -274,7 +298,6 @@ __global__ void pack_kernel(const uint8_t *__restrict__ reads, const int64_t *__
             const uint32_t c = (dw >> (8 * t)) & 0xFFu;
             const uint32_t lc = c | 0x20u;
             const bool ok = lc == 'a' || lc == 'c' || lc == 'g' || lc == 't';
-            // a->0 c->1 g->2 t->3 for either case
             const uint32_t code = ((c >> 1) ^ (c >> 2)) & 3u;
             if (!ok && idx < mv) mv = idx;
             word |= (uint64_t)(ok ? code : 0u) << (62 - 2 * (idx & 31));
@@ -282,14 +305,86 @@ __global__ void pack_kernel(const uint8_t *__restrict__ reads, const int64_t *__
         }
     }
     if ((m & 31) != 0 || m == 0) dst[k] = word;
-    b.qlen[i] = m;
-    b.qmv[i] = mv;
-    int bucket = bt.count - 1;
-    for (int j = 0; j < bt.count; ++j)
-        if (m <= bt.edge[j]) { bucket = j; break; }
-    const uint64_t w0 = dst[0];
-    b.key[0][i] = ((uint32_t)bucket << 24) | (uint32_t)(w0 >> 40);
-    b.val[0][i] = (uint32_t)i;
+    w0 = dst[0];
+}
+
+// Packing: each workgroup copies the bytes of its 256 consecutive reads
+// into LDS with coalesced, aligned 16-byte loads, then each thread packs
+// its read from LDS four bases at a time.  Reads whose bytes are not in the
+// staged span (offsets that are not contiguous, or a span larger than the
+// staging buffer) take the global path.  Read i is reads[offs[i] ..
+// offs[i+1]), or reads[offs[i] .. ends[i]) when an end array is given
+// (reads scattered over a larger buffer; always the global path).
+constexpr int kPackBlock = 256;
+constexpr int kPackStage = 48 * 1024;
+
+__global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restrict__ reads,
+                                                          const int64_t *__restrict__ offs,
+                                                          const int64_t *__restrict__ ends, int64_t nreads,
+                                                          BatchBuffers b, BucketTable bt) {
+    __shared__ uint32_t stage[kPackStage / 4 + 8];
+    const int64_t r0 = (int64_t)blockIdx.x * kPackBlock;
+    const int64_t r1 = r0 + kPackBlock < nreads ? r0 + kPackBlock : nreads;
+    const int64_t i = r0 + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *b.counter = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 8) b.stats[threadIdx.x] = 0ull;
+    const int64_t span0 = offs[r0];
+    const int64_t span1 = ends ? span0 : offs[r1];
+    const uintptr_t A0 = (uintptr_t)(reads + span0) & ~(uintptr_t)15;
+    const uintptr_t A1 = ((uintptr_t)(reads + span1) + 15) & ~(uintptr_t)15;
+    const bool staged = !ends && span1 > span0 && A1 - A0 <= (uintptr_t)kPackStage;
+    if (staged) {
+        // every aligned 16-byte chunk here holds a byte of [span0, span1)
+        for (uintptr_t c = A0 + 16u * threadIdx.x; c < A1; c += 16u * kPackBlock)
+            *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(stage) + (c - A0)) =
+                *reinterpret_cast<const uint4 *>(c);
+    }
+    __syncthreads();
+    if (i >= nreads) return;
+    const int64_t a = offs[i], e = ends ? ends[i] : offs[i + 1];
+    const int64_t m64 = e - a;
+    if (m64 < 0 || m64 > kMaxRead) {
+        pack_reject(b, i);
+        return;
+    }
+    const int m = (int)m64;
+    uint64_t *dst = b.qw + (size_t)i * kWMax;
+    int mv = m;
+    uint64_t w0 = 0;
+    if (staged && a >= span0 && e <= span1) {
+        const uint32_t q = (uint32_t)((uintptr_t)(reads + a) - A0);
+        const uint32_t *src = stage + (q >> 2);
+        const uint32_t sh = (q & 3u) * 8u;
+        const int ndw = (m + 3) >> 2;
+        uint64_t word = 0;
+        int k = 0;
+        uint32_t lo = src[0];
+        for (int j = 0; j < ndw; ++j) {
+            const uint32_t hi = src[j + 1];
+            const uint32_t dw = sh ? (lo >> sh) | (hi << (32u - sh)) : lo;
+            lo = hi;
+            const int rem = m - 4 * j;
+            const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u);
+            uint32_t bad;
+            word = (word << 8) | pack4(dw, keep, bad);
+            if (bad && mv == m) mv = 4 * j + (__builtin_ctz(bad) >> 3);
+            if ((j & 7) == 7) {
+                if (k == 0) w0 = word;
+                dst[k++] = word;
+                word = 0;
+            }
+        }
+        if ((ndw & 7) != 0) {
+            word <<= 8 * (8 - (ndw & 7));
+            if (k == 0) w0 = word;
+            dst[k] = word;
+        } else if (m == 0) {
+            dst[0] = 0;
+        }
+    } else {
+        pack_from_global(reads, a, m, dst, mv, w0);
+    }
+    pack_finish(b, bt, i, m, mv, w0);
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -603,9 +698,9 @@ hipError_t launch_build_tile(const uint64_t *text, const int32_t *sa, int32_t n,
 
 hipError_t launch_pack(const uint8_t *reads, const int64_t *offs, const int64_t *ends, int64_t nreads,
                        const BatchBuffers &b, const BucketTable &bt, hipStream_t s) {
-    const int64_t blocks = (nreads + 255) / 256;
-    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, reads, offs, ends,
-                       nreads, b, bt);
+    const int64_t blocks = (nreads + kPackBlock - 1) / kPackBlock;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kPackBlock), 0, s, reads, offs,
+                       ends, nreads, b, bt);
     return hipGetLastError();
 }
 
