@@ -54,6 +54,11 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the built-in launch defaults")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, copy this many MiB device to device once (a kernel of known traffic "
+                         "for scaling memory counters)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1303_3692_amd", "tuning_cache.jsonl"),
+                    help="autotuner cache (JSON lines); a hit skips the sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (reads shard across GPUs "
@@ -90,10 +95,19 @@ def main():
     d_out = torch.zeros((N, 4), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del src, dst
+
     tuned_ms = None
     if not args.no_tune:
         t = time.perf_counter()
-        _, tuned_ms = S.sa_tune(d, d_reads, d_offs, stream=stream)
+        _, tuned_ms = S.sa_tune(d, d_reads, d_offs, stream=stream, cache_path=args.tune_cache)
         log(f"tuner: {time.perf_counter() - t:.1f}s -> {S.cfg(d).as_dict()} ({tuned_ms:.3f} ms)")
     cfg = S.cfg(d)
 
@@ -127,8 +141,8 @@ def main():
 
     def alg_bytes(cnt):
         # per read: packed query + 16-byte result; per global probe: a 4-byte
-        # SA entry plus the 8-byte text words it compares
-        return read_bytes + 16 * N + 4 * cnt["global_probes"] + 8 * cnt["text_words"]
+        # SA entry plus the 8-byte words it compares (row keys and text words)
+        return read_bytes + 16 * N + 4 * cnt["global_probes"] + 8 * (cnt["text_words"] + cnt["key_words"])
 
     # ---- tuned path
     cnt = counts(cfg)
@@ -198,7 +212,7 @@ def main():
         "exact_fraction": round(exact, 5),
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "probes_per_read": {"global": round(cnt["global_probes"] / N, 3), "lds": round(cnt["tile_probes"] / N, 3),
-                            "text_words": round(cnt["text_words"] / N, 3)},
+                            "text_words": round(cnt["text_words"] / N, 3), "key_words": round(cnt["key_words"] / N, 3)},
         "index": {"dc3_s": round(t_build, 2), "upload_s": round(t_upload, 4)},
         "plain": plain,
         "speedup_vs_plain": round(value / plain["reads_per_s"], 3) if plain else None,

@@ -95,9 +95,11 @@ int sa_load(const char *path, sa_index **out);
 void sa_free(sa_index *ix);                           /* NULL is a no-op            */
 
 /* Copy the index to device `device` and keep it resident: the packed text
- * (with zero padding words after the end), the int32 SA, and the table of
- * the top levels of the implicit binary-search tree that the tuned kernel
- * stages in LDS (the tile of Section IV).  The host index may be freed
+ * (with zero padding words after the end), the int32 SA, the first 32 bases
+ * of the suffix at every SA row (8 bytes per row, so that most probes of the
+ * tuned kernel never touch the text), and the table of the top levels of
+ * the implicit binary-search tree that the tuned kernel stages in LDS (the
+ * tile of Section IV).  The host index may be freed
  * afterwards.  Released with sa_dfree (NULL is a no-op). */
 int sa_upload(const sa_index *ix, int device, sa_dindex **out);
 void sa_dfree(sa_dindex *d);
@@ -124,6 +126,8 @@ typedef struct {
     int count;           /* 1 = run the instrumented search kernel that counts
                             probes and text words for sa_probe_counts (slower;
                             results are the same)                                */
+    int group;           /* tuned: 64-read chunks per block of the work split
+                            (1..64): workgroup rank r takes blocks r, r+G, ... */
 } sa_match_cfg;
 
 /* Fill cfg with the index's current defaults. */
@@ -154,8 +158,10 @@ int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]);
 /* Counts of the last batch enqueued with cfg.count on this (index, stream):
  * c[0] global-memory probes (one SA entry each), c[1] 64-bit text words
  * those probes compare, c[2] probes answered from the LDS tile, c[3] reads
- * searched, c[4] packed query words loaded.  Waits for that batch. */
-int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[5]);
+ * searched, c[4] packed query words loaded, c[5] probes that also loaded
+ * the 8-byte row key (first 32 bases of the row's suffix).  Waits for that
+ * batch. */
+int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[6]);
 
 /* Autotuner: time candidate configurations (tile depth, workgroups per CU,
  * block size, bucket edges) on the given device batch, keep the fastest as

@@ -36,6 +36,15 @@ def hipcc() -> str:
     return p
 
 
+def build_id() -> str:
+    """Hash of the sources: tuned launch settings are only reused for the same kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for s in SOURCES + ["kernels.h", "device_state.h", "internal.h"]:
+        h.update(open(os.path.join(CSRC, s), "rb").read())
+    return h.hexdigest()[:12]
+
+
 def _compile(src: str, extra: list[str]) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     path = os.path.join(CSRC, src)
@@ -52,7 +61,7 @@ def _compile(src: str, extra: list[str]) -> str:
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     """Compile every source and link libsamatch.so next to this file."""
     os.makedirs(BUILD, exist_ok=True)
-    extra = list(extra or [])
+    extra = list(extra or []) + [f'-DSAMATCH_BUILD_ID="{build_id()}"']
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra), SOURCES))
     tmp = OUT + ".tmp"

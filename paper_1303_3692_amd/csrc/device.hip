@@ -29,7 +29,7 @@ DeviceGuard::~DeviceGuard() {
 Workspace::~Workspace() {
     for (void *p : {(void *)b.qw, (void *)b.qlen, (void *)b.qmv, (void *)b.key[0], (void *)b.key[1],
                     (void *)b.val[0], (void *)b.val[1], (void *)b.hist, (void *)b.digit_total,
-                    (void *)b.counter, (void *)b.stats, (void *)d_reads, (void *)d_offs, (void *)d_out})
+                    (void *)b.stats, (void *)d_reads, (void *)d_offs, (void *)d_out})
         if (p) (void)hipFree(p);
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
@@ -61,8 +61,6 @@ int Workspace::reserve(int64_t nreads) {
         (e = grow((void **)&b.hist, sizeof(uint32_t) * 256 * (size_t)nblocks)) != hipSuccess)
         return hip_fail(e, "scratch allocation");
     if (!b.digit_total && (e = hipMalloc((void **)&b.digit_total, sizeof(uint32_t) * 256)) != hipSuccess)
-        return hip_fail(e, "scratch allocation");
-    if (!b.counter && (e = hipMalloc((void **)&b.counter, sizeof(unsigned) * 64)) != hipSuccess)
         return hip_fail(e, "scratch allocation");
     if (!b.stats && (e = hipMalloc((void **)&b.stats, sizeof(unsigned long long) * 8)) != hipSuccess)
         return hip_fail(e, "scratch allocation");
@@ -123,6 +121,7 @@ int check_cfg(const sa_dindex *d, const sa_match_cfg &c) {
     if (c.block != 256 && c.block != 512 && c.block != 1024) return fail(SA_EINVAL, "block must be 256, 512 or 1024");
     if (c.blocks_per_cu < 1 || c.blocks_per_cu > 16) return fail(SA_EINVAL, "blocks_per_cu must be in 1..16");
     if (c.nbuckets < 1 || c.nbuckets > 8) return fail(SA_EINVAL, "nbuckets must be in 1..8");
+    if (c.group < 1 || c.group > 64) return fail(SA_EINVAL, "group must be in 1..64");
     for (int i = 0; i + 1 < c.nbuckets; i++)
         if (c.bucket_edge[i] < 1 || (i > 0 && c.bucket_edge[i] <= c.bucket_edge[i - 1]))
             return fail(SA_EINVAL, "bucket edges must ascend");
@@ -136,6 +135,7 @@ sa_match_cfg resolve_cfg(const sa_dindex *d, const sa_match_cfg *cfg) {
         if (c.tile_levels == 0) c.tile_levels = def.tile_levels;
         if (c.block == 0) c.block = def.block;
         if (c.blocks_per_cu == 0) c.blocks_per_cu = def.blocks_per_cu;
+        if (c.group == 0) c.group = def.group;
         if (c.nbuckets == 0) {
             c.nbuckets = def.nbuckets;
             std::memcpy(c.bucket_edge, def.bucket_edge, sizeof c.bucket_edge);
@@ -171,7 +171,8 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         if (e != hipSuccess) return hip_fail(e, "plain search launch");
     } else {
         const int grid = std::max(1, d->cu_count * c.blocks_per_cu);
-        e = launch_search_tuned(d->view, c.tile_levels, c.block, grid, ws->b, order, nreads, d_out, c.count != 0, s);
+        e = launch_search_tuned(d->view, c.tile_levels, c.block, grid, c.group, ws->b, order, nreads, d_out,
+                                c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
     if (prof && (e = hipEventRecord(ws->ev[3], s)) != hipSuccess) return hip_fail(e, "event record");
@@ -208,16 +209,18 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
     if ((e = hipMalloc((void **)&d->d_text, text_bytes)) != hipSuccess ||
         (e = hipMalloc((void **)&d->d_sa, sa_bytes)) != hipSuccess ||
         (e = hipMalloc((void **)&d->d_tile_key, nodes * sizeof(uint64_t))) != hipSuccess ||
-        (e = hipMalloc((void **)&d->d_tile_sa, nodes * sizeof(int32_t))) != hipSuccess)
+        (e = hipMalloc((void **)&d->d_tile_sa, nodes * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc((void **)&d->d_row_key, sizeof(uint64_t) * (size_t)ix->n)) != hipSuccess)
         return hip_fail(e, "index allocation");
     if ((e = hipMemcpy(d->d_text, ix->packed.data(), text_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(d->d_sa, ix->sa.data(), sa_bytes, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "index upload");
-    if ((e = launch_build_tile(d->d_text, d->d_sa, (int32_t)ix->n, d->tile_levels, d->d_tile_key, d->d_tile_sa,
+    if ((e = launch_build_row_keys(d->d_text, d->d_sa, (int32_t)ix->n, d->d_row_key, nullptr)) != hipSuccess ||
+        (e = launch_build_tile(d->d_text, d->d_sa, (int32_t)ix->n, d->tile_levels, d->d_tile_key, d->d_tile_sa,
                                nullptr)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess)
         return hip_fail(e, "tile build");
-    d->view = DevIndex{d->d_text, d->d_sa, d->d_tile_key, d->d_tile_sa, (int32_t)ix->n};
+    d->view = DevIndex{d->d_text, d->d_sa, d->d_tile_key, d->d_tile_sa, d->d_row_key, (int32_t)ix->n};
     sa_match_cfg &c = d->defaults;
     std::memset(&c, 0, sizeof c);
     c.kernel = SA_KERNEL_TUNED;
@@ -228,6 +231,7 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
     c.bucket_edge[0] = SA_MAX_READ;
     c.sort = 1;
     c.use_graph = 0;
+    c.group = 4;
     *out = d.release();
     return SA_OK;
 }
@@ -235,7 +239,7 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
 sa_dindex::~sa_dindex() {
     DeviceGuard g(device);
     ws.clear();
-    for (void *p : {(void *)d_text, (void *)d_sa, (void *)d_tile_key, (void *)d_tile_sa})
+    for (void *p : {(void *)d_text, (void *)d_sa, (void *)d_tile_key, (void *)d_tile_sa, (void *)d_row_key})
         if (p) (void)hipFree(p);
 }
 
@@ -333,7 +337,7 @@ extern "C" int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]
     return SA_OK;
 }
 
-extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[5]) {
+extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[6]) {
     clear_error();
     if (!d || !c) return fail(SA_EINVAL, "NULL argument");
     DeviceGuard g(d->device);
@@ -345,6 +349,6 @@ extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[5
     hipError_t e = hipMemcpyAsync(h, ws->b.stats, sizeof h, hipMemcpyDeviceToHost, static_cast<hipStream_t>(hip_stream));
     if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "counter download");
-    for (int i = 0; i < 5; i++) c[i] = (int64_t)h[i];
+    for (int i = 0; i < 6; i++) c[i] = (int64_t)h[i];
     return SA_OK;
 }

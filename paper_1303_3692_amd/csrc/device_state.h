@@ -64,6 +64,7 @@ struct sa_dindex {
     int32_t *d_sa = nullptr;
     uint64_t *d_tile_key = nullptr;
     int32_t *d_tile_sa = nullptr;
+    uint64_t *d_row_key = nullptr;
     int tile_levels = 0;  // levels stored (the kernel may use fewer)
     samatch::DevIndex view{};
     sa_match_cfg defaults{};

@@ -18,6 +18,7 @@ struct DevIndex {
     const int32_t *sa;         // suffix array, n entries
     const uint64_t *tile_key;  // first 32 bases of the pivot suffix of each tree node
     const int32_t *tile_sa;    // text position of each tree node's pivot suffix
+    const uint64_t *row_key;   // first 32 bases of the suffix at each SA row
     int32_t n;
 };
 
@@ -35,9 +36,11 @@ struct BatchBuffers {
     uint32_t *val[2];    // read ids (ping-pong)
     uint32_t *hist;      // 256 * sort blocks
     uint32_t *digit_total;  // 256
-    unsigned *counter;   // work counter of the persistent kernel
     unsigned long long *stats;  // 8 counters of the instrumented search (zeroed by pack)
 };
+
+hipError_t launch_build_row_keys(const uint64_t *text, const int32_t *sa, int32_t n, uint64_t *key,
+                                 hipStream_t s);
 
 hipError_t launch_build_tile(const uint64_t *text, const int32_t *sa, int32_t n, int levels,
                              uint64_t *key, int32_t *tsa, hipStream_t s);
@@ -52,9 +55,10 @@ hipError_t launch_pack(const uint8_t *reads, const int64_t *offs, const int64_t 
 hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *which, hipStream_t s);
 
 // count = true runs the instrumented variant that fills b.stats.
-hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int block, int grid,
-                               const BatchBuffers &b, const uint32_t *order, int64_t nreads,
-                               void *out, bool count, hipStream_t s);
+// group: 64-read chunks per block of the work split (see the kernel).
+hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int block, int grid, int group,
+                               const BatchBuffers &b, const uint32_t *order, int64_t nreads, void *out,
+                               bool count, hipStream_t s);
 
 hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_t nreads,
                                void *out, bool count, hipStream_t s);

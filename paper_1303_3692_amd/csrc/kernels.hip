@@ -35,12 +35,14 @@ __device__ __forceinline__ int max_i(int a, int b) { return a > b ? a : b; }
 // 64-bit text words each probe compares, and probes answered in LDS.
 struct NoCount {
     __device__ __forceinline__ void global_probe() {}
+    __device__ __forceinline__ void key_probe() {}
     __device__ __forceinline__ void tile_probe() {}
     __device__ __forceinline__ void text_words(uint32_t, uint32_t) {}
 };
 struct Count {
-    uint32_t global = 0, words = 0, tile = 0;
+    uint32_t global = 0, words = 0, tile = 0, keys = 0;
     __device__ __forceinline__ void global_probe() { ++global; }
+    __device__ __forceinline__ void key_probe() { ++global; ++keys; }
     __device__ __forceinline__ void tile_probe() { ++tile; }
     // bases [first, end) of the text were compared
     __device__ __forceinline__ void text_words(uint32_t first, uint32_t end) {
@@ -95,6 +97,22 @@ __device__ __forceinline__ int compare_from(const uint64_t *__restrict__ text, i
     return sign;
 }
 
+// Probe of one row whose first 32 bases (key) and text position p are in
+// hand: when fewer than 32 bases are known to match (h < 32) the key
+// decides unless it ties over all its bases with more to compare; the text
+// is read only from word 1 (or from word h/32 when h >= 32).
+template <int W, class Cnt>
+__device__ __forceinline__ int compare_keyed(const DevIndex &ix, const uint64_t (&q)[W], int plen, int32_t p,
+                                             uint64_t key, int h, int &lcp, Cnt &cnt) {
+    if (h >= 32) return compare_from<W>(ix.text, ix.n, q, plen, p, h >> 5, lcp, cnt);
+    const int lim = min_i(plen, ix.n - p);
+    const uint64_t x = q[0] ^ key;
+    const int mm = (int)(__clzll((long long)x) >> 1);
+    if (x != 0 && mm < lim) { lcp = mm; return q[0] > key ? 1 : -1; }
+    if (lim <= 32) { lcp = lim; return lim == plen ? 0 : 1; }
+    return compare_from<W>(ix.text, ix.n, q, plen, p, 1, lcp, cnt);
+}
+
 __device__ __forceinline__ int midpoint(int L, int R) {
     return L + (int)((uint32_t)(R - L) >> 1);
 }
@@ -111,9 +129,10 @@ __device__ __forceinline__ int bounded_search(const DevIndex &ix, const uint64_t
     while (R > L + 1) {
         const int piv = midpoint(L, R);
         const int32_t p = ix.sa[piv];
+        const uint64_t key = ix.row_key[piv];
         int lcp;
-        cnt.global_probe();
-        const int sign = compare_from<W>(ix.text, ix.n, q, plen, p, min_i(lcpL, lcpR) >> 5, lcp, cnt);
+        cnt.key_probe();
+        const int sign = compare_keyed<W>(ix, q, plen, p, key, min_i(lcpL, lcpR), lcp, cnt);
         const bool go_left = UPPER ? (sign < 0) : (sign <= 0);
         if (go_left) { R = piv; lcpR = lcp; }
         else { L = piv; lcpL = lcp; }
@@ -154,14 +173,9 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
     for (int d = 0; d < levels && st.R > st.L + 1; ++d) {
         const uint64_t key = s_key[node];
         const int32_t p = s_sa[node];
-        const int lim = min_i(plen, ix.n - p);
-        const uint64_t x = q[0] ^ key;
-        const int mm = (int)(__clzll((long long)x) >> 1);
-        int lcp, sign;
+        int lcp;
         cnt.tile_probe();
-        if (x != 0 && mm < lim) { lcp = mm; sign = q[0] > key ? 1 : -1; }
-        else if (lim <= 32) { lcp = lim; sign = (lim == plen) ? 0 : 1; }
-        else sign = compare_from<W>(ix.text, ix.n, q, plen, p, 1, lcp, cnt);
+        const int sign = compare_keyed<W>(ix, q, plen, p, key, min_i(st.lcpL, st.lcpR), lcp, cnt);
         const int piv = midpoint(st.L, st.R);
         lb_update(st, sign, piv, lcp);
         node = 2 * node + (sign <= 0 ? 1 : 2);
@@ -169,9 +183,10 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
     while (st.R > st.L + 1) {
         const int piv = midpoint(st.L, st.R);
         const int32_t p = ix.sa[piv];
+        const uint64_t key = ix.row_key[piv];
         int lcp;
-        cnt.global_probe();
-        const int sign = compare_from<W>(ix.text, ix.n, q, plen, p, min_i(st.lcpL, st.lcpR) >> 5, lcp, cnt);
+        cnt.key_probe();
+        const int sign = compare_keyed<W>(ix, q, plen, p, key, min_i(st.lcpL, st.lcpR), lcp, cnt);
         lb_update(st, sign, piv, lcp);
     }
 }
@@ -204,6 +219,15 @@ __device__ __forceinline__ void load_query(const uint64_t *__restrict__ qw, int 
 }
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// ------------------------------------------------------------------ row keys
+
+// First 32 bases of the suffix at every SA row (zero past the text end).
+__global__ void build_row_keys_kernel(const uint64_t *__restrict__ text, const int32_t *__restrict__ sa, int32_t n,
+                                      uint64_t *__restrict__ key) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) key[r] = text_word(text, (uint32_t)sa[r]);
+}
 
 // ------------------------------------------------------------------ tile
 
@@ -326,7 +350,6 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
     const int64_t r0 = (int64_t)blockIdx.x * kPackBlock;
     const int64_t r1 = r0 + kPackBlock < nreads ? r0 + kPackBlock : nreads;
     const int64_t i = r0 + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *b.counter = 0u;
     if (blockIdx.x == 0 && threadIdx.x < 8) b.stats[threadIdx.x] = 0ull;
     const int64_t span0 = offs[r0];
     const int64_t span1 = ends ? span0 : offs[r1];
@@ -547,18 +570,34 @@ __device__ __forceinline__ void wave_add(unsigned long long *dst, uint32_t v) {
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
 }
 
+// Work split of the persistent kernel, with no global atomics: the sorted
+// reads are cut into chunks of 64 (one per lane of a wave) and the chunks
+// into blocks of `group` chunks.  Workgroup rank r takes blocks r, r + G,
+// r + 2G, ... (G workgroups), so every workgroup sees the same mix of read
+// lengths, and all workgroups advance through one window of the sorted
+// order together.  The waves of a workgroup share its blocks through a
+// counter in LDS.  Workgroups are dispatched to the eight XCDs round-robin
+// by id, so ranks are assigned XCD by XCD: neighbouring blocks (reads that
+// visit the same index rows) run in one XCD's L2.
+__device__ __forceinline__ int64_t workgroup_rank() {
+    const int64_t G = gridDim.x, w = blockIdx.x;
+    return (G % 8 == 0) ? (w % 8) * (G / 8) + w / 8 : w;
+}
+
 // Persistent kernel: each workgroup stages the top `levels` tree levels in
-// LDS once, then its waves take 64 consecutive (prefix-sorted) reads at a
-// time from a global counter until none are left.  Each chunk runs the
-// instantiation for the longest read it holds.
+// LDS once, then its waves take 64-read chunks of prefix-sorted reads until
+// the workgroup's blocks are done.  Each chunk runs the instantiation for
+// the longest read it holds.
 template <int BLOCK, bool COUNT>
-__global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, BatchBuffers b,
+__global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, int group, BatchBuffers b,
                                                              const uint32_t *__restrict__ order,
                                                              int64_t nreads, int4 *__restrict__ out) {
     extern __shared__ uint64_t smem[];
+    __shared__ unsigned s_next;
     const int nodes = (1 << levels) - 1;
     uint64_t *s_key = smem;
     int32_t *s_sa = reinterpret_cast<int32_t *>(smem + nodes);
+    if (threadIdx.x == 0) s_next = 0u;
     for (int i = threadIdx.x; i < nodes; i += BLOCK) {
         s_key[i] = ix.tile_key[i];
         s_sa[i] = ix.tile_sa[i];
@@ -569,12 +608,14 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
     uint32_t nsearched = 0, nqwords = 0;
     const int lane = threadIdx.x & 63;
     const int64_t nchunks = (nreads + 63) >> 6;
+    const int64_t G = gridDim.x, rank = workgroup_rank();
     for (;;) {
         unsigned c = 0;
-        if (lane == 0) c = atomicAdd(b.counter, 1u);
+        if (lane == 0) c = atomicAdd(&s_next, 1u);
         c = __shfl(c, 0, 64);
-        if ((int64_t)c >= nchunks) break;
-        const int64_t j = ((int64_t)c << 6) + lane;
+        const int64_t chunk = ((int64_t)(c / group) * G + rank) * group + (c % group);
+        if (chunk >= nchunks) break;  // every later chunk of this workgroup lies further on
+        const int64_t j = (chunk << 6) + lane;
         const bool active = j < nreads;
         const int rid = active ? (order ? (int)order[j] : (int)j) : 0;
         const int m = active ? b.qlen[rid] : 0;
@@ -604,6 +645,7 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         wave_add(&b.stats[2], cnt.tile);
         wave_add(&b.stats[3], nsearched);
         wave_add(&b.stats[4], nqwords);
+        wave_add(&b.stats[5], cnt.keys);
     }
 }
 
@@ -670,7 +712,7 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
 }
 
 template <int BLOCK, bool COUNT>
-hipError_t launch_tuned_block(const DevIndex &ix, int levels, int grid, const BatchBuffers &b,
+hipError_t launch_tuned_block(const DevIndex &ix, int levels, int group, int grid, const BatchBuffers &b,
                               const uint32_t *order, int64_t nreads, int4 *out, hipStream_t s) {
     const size_t lds = tile_lds_bytes(levels);
     static std::atomic<bool> attr_set{false};
@@ -681,12 +723,18 @@ hipError_t launch_tuned_block(const DevIndex &ix, int levels, int grid, const Ba
         if (e != hipSuccess) return e;
         attr_set.store(true);
     }
-    hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, b, order,
-                       nreads, out);
+    hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, group, b,
+                       order, nreads, out);
     return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t launch_build_row_keys(const uint64_t *text, const int32_t *sa, int32_t n, uint64_t *key, hipStream_t s) {
+    const int64_t blocks = ((int64_t)n + 255) / 256;
+    hipLaunchKernelGGL(build_row_keys_kernel, dim3((unsigned)blocks), dim3(256), 0, s, text, sa, n, key);
+    return hipGetLastError();
+}
 
 hipError_t launch_build_tile(const uint64_t *text, const int32_t *sa, int32_t n, int levels, uint64_t *key,
                              int32_t *tsa, hipStream_t s) {
@@ -724,15 +772,16 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *whi
     return hipSuccess;
 }
 
-hipError_t launch_search_tuned(const DevIndex &ix, int levels, int block, int grid, const BatchBuffers &b,
+hipError_t launch_search_tuned(const DevIndex &ix, int levels, int block, int grid, int group, const BatchBuffers &b,
                                const uint32_t *order, int64_t nreads, void *out, bool count, hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
-    if (count)  // counts do not depend on the workgroup shape
-        return launch_tuned_block<256, true>(ix, levels, grid * (block / 256), b, order, nreads, o, s);
+    if (group < 1) return hipErrorInvalidValue;
+    if (count)  // counts do not depend on the workgroup shape or the work split
+        return launch_tuned_block<256, true>(ix, levels, group, grid * (block / 256), b, order, nreads, o, s);
     switch (block) {
-        case 256: return launch_tuned_block<256, false>(ix, levels, grid, b, order, nreads, o, s);
-        case 512: return launch_tuned_block<512, false>(ix, levels, grid, b, order, nreads, o, s);
-        case 1024: return launch_tuned_block<1024, false>(ix, levels, grid, b, order, nreads, o, s);
+        case 256: return launch_tuned_block<256, false>(ix, levels, group, grid, b, order, nreads, o, s);
+        case 512: return launch_tuned_block<512, false>(ix, levels, group, grid, b, order, nreads, o, s);
+        case 1024: return launch_tuned_block<1024, false>(ix, levels, group, grid, b, order, nreads, o, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -13,6 +14,10 @@
 #include "device_state.h"
 
 using namespace samatch;
+
+#ifndef SAMATCH_BUILD_ID
+#define SAMATCH_BUILD_ID "dev"
+#endif
 
 namespace {
 
@@ -33,7 +38,7 @@ int length_histogram(const int64_t *d_offs, int64_t nreads, hipStream_t s, std::
 
 std::string cache_key(const sa_dindex *d, const std::vector<int64_t> &hist, int64_t nreads) {
     std::ostringstream k;
-    k << d->arch << "|n=" << d->n << "|cu=" << d->cu_count << "|h=";
+    k << SAMATCH_BUILD_ID << "|" << d->arch << "|n=" << d->n << "|cu=" << d->cu_count << "|h=";
     // length classes present with their share in percent, so that batches of
     // the same shape share a tuning
     for (size_t i = 0; i < hist.size(); i++) {
@@ -46,7 +51,8 @@ std::string cache_key(const sa_dindex *d, const std::vector<int64_t> &hist, int6
 std::string cfg_json(const sa_match_cfg &c) {
     std::ostringstream o;
     o << "\"tile_levels\":" << c.tile_levels << ",\"block\":" << c.block << ",\"blocks_per_cu\":" << c.blocks_per_cu
-      << ",\"sort\":" << c.sort << ",\"nbuckets\":" << c.nbuckets << ",\"bucket_edge\":[";
+      << ",\"group\":" << c.group << ",\"sort\":" << c.sort
+      << ",\"nbuckets\":" << c.nbuckets << ",\"bucket_edge\":[";
     for (int i = 0; i < c.nbuckets; i++) o << (i ? "," : "") << c.bucket_edge[i];
     o << "]";
     return o.str();
@@ -72,6 +78,7 @@ bool parse_cached(const std::string &path, const std::string &key, sa_match_cfg 
         c.tile_levels = json_int(line, "tile_levels", 12);
         c.block = json_int(line, "block", 256);
         c.blocks_per_cu = json_int(line, "blocks_per_cu", 8);
+        c.group = json_int(line, "group", 4);
         c.sort = json_int(line, "sort", 1);
         c.nbuckets = std::max(1, std::min(8, json_int(line, "nbuckets", 1)));
         const size_t p = line.find("\"bucket_edge\":[");
@@ -168,6 +175,9 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
             best_rep = std::min(best_rep, t);
         }
         ms = best_rep;
+        if (std::getenv("SAMATCH_TUNE_LOG"))
+            std::fprintf(stderr, "tune: levels=%d block=%d per_cu=%d group=%d buckets=%d -> %.4f ms\n", c.tile_levels,
+                         c.block, c.blocks_per_cu, c.group, c.nbuckets, ms);
         return SA_OK;
     };
     // stage 1: tile depth x workgroup shape with one bucket
@@ -185,6 +195,7 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
                 c.nbuckets = 1;
                 c.bucket_edge[0] = SA_MAX_READ;
                 c.sort = 1;
+                c.group = 4;
                 double ms = 0;
                 rc = time_cfg(c, ms);
                 if (rc == SA_EINVAL) continue;
@@ -192,6 +203,16 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
                 if (ms < top_ms) { top_ms = ms; top = c; }
             }
         }
+    }
+    // stage 1b: block size of the work split with the best shape
+    for (int group : {1, 2, 8, 16}) {
+        sa_match_cfg c = top;
+        c.group = group;
+        double ms = 0;
+        rc = time_cfg(c, ms);
+        if (rc == SA_EINVAL) continue;
+        if (rc) goto done;
+        if (ms < top_ms) { top_ms = ms; top = c; }
     }
     // stage 2: bucket layouts with the best shape
     for (const auto &edges : bucket_layouts(hist)) {
