@@ -154,7 +154,10 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
     const bool prof = c.profile != 0;
     hipError_t e = hipSuccess;
     if (prof && (e = hipEventRecord(ws->ev[0], s)) != hipSuccess) return hip_fail(e, "event record");
-    e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bucket_table(c), s);
+    // the plain kernel searches packed words; the tuned kernel converts each
+    // read itself and needs only the sort keys and lengths
+    if (c.kernel == SA_KERNEL_PLAIN) e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bucket_table(c), s);
+    else e = launch_keys(d_reads, d_offs, d_ends, nreads, ws->b, bucket_table(c), s);
     if (e != hipSuccess) return hip_fail(e, "pack launch");
     if (prof && (e = hipEventRecord(ws->ev[1], s)) != hipSuccess) return hip_fail(e, "event record");
     const uint32_t *order = nullptr;
@@ -171,8 +174,8 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         if (e != hipSuccess) return hip_fail(e, "plain search launch");
     } else {
         const int grid = std::max(1, d->cu_count * c.blocks_per_cu);
-        e = launch_search_tuned(d->view, c.tile_levels, c.block, grid, c.group, ws->b, order, nreads, d_out,
-                                c.count != 0, s);
+        e = launch_search_tuned(d->view, c.tile_levels, c.block, grid, c.group, ws->b, d_reads, d_offs, order, nreads,
+                                d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
     if (prof && (e = hipEventRecord(ws->ev[3], s)) != hipSuccess) return hip_fail(e, "event record");

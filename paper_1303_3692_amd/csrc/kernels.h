@@ -55,10 +55,15 @@ hipError_t launch_pack(const uint8_t *reads, const int64_t *offs, const int64_t 
 hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *which, hipStream_t s);
 
 // count = true runs the instrumented variant that fills b.stats.
-// group: 64-read chunks per block of the work split (see the kernel).
+// Sort keys and lengths only (the tuned search converts reads itself).
+hipError_t launch_keys(const uint8_t *reads, const int64_t *offs, const int64_t *ends, int64_t nreads,
+                       const BatchBuffers &b, const BucketTable &bt, hipStream_t s);
+
+// group: 64-read chunks per block of the work split (see the kernel).  The
+// search reads the ASCII bytes of read i at reads + offs[i].
 hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int block, int grid, int group,
-                               const BatchBuffers &b, const uint32_t *order, int64_t nreads, void *out,
-                               bool count, hipStream_t s);
+                               const BatchBuffers &b, const uint8_t *reads, const int64_t *offs,
+                               const uint32_t *order, int64_t nreads, void *out, bool count, hipStream_t s);
 
 hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_t nreads,
                                void *out, bool count, hipStream_t s);

@@ -410,6 +410,52 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
     pack_finish(b, bt, i, m, mv, w0);
 }
 
+// Sort keys only (the tuned path converts each read inside the search
+// kernel): length, and key = (length bucket, first 12 bases).  Reads the
+// aligned dwords that hold the first bases; an aligned dword holding a byte
+// of the read never crosses a page.
+__global__ __launch_bounds__(256) void key_kernel(const uint8_t *__restrict__ reads, const int64_t *__restrict__ offs,
+                                                  const int64_t *__restrict__ ends, int64_t nreads, BatchBuffers b,
+                                                  BucketTable bt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 8) b.stats[i] = 0ull;
+    if (i >= nreads) return;
+    const int64_t a = offs[i], e = ends ? ends[i] : offs[i + 1];
+    const int64_t m64 = e - a;
+    b.val[0][i] = (uint32_t)i;
+    if (m64 < 0 || m64 > kMaxRead) {
+        b.qlen[i] = -1;
+        b.key[0][i] = 0;
+        return;
+    }
+    const int m = (int)m64;
+    const int take = m < 12 ? m : 12;
+    const uintptr_t start = (uintptr_t)(reads + a);
+    const uintptr_t stop = start + (uintptr_t)take;
+    const uintptr_t abase = start & ~(uintptr_t)3;
+    const uint32_t sh = (uint32_t)(start & 3u) * 8u;
+    uint32_t prefix = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int rem = take - 4 * j;
+        uint32_t b8 = 0;
+        if (rem > 0) {
+            const uintptr_t p0 = abase + 4u * j, p1 = p0 + 4u;
+            const uint32_t lo = *reinterpret_cast<const uint32_t *>(p0);
+            const uint32_t hi = (sh && p1 < stop) ? *reinterpret_cast<const uint32_t *>(p1) : 0u;
+            const uint32_t dw = sh ? (lo >> sh) | (hi << (32u - sh)) : lo;
+            uint32_t bad;
+            b8 = pack4(dw, rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u), bad);
+        }
+        prefix = (prefix << 8) | b8;
+    }
+    b.qlen[i] = m;
+    int bucket = bt.count - 1;
+    for (int j = 0; j < bt.count; ++j)
+        if (m <= bt.edge[j]) { bucket = j; break; }
+    b.key[0][i] = ((uint32_t)bucket << 24) | prefix;
+}
+
 // ------------------------------------------------------------------ radix sort
 
 // Per-block digit counts, digit-major: hist[d * nblocks + block].
@@ -494,10 +540,27 @@ __global__ __launch_bounds__(256) void sort_scan_kernel(uint32_t *hist, int nblo
     }
 }
 
-// Stable scatter: keys of a block are taken in input order, 256 per round;
-// inside a wave, lanes with the same digit are found with eight ballots
-// (one per digit bit) and ranked by their lane order; waves are ordered by
-// per-round digit counts in LDS.
+// Stable scatter of one tile of kSortTile keys.  Each wave owns a contiguous
+// quarter of the tile, taken 64 keys per round in input order; lanes with
+// the same digit are found with eight ballots (one per digit bit) and
+// ranked by lane order.  Sweep 1 counts digits per wave; a block scan turns
+// the counts into each wave's first slot per digit inside the tile; sweep 2
+// places every key in an LDS copy of the tile, ordered by digit; the tile
+// is then written out so that consecutive threads store consecutive
+// addresses of one digit's run.
+__device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, bool valid) {
+    uint64_t peers = wave_ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const bool set = (d >> bit) & 1u;
+        const uint64_t bal = wave_ballot(set);
+        peers &= set ? bal : ~bal;
+    }
+    return peers;
+}
+
+static_assert(kSortBlock == 256, "the scatter kernel's digit loops assume one digit per thread");
+
 __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(const uint32_t *__restrict__ kin,
                                                                   const uint32_t *__restrict__ vin,
                                                                   uint32_t *__restrict__ kout,
@@ -505,62 +568,146 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(const uint32_t
                                                                   int shift, const uint32_t *__restrict__ hist,
                                                                   int nblocks) {
     constexpr int kWaves = kSortBlock / 64;
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t wcount[kWaves][256];
+    constexpr int kPerWave = kSortTile / kWaves;
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t wslot[kWaves][256];  // per wave: count, then next slot per digit
+    __shared__ uint32_t loc[256];            // first slot of each digit in the tile
+    __shared__ uint32_t gbase[256];          // global position of the tile's first key of each digit
+    __shared__ uint32_t scan_tmp[kWaves];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int d = t; d < 256; d += kSortBlock) {
-        base[d] = hist[(size_t)d * nblocks + blockIdx.x];
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) wcount[w][d] = 0;
-    }
+    for (int i = t; i < kWaves * 256; i += kSortBlock) (&wslot[0][0])[i] = 0;
+    for (int d = t; d < 256; d += kSortBlock) gbase[d] = hist[(size_t)d * nblocks + blockIdx.x];
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t blk = (int64_t)blockIdx.x * kSortTile;
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t i = blk + r * kSortBlock + t;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * kPerWave;
+    // sweep 1: digit counts per wave
+#pragma unroll 1
+    for (int r = 0; r < kPerWave / 64; ++r) {
+        const int64_t i = base + r * 64 + lane;
         const bool valid = i < n;
         const uint32_t key = valid ? kin[i] : 0u;
         const uint32_t d = (key >> shift) & 255u;
-        uint64_t peers = wave_ballot(valid);
+        const uint64_t peers = same_digit_lanes(d, valid);
+        if (valid && __popcll(peers & lt_mask) == 0) wslot[wave][d] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // block scan over digits of the per-digit tile totals; then each wave's
+    // first slot for each digit
+    for (int d = t; d < 256; d += kSortBlock) {
+        uint32_t tot = 0;
 #pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const bool set = (d >> bit) & 1u;
-            const uint64_t bal = wave_ballot(set);
-            peers &= set ? bal : ~bal;
+        for (int w = 0; w < kWaves; ++w) tot += wslot[w][d];
+        uint32_t excl;
+        block_exclusive_scan(tot, excl, scan_tmp);
+        loc[d] = excl;
+        uint32_t run = excl;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = wslot[w][d];
+            wslot[w][d] = run;
+            run += c;
         }
+    }
+    __syncthreads();
+    // sweep 2: place keys in the LDS tile, stable within each digit (the
+    // tile's keys are read again; they are still in cache)
+#pragma unroll 1
+    for (int r = 0; r < kPerWave / 64; ++r) {
+        const int64_t i = base + r * 64 + lane;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        const uint64_t peers = same_digit_lanes(d, valid);
         const int rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0) wcount[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
         if (valid) {
-            uint32_t pos = base[d] + (uint32_t)rank;
-            for (int w = 0; w < wave; ++w) pos += wcount[w][d];
-            kout[pos] = key;
-            vout[pos] = vin[i];
+            const uint32_t pos = wslot[wave][d] + (uint32_t)rank;
+            s_key[pos] = key;
+            s_val[pos] = vin[i];
         }
-        __syncthreads();
-        for (int dd = t; dd < 256; dd += kSortBlock) {
-            uint32_t s = 0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) { s += wcount[w][dd]; wcount[w][dd] = 0; }
-            base[dd] += s;
-        }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) wslot[wave][d] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // write out: runs of one digit go to consecutive addresses
+    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    const int count = (int)((n - tile0) < kSortTile ? (n - tile0) : kSortTile);
+    for (int p = t; p < count; p += kSortBlock) {
+        const uint32_t k = s_key[p];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t g = gbase[d] + (uint32_t)p - loc[d];
+        kout[g] = k;
+        vout[g] = s_val[p];
     }
 }
 
 // ------------------------------------------------------------------ search
 
+// Convert read bytes [a, a+m) to W packed words in registers and find the
+// length of its ACGT prefix.  The bytes come in aligned 16-byte chunks, two
+// new chunks per 32 bases; only chunks that hold a byte of the read are
+// fetched (an aligned chunk never crosses a page), others read as 0.
+__device__ __forceinline__ uint4 read_chunk(uintptr_t p, uintptr_t stop) {
+    return p < stop ? *reinterpret_cast<const uint4 *>(p) : make_uint4(0u, 0u, 0u, 0u);
+}
+
+__device__ __forceinline__ uint32_t pick4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t i) {
+    return i == 0 ? a : (i == 1 ? b : (i == 2 ? c : d));
+}
+
+template <int W>
+__device__ __forceinline__ void convert_read(const uint8_t *__restrict__ reads, int64_t a, int m, uint64_t (&q)[W],
+                                             int &mv) {
+    const uintptr_t start = (uintptr_t)(reads + a);
+    const uintptr_t stop = start + (uintptr_t)m;
+    const uintptr_t base = start & ~(uintptr_t)15;
+    const uint32_t dsh = (uint32_t)(start - base) >> 2;  // dword offset of the first byte, 0..3
+    const uint32_t bsh = (uint32_t)(start & 3u);         // byte offset inside that dword
+    mv = m;
+    uint4 c0 = read_chunk(base, stop);
+#pragma unroll
+    for (int k = 0; k < W; ++k) q[k] = 0;
+    // one word at a time (rolled), so that only one word's chunks are live
+#pragma unroll 1
+    for (int k = 0; k < W; ++k) {
+        const uint4 c1 = read_chunk(base + 32u * k + 16u, stop);
+        const uint4 c2 = read_chunk(base + 32u * k + 32u, stop);
+        const uint32_t d[12] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2.x, c2.y, c2.z, c2.w};
+        uint32_t sel[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) sel[j] = pick4(d[j], d[j + 1], d[j + 2], d[j + 3], dsh);
+        uint64_t word = 0;
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const int rem = m - 32 * k - 4 * jj;
+            // bytes 32k+4jj .. +3 of the read
+            const uint32_t dw = __builtin_amdgcn_alignbyte(sel[jj + 1], sel[jj], bsh);
+            const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : (rem > 0 ? ((1u << (8 * rem)) - 1u) : 0u);
+            uint32_t bad;
+            const uint32_t b8 = pack4(dw, keep, bad);
+            if (bad && mv == m) mv = 32 * k + 4 * jj + (__builtin_ctz(bad) >> 3);
+            word |= (uint64_t)b8 << (56 - 8 * jj);
+        }
+#pragma unroll
+        for (int t = 0; t < W; ++t) q[t] = (t == k) ? word : q[t];
+        c0 = c2;
+    }
+}
+
 template <int W, class Cnt>
 __device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa,
-                                          int levels, const BatchBuffers &b, int rid, int4 *out, Cnt &cnt) {
+                                          int levels, const BatchBuffers &b, const uint8_t *__restrict__ reads,
+                                          const int64_t *__restrict__ offs, int rid, int4 *out, Cnt &cnt) {
     const int m = b.qlen[rid];
     if (m < 0) {
         out[rid] = make_int4(0, 0, 0, (int)kHitTooLong);
         return;
     }
     uint64_t q[W];
-    load_query<W>(b.qw, rid, q);
-    out[rid] = match_read<W>(ix, s_key, s_sa, levels, q, m, b.qmv[rid], cnt);
+    int mv;
+    convert_read<W>(reads, offs[rid], m, q, mv);
+    out[rid] = match_read<W>(ix, s_key, s_sa, levels, q, m, mv, cnt);
 }
 
 // Sum a per-lane count over the wave and add it to a global counter.
@@ -590,6 +737,8 @@ __device__ __forceinline__ int64_t workgroup_rank() {
 // the longest read it holds.
 template <int BLOCK, bool COUNT>
 __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, int group, BatchBuffers b,
+                                                             const uint8_t *__restrict__ reads,
+                                                             const int64_t *__restrict__ offs,
                                                              const uint32_t *__restrict__ order,
                                                              int64_t nreads, int4 *__restrict__ out) {
     extern __shared__ uint64_t smem[];
@@ -627,16 +776,16 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         if (!active) continue;
         if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
         switch (wc) {
-            case 1: tuned_one<1>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
-            case 2: tuned_one<2>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
-            case 3: tuned_one<3>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
-            case 4: tuned_one<4>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
-            case 5: tuned_one<5>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
-            case 6: tuned_one<6>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
-            case 7: tuned_one<7>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
-            case 8: tuned_one<8>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
-            case 9: tuned_one<9>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
-            default: tuned_one<10>(ix, s_key, s_sa, levels, b, rid, out, cnt); break;
+            case 1: tuned_one<1>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            case 2: tuned_one<2>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            case 3: tuned_one<3>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            case 4: tuned_one<4>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            case 5: tuned_one<5>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            case 6: tuned_one<6>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            case 7: tuned_one<7>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            case 8: tuned_one<8>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            case 9: tuned_one<9>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            default: tuned_one<10>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
         }
     }
     if constexpr (COUNT) {
@@ -713,7 +862,8 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
 
 template <int BLOCK, bool COUNT>
 hipError_t launch_tuned_block(const DevIndex &ix, int levels, int group, int grid, const BatchBuffers &b,
-                              const uint32_t *order, int64_t nreads, int4 *out, hipStream_t s) {
+                              const uint8_t *reads, const int64_t *offs, const uint32_t *order, int64_t nreads,
+                              int4 *out, hipStream_t s) {
     const size_t lds = tile_lds_bytes(levels);
     static std::atomic<bool> attr_set{false};
     if (!attr_set.load()) {
@@ -724,7 +874,7 @@ hipError_t launch_tuned_block(const DevIndex &ix, int levels, int group, int gri
         attr_set.store(true);
     }
     hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, group, b,
-                       order, nreads, out);
+                       reads, offs, order, nreads, out);
     return hipGetLastError();
 }
 
@@ -773,17 +923,27 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *whi
 }
 
 hipError_t launch_search_tuned(const DevIndex &ix, int levels, int block, int grid, int group, const BatchBuffers &b,
-                               const uint32_t *order, int64_t nreads, void *out, bool count, hipStream_t s) {
+                               const uint8_t *reads, const int64_t *offs, const uint32_t *order, int64_t nreads,
+                               void *out, bool count, hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
     if (group < 1) return hipErrorInvalidValue;
     if (count)  // counts do not depend on the workgroup shape or the work split
-        return launch_tuned_block<256, true>(ix, levels, group, grid * (block / 256), b, order, nreads, o, s);
+        return launch_tuned_block<256, true>(ix, levels, group, grid * (block / 256), b, reads, offs, order, nreads,
+                                             o, s);
     switch (block) {
-        case 256: return launch_tuned_block<256, false>(ix, levels, group, grid, b, order, nreads, o, s);
-        case 512: return launch_tuned_block<512, false>(ix, levels, group, grid, b, order, nreads, o, s);
-        case 1024: return launch_tuned_block<1024, false>(ix, levels, group, grid, b, order, nreads, o, s);
+        case 256: return launch_tuned_block<256, false>(ix, levels, group, grid, b, reads, offs, order, nreads, o, s);
+        case 512: return launch_tuned_block<512, false>(ix, levels, group, grid, b, reads, offs, order, nreads, o, s);
+        case 1024: return launch_tuned_block<1024, false>(ix, levels, group, grid, b, reads, offs, order, nreads, o, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_keys(const uint8_t *reads, const int64_t *offs, const int64_t *ends, int64_t nreads,
+                       const BatchBuffers &b, const BucketTable &bt, hipStream_t s) {
+    const int64_t blocks = (nreads + 255) / 256;
+    hipLaunchKernelGGL(key_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, reads, offs, ends,
+                       nreads, b, bt);
+    return hipGetLastError();
 }
 
 hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_t nreads, void *out, bool count,
