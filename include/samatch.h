@@ -97,9 +97,11 @@ void sa_free(sa_index *ix);                           /* NULL is a no-op        
 /* Copy the index to device `device` and keep it resident: the packed text
  * (with zero padding words after the end), the int32 SA, the first 32 bases
  * of the suffix at every SA row (8 bytes per row, so that most probes of the
- * tuned kernel never touch the text), and the table of the top levels of
- * the implicit binary-search tree that the tuned kernel stages in LDS (the
- * tile of Section IV).  The host index may be freed
+ * tuned kernel never touch the text), the table of the top levels of the
+ * implicit binary-search tree that the tuned kernel stages in LDS (the tile
+ * of Section IV), and, for n >= 4096, a prefix table: for every string v of
+ * k = round(log4 n) bases (4 <= k <= 14), the first SA row whose suffix is
+ * not below v (4^k + 1 int32 entries).  The host index may be freed
  * afterwards.  Released with sa_dfree (NULL is a no-op). */
 int sa_upload(const sa_index *ix, int device, sa_dindex **out);
 void sa_dfree(sa_dindex *d);
@@ -128,6 +130,8 @@ typedef struct {
                             results are the same)                                */
     int group;           /* tuned: 64-read chunks per block of the work split
                             (1..64): workgroup rank r takes blocks r, r+G, ... */
+    int prefix_table;    /* tuned: 1 = start each search from the prefix table
+                            (when the index has one), 0 = from the LDS tile     */
 } sa_match_cfg;
 
 /* Fill cfg with the index's current defaults. */
@@ -159,9 +163,9 @@ int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]);
  * c[0] global-memory probes (one SA entry each), c[1] 64-bit text words
  * those probes compare, c[2] probes answered from the LDS tile, c[3] reads
  * searched, c[4] packed query words loaded, c[5] probes that also loaded
- * the 8-byte row key (first 32 bases of the row's suffix).  Waits for that
- * batch. */
-int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[6]);
+ * the 8-byte row key (first 32 bases of the row's suffix), c[6] prefix-table
+ * lookups (two adjacent 4-byte entries each).  Waits for that batch. */
+int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[7]);
 
 /* Autotuner: time candidate configurations (tile depth, workgroups per CU,
  * block size, bucket edges) on the given device batch, keep the fastest as

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
+#include <vector>
 #include <cstring>
 #include <mutex>
 
@@ -174,8 +176,8 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         if (e != hipSuccess) return hip_fail(e, "plain search launch");
     } else {
         const int grid = std::max(1, d->cu_count * c.blocks_per_cu);
-        e = launch_search_tuned(d->view, c.tile_levels, c.block, grid, c.group, ws->b, d_reads, d_offs, order, nreads,
-                                d_out, c.count != 0, s);
+        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, c.group, ws->b, d_reads, d_offs,
+                                order, nreads, d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
     if (prof && (e = hipEventRecord(ws->ev[3], s)) != hipSuccess) return hip_fail(e, "event record");
@@ -223,7 +225,48 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
                                nullptr)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess)
         return hip_fail(e, "tile build");
-    d->view = DevIndex{d->d_text, d->d_sa, d->d_tile_key, d->d_tile_sa, d->d_row_key, (int32_t)ix->n};
+    DevIndex v{};
+    v.text = d->d_text;
+    v.sa = d->d_sa;
+    v.tile_key = d->d_tile_key;
+    v.tile_sa = d->d_tile_sa;
+    v.row_key = d->d_row_key;
+    v.n = (int32_t)ix->n;
+    // rows of the shortest suffixes (the last kShort text positions)
+    {
+        std::vector<std::pair<int32_t, int32_t>> rows;  // (row, length)
+        const int64_t cut = ix->n - kShort;
+        for (int64_t r = 0; r < ix->n; r++)
+            if (ix->sa[(size_t)r] >= cut) rows.emplace_back((int32_t)r, (int32_t)(ix->n - ix->sa[(size_t)r]));
+        std::sort(rows.begin(), rows.end());
+        v.nshort = (int32_t)rows.size();
+        for (size_t i = 0; i < rows.size(); i++) {
+            v.short_row[i] = rows[i].first;
+            v.short_len[i] = rows[i].second;
+            // first 32 bases of the suffix, zero past the end
+            const int64_t p = ix->n - rows[i].second;
+            const uint64_t lo = ix->packed[(size_t)(p >> 5)], hi = ix->packed[(size_t)(p >> 5) + 1];
+            const unsigned sh = (unsigned)(p & 31) * 2u;
+            v.short_key[i] = sh ? (lo << sh) | (hi >> (64u - sh)) : lo;
+        }
+    }
+    // prefix table over k = log4(n) rounded, at most kMaxPrefixBases bases
+    int k = 0;
+    if (ix->n >= 4096) {
+        k = (int)std::lround(std::log2((double)ix->n) / 2.0);
+        k = std::max(4, std::min(kMaxPrefixBases, k));
+    }
+    if (k > 0) {
+        const size_t entries = ((size_t)1 << (2 * k)) + 1;
+        if ((e = hipMalloc((void **)&d->d_ptab, entries * sizeof(uint32_t))) != hipSuccess)
+            return hip_fail(e, "prefix table allocation");
+        v.ptab = d->d_ptab;
+        v.ptab_k = k;
+        if ((e = launch_build_prefix_table(v, k, d->d_ptab, nullptr)) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess)
+            return hip_fail(e, "prefix table build");
+    }
+    d->view = v;
     sa_match_cfg &c = d->defaults;
     std::memset(&c, 0, sizeof c);
     c.kernel = SA_KERNEL_TUNED;
@@ -235,6 +278,7 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
     c.sort = 1;
     c.use_graph = 0;
     c.group = 4;
+    c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
     *out = d.release();
     return SA_OK;
 }
@@ -242,7 +286,8 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
 sa_dindex::~sa_dindex() {
     DeviceGuard g(device);
     ws.clear();
-    for (void *p : {(void *)d_text, (void *)d_sa, (void *)d_tile_key, (void *)d_tile_sa, (void *)d_row_key})
+    for (void *p : {(void *)d_text, (void *)d_sa, (void *)d_tile_key, (void *)d_tile_sa, (void *)d_row_key,
+                    (void *)d_ptab})
         if (p) (void)hipFree(p);
 }
 
@@ -340,7 +385,7 @@ extern "C" int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]
     return SA_OK;
 }
 
-extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[6]) {
+extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[7]) {
     clear_error();
     if (!d || !c) return fail(SA_EINVAL, "NULL argument");
     DeviceGuard g(d->device);
@@ -352,6 +397,6 @@ extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[6
     hipError_t e = hipMemcpyAsync(h, ws->b.stats, sizeof h, hipMemcpyDeviceToHost, static_cast<hipStream_t>(hip_stream));
     if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "counter download");
-    for (int i = 0; i < 6; i++) c[i] = (int64_t)h[i];
+    for (int i = 0; i < 7; i++) c[i] = (int64_t)h[i];
     return SA_OK;
 }

@@ -65,6 +65,7 @@ struct sa_dindex {
     uint64_t *d_tile_key = nullptr;
     int32_t *d_tile_sa = nullptr;
     uint64_t *d_row_key = nullptr;
+    uint32_t *d_ptab = nullptr;
     int tile_levels = 0;  // levels stored (the kernel may use fewer)
     samatch::DevIndex view{};
     sa_match_cfg defaults{};

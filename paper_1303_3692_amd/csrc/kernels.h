@@ -19,8 +19,18 @@ struct DevIndex {
     const uint64_t *tile_key;  // first 32 bases of the pivot suffix of each tree node
     const int32_t *tile_sa;    // text position of each tree node's pivot suffix
     const uint64_t *row_key;   // first 32 bases of the suffix at each SA row
+    const uint32_t *ptab;      // prefix table, 4^ptab_k + 1 entries (NULL when ptab_k == 0)
     int32_t n;
+    int32_t ptab_k;            // bases indexed by the prefix table (0: no table)
+    // the rows of the kShort shortest suffixes (lengths 1..kShort), ascending
+    // by row, with their lengths and first bases (zero past the text end)
+    int32_t nshort;
+    int32_t short_row[15];
+    int32_t short_len[15];
+    uint64_t short_key[15];
 };
+constexpr int kShort = 15;
+constexpr int kMaxPrefixBases = 14;
 
 struct BucketTable {
     int count;     // 1..8
@@ -42,6 +52,9 @@ struct BatchBuffers {
 hipError_t launch_build_row_keys(const uint64_t *text, const int32_t *sa, int32_t n, uint64_t *key,
                                  hipStream_t s);
 
+// T[v] = first SA row whose suffix is not below the k-base string v.
+hipError_t launch_build_prefix_table(const DevIndex &ix, int k, uint32_t *tab, hipStream_t s);
+
 hipError_t launch_build_tile(const uint64_t *text, const int32_t *sa, int32_t n, int levels,
                              uint64_t *key, int32_t *tsa, hipStream_t s);
 
@@ -61,8 +74,9 @@ hipError_t launch_keys(const uint8_t *reads, const int64_t *offs, const int64_t 
 
 // group: 64-read chunks per block of the work split (see the kernel).  The
 // search reads the ASCII bytes of read i at reads + offs[i].
-hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int block, int grid, int group,
-                               const BatchBuffers &b, const uint8_t *reads, const int64_t *offs,
+// use_table: start LB searches from the prefix table (when the index has one).
+hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int use_table, int block, int grid,
+                               int group, const BatchBuffers &b, const uint8_t *reads, const int64_t *offs,
                                const uint32_t *order, int64_t nreads, void *out, bool count, hipStream_t s);
 
 hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_t nreads,

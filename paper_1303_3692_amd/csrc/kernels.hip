@@ -34,13 +34,15 @@ __device__ __forceinline__ int max_i(int a, int b) { return a > b ? a : b; }
 // the instrumented variant counts global probes (one SA entry each), the
 // 64-bit text words each probe compares, and probes answered in LDS.
 struct NoCount {
+    __device__ __forceinline__ void table_probe() {}
     __device__ __forceinline__ void global_probe() {}
     __device__ __forceinline__ void key_probe() {}
     __device__ __forceinline__ void tile_probe() {}
     __device__ __forceinline__ void text_words(uint32_t, uint32_t) {}
 };
 struct Count {
-    uint32_t global = 0, words = 0, tile = 0, keys = 0;
+    uint32_t global = 0, words = 0, tile = 0, keys = 0, table = 0;
+    __device__ __forceinline__ void table_probe() { ++table; }
     __device__ __forceinline__ void global_probe() { ++global; }
     __device__ __forceinline__ void key_probe() { ++global; ++keys; }
     __device__ __forceinline__ void tile_probe() { ++tile; }
@@ -191,21 +193,126 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
     }
 }
 
+// ---- prefix table
+// The table T[v] (v a k-base string) is the first SA row whose suffix is not
+// below v.  For a query P with at least k leading ACGT bases and first k
+// bases v, every row before T[v] is below P and every row from T[v+1] on
+// is above it, so the LB search of P runs inside (T[v] - 1, T[v+1]).  Rows
+// in that bracket start with v, except suffixes shorter than k (only the
+// last k - 1 text positions), whose rows are passed in the index view.
+
+// Short suffix (length < k) whose row lies in [lo, hi), if any.
+__device__ __forceinline__ bool short_rows_in(const DevIndex &ix, int lo, int hi) {
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < kShort; ++i)
+        any |= i < ix.nshort && ix.short_len[i] < ix.ptab_k && ix.short_row[i] >= lo && ix.short_row[i] < hi;
+    return any;
+}
+
+// Index of the short suffix (length < k) at `row`, or -1.
+__device__ __forceinline__ int short_at(const DevIndex &ix, int row) {
+    int at = -1;
+#pragma unroll
+    for (int i = 0; i < kShort; ++i)
+        if (i < ix.nshort && ix.short_len[i] < ix.ptab_k && ix.short_row[i] == row) at = i;
+    return at;
+}
+
+// LB search of P[0..plen) inside the table bracket.  Returns false when the
+// bracket holds a short suffix (the caller then searches from the root).
+// Rows inside the bracket share k bases with P, so when the search moves a
+// bound inside, the other bound's common-prefix length (below k) never
+// decides anything and starts as 0; when the bracket is empty, both
+// neighbours are probed for their exact common-prefix lengths.
+template <int W, class Cnt>
+__device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const uint64_t (&q)[W], int plen, LbState &st,
+                                                Cnt &cnt) {
+    const int K = ix.ptab_k;
+    const uint32_t v = (uint32_t)(q[0] >> (64 - 2 * K));
+    const int lo_k = (int)ix.ptab[v];
+    const int hi_k = (int)ix.ptab[v + 1];
+    cnt.table_probe();
+    if (short_rows_in(ix, lo_k, hi_k)) return false;
+    st.L = lo_k - 1; st.R = hi_k; st.lcpL = 0; st.lcpR = 0;
+    st.Llt = -1; st.lcpLlt = 0; st.Rlt = ix.n; st.lcpRlt = 0;
+    if (hi_k == lo_k) {
+        const int rl = st.L >= 0 ? st.L : 0;
+        const int rr = st.R < ix.n ? st.R : ix.n - 1;
+        const int32_t pl = ix.sa[rl], pr = ix.sa[rr];
+        const uint64_t kl = ix.row_key[rl], kr = ix.row_key[rr];
+        int a = 0, c = 0;
+        if (st.L >= 0) { cnt.key_probe(); compare_keyed<W>(ix, q, plen, pl, kl, 0, a, cnt); }
+        if (st.R < ix.n) { cnt.key_probe(); compare_keyed<W>(ix, q, plen, pr, kr, 0, c, cnt); }
+        st.lcpL = a;
+        st.lcpR = c;
+        return true;
+    }
+    while (st.R > st.L + 1) {
+        const int piv = midpoint(st.L, st.R);
+        const int32_t p = ix.sa[piv];
+        const uint64_t key = ix.row_key[piv];
+        int lcp;
+        cnt.key_probe();
+        const int sign = compare_keyed<W>(ix, q, plen, p, key, min_i(st.lcpL, st.lcpR), lcp, cnt);
+        lb_update(st, sign, piv, lcp);
+    }
+    return true;
+}
+
+// Row interval [lo, hi) of u = P[0..l), 1 <= l < k, from the table: lo is
+// T[u A..A] less the short suffixes u, uA, uAA... sorting right before it;
+// hi is T[successor of u T..T] less the short suffixes that are proper
+// prefixes of that successor and sort after u (right before it).
+template <class Cnt>
+__device__ __forceinline__ void table_interval(const DevIndex &ix, uint64_t q0, int l, int &lo, int &hi, Cnt &cnt) {
+    const int K = ix.ptab_k;
+    const uint32_t u = (uint32_t)(q0 >> (64 - 2 * l));
+    const uint32_t ulo = u << (2 * (K - l));
+    const uint32_t w = ulo + (1u << (2 * (K - l)));
+    lo = (int)ix.ptab[ulo];
+    hi = (int)ix.ptab[w];
+    cnt.table_probe();
+    for (;;) {
+        const int si = lo > 0 ? short_at(ix, lo - 1) : -1;
+        if (si < 0) break;
+        const int len = ix.short_len[si];
+        if (len >= l && (uint32_t)(ix.short_key[si] >> (64 - 2 * l)) == u) lo--;
+        else break;
+    }
+    for (;;) {
+        const int si = hi > lo ? short_at(ix, hi - 1) : -1;
+        if (si < 0) break;
+        const int len = ix.short_len[si];
+        const int c = len < l ? len : l;
+        const uint32_t kp = (uint32_t)(ix.short_key[si] >> (64 - 2 * c));
+        const uint32_t up = u >> (2 * (l - c));
+        if (kp > up) hi--;
+        else break;
+    }
+}
+
 // One read: LB search of its ACGT prefix; exact reads finish with an RB
 // search confined to (LB, Rlt]; other reads take the longest matched prefix
 // l = max(lcpL, lcpR) from the two rows around the insertion point and find
 // the interval of P[0..l) inside the bounds the LB search already bracketed.
 template <int W, class Cnt>
 __device__ __forceinline__ int4 match_read(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
-                           const uint64_t (&q)[W], int m, int mv, Cnt &cnt) {
+                           bool use_table, const uint64_t (&q)[W], int m, int mv, Cnt &cnt) {
     LbState st;
-    lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, cnt);
+    const bool via_table = use_table && ix.ptab_k > 0 && mv >= ix.ptab_k && lb_search_table<W>(ix, q, mv, st, cnt);
+    if (!via_table) lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, cnt);
     if (mv == m && st.lcpR == m) {
         const int hi = bounded_search<W, true>(ix, q, m, st.R, st.Rlt, m, st.lcpRlt, cnt);
         return make_int4(st.R, hi, m, (int)kHitExact);
     }
     const int l = max_i(st.lcpL, st.lcpR);
     if (l == 0) return make_int4(0, ix.n, 0, 0);
+    if (via_table && l < ix.ptab_k) {
+        int lo, hi;
+        table_interval(ix, q[0], l, lo, hi, cnt);
+        return make_int4(lo, hi, l, 0);
+    }
     const int lo = (st.lcpL == l) ? bounded_search<W, false>(ix, q, l, st.Llt, st.L, st.lcpLlt, l, cnt) : st.R;
     const int hi = (st.lcpR == l) ? bounded_search<W, true>(ix, q, l, st.R, st.Rlt, l, st.lcpRlt, cnt) : st.R;
     return make_int4(lo, hi, l, 0);
@@ -227,6 +334,31 @@ __global__ void build_row_keys_kernel(const uint64_t *__restrict__ text, const i
                                       uint64_t *__restrict__ key) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) key[r] = text_word(text, (uint32_t)sa[r]);
+}
+
+// ------------------------------------------------------------------ prefix table
+
+// Order key of a row for a k-base table: 2 * (first k bases, zero-padded)
+// + 1 for a suffix of at least k bases, without the +1 for a shorter one (it
+// sorts before every k-base string it is a proper prefix of).  It does not
+// decrease along the suffix array.
+__device__ __forceinline__ uint64_t row_order_key(const DevIndex &ix, int k, int r) {
+    const uint64_t pre = ix.row_key[r] >> (64 - 2 * k);
+    return 2 * pre + ((ix.n - ix.sa[r]) >= k ? 1u : 0u);
+}
+
+// T[v] = first row whose order key reaches 2v + 1 (binary search per entry).
+__global__ void build_prefix_table_kernel(DevIndex ix, int k, int64_t entries, uint32_t *__restrict__ tab) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= entries) return;
+    const uint64_t target = 2 * (uint64_t)v + 1;
+    int lo = 0, hi = ix.n;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (row_order_key(ix, k, mid) >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    tab[v] = (uint32_t)lo;
 }
 
 // ------------------------------------------------------------------ tile
@@ -697,7 +829,8 @@ __device__ __forceinline__ void convert_read(const uint8_t *__restrict__ reads, 
 
 template <int W, class Cnt>
 __device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa,
-                                          int levels, const BatchBuffers &b, const uint8_t *__restrict__ reads,
+                                          int levels, bool use_table, const BatchBuffers &b,
+                                          const uint8_t *__restrict__ reads,
                                           const int64_t *__restrict__ offs, int rid, int4 *out, Cnt &cnt) {
     const int m = b.qlen[rid];
     if (m < 0) {
@@ -707,7 +840,7 @@ __device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_
     uint64_t q[W];
     int mv;
     convert_read<W>(reads, offs[rid], m, q, mv);
-    out[rid] = match_read<W>(ix, s_key, s_sa, levels, q, m, mv, cnt);
+    out[rid] = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, cnt);
 }
 
 // Sum a per-lane count over the wave and add it to a global counter.
@@ -736,7 +869,8 @@ __device__ __forceinline__ int64_t workgroup_rank() {
 // the workgroup's blocks are done.  Each chunk runs the instantiation for
 // the longest read it holds.
 template <int BLOCK, bool COUNT>
-__global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, int group, BatchBuffers b,
+__global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group,
+                                                             BatchBuffers b,
                                                              const uint8_t *__restrict__ reads,
                                                              const int64_t *__restrict__ offs,
                                                              const uint32_t *__restrict__ order,
@@ -755,6 +889,7 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
     using Cnt = typename std::conditional<COUNT, Count, NoCount>::type;
     Cnt cnt;
     uint32_t nsearched = 0, nqwords = 0;
+    const bool use_table = use_table_i != 0;
     const int lane = threadIdx.x & 63;
     const int64_t nchunks = (nreads + 63) >> 6;
     const int64_t G = gridDim.x, rank = workgroup_rank();
@@ -776,16 +911,16 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         if (!active) continue;
         if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
         switch (wc) {
-            case 1: tuned_one<1>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
-            case 2: tuned_one<2>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
-            case 3: tuned_one<3>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
-            case 4: tuned_one<4>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
-            case 5: tuned_one<5>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
-            case 6: tuned_one<6>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
-            case 7: tuned_one<7>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
-            case 8: tuned_one<8>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
-            case 9: tuned_one<9>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
-            default: tuned_one<10>(ix, s_key, s_sa, levels, b, reads, offs, rid, out, cnt); break;
+            case 1: tuned_one<1>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            case 2: tuned_one<2>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            case 3: tuned_one<3>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            case 4: tuned_one<4>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            case 5: tuned_one<5>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            case 6: tuned_one<6>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            case 7: tuned_one<7>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            case 8: tuned_one<8>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            case 9: tuned_one<9>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            default: tuned_one<10>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
         }
     }
     if constexpr (COUNT) {
@@ -795,6 +930,7 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         wave_add(&b.stats[3], nsearched);
         wave_add(&b.stats[4], nqwords);
         wave_add(&b.stats[5], cnt.keys);
+        wave_add(&b.stats[6], cnt.table);
     }
 }
 
@@ -861,7 +997,7 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
 }
 
 template <int BLOCK, bool COUNT>
-hipError_t launch_tuned_block(const DevIndex &ix, int levels, int group, int grid, const BatchBuffers &b,
+hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int group, int grid, const BatchBuffers &b,
                               const uint8_t *reads, const int64_t *offs, const uint32_t *order, int64_t nreads,
                               int4 *out, hipStream_t s) {
     const size_t lds = tile_lds_bytes(levels);
@@ -873,8 +1009,8 @@ hipError_t launch_tuned_block(const DevIndex &ix, int levels, int group, int gri
         if (e != hipSuccess) return e;
         attr_set.store(true);
     }
-    hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, group, b,
-                       reads, offs, order, nreads, out);
+    hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, use_table,
+                       group, b, reads, offs, order, nreads, out);
     return hipGetLastError();
 }
 
@@ -922,20 +1058,31 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *whi
     return hipSuccess;
 }
 
-hipError_t launch_search_tuned(const DevIndex &ix, int levels, int block, int grid, int group, const BatchBuffers &b,
-                               const uint8_t *reads, const int64_t *offs, const uint32_t *order, int64_t nreads,
-                               void *out, bool count, hipStream_t s) {
+hipError_t launch_search_tuned(const DevIndex &ix, int levels, int use_table, int block, int grid, int group,
+                               const BatchBuffers &b, const uint8_t *reads, const int64_t *offs, const uint32_t *order,
+                               int64_t nreads, void *out, bool count, hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
     if (group < 1) return hipErrorInvalidValue;
     if (count)  // counts do not depend on the workgroup shape or the work split
-        return launch_tuned_block<256, true>(ix, levels, group, grid * (block / 256), b, reads, offs, order, nreads,
-                                             o, s);
+        return launch_tuned_block<256, true>(ix, levels, use_table, group, grid * (block / 256), b, reads, offs, order,
+                                             nreads, o, s);
     switch (block) {
-        case 256: return launch_tuned_block<256, false>(ix, levels, group, grid, b, reads, offs, order, nreads, o, s);
-        case 512: return launch_tuned_block<512, false>(ix, levels, group, grid, b, reads, offs, order, nreads, o, s);
-        case 1024: return launch_tuned_block<1024, false>(ix, levels, group, grid, b, reads, offs, order, nreads, o, s);
+        case 256:
+            return launch_tuned_block<256, false>(ix, levels, use_table, group, grid, b, reads, offs, order, nreads, o, s);
+        case 512:
+            return launch_tuned_block<512, false>(ix, levels, use_table, group, grid, b, reads, offs, order, nreads, o, s);
+        case 1024:
+            return launch_tuned_block<1024, false>(ix, levels, use_table, group, grid, b, reads, offs, order, nreads, o,
+                                                   s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_build_prefix_table(const DevIndex &ix, int k, uint32_t *tab, hipStream_t s) {
+    const int64_t entries = ((int64_t)1 << (2 * k)) + 1;
+    hipLaunchKernelGGL(build_prefix_table_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix, k,
+                       entries, tab);
+    return hipGetLastError();
 }
 
 hipError_t launch_keys(const uint8_t *reads, const int64_t *offs, const int64_t *ends, int64_t nreads,

@@ -51,7 +51,7 @@ std::string cache_key(const sa_dindex *d, const std::vector<int64_t> &hist, int6
 std::string cfg_json(const sa_match_cfg &c) {
     std::ostringstream o;
     o << "\"tile_levels\":" << c.tile_levels << ",\"block\":" << c.block << ",\"blocks_per_cu\":" << c.blocks_per_cu
-      << ",\"group\":" << c.group << ",\"sort\":" << c.sort
+      << ",\"group\":" << c.group << ",\"prefix_table\":" << c.prefix_table << ",\"sort\":" << c.sort
       << ",\"nbuckets\":" << c.nbuckets << ",\"bucket_edge\":[";
     for (int i = 0; i < c.nbuckets; i++) o << (i ? "," : "") << c.bucket_edge[i];
     o << "]";
@@ -79,6 +79,7 @@ bool parse_cached(const std::string &path, const std::string &key, sa_match_cfg 
         c.block = json_int(line, "block", 256);
         c.blocks_per_cu = json_int(line, "blocks_per_cu", 8);
         c.group = json_int(line, "group", 4);
+        c.prefix_table = json_int(line, "prefix_table", 0);
         c.sort = json_int(line, "sort", 1);
         c.nbuckets = std::max(1, std::min(8, json_int(line, "nbuckets", 1)));
         const size_t p = line.find("\"bucket_edge\":[");
@@ -176,8 +177,8 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
         }
         ms = best_rep;
         if (std::getenv("SAMATCH_TUNE_LOG"))
-            std::fprintf(stderr, "tune: levels=%d block=%d per_cu=%d group=%d buckets=%d -> %.4f ms\n", c.tile_levels,
-                         c.block, c.blocks_per_cu, c.group, c.nbuckets, ms);
+            std::fprintf(stderr, "tune: levels=%d block=%d per_cu=%d group=%d table=%d buckets=%d -> %.4f ms\n",
+                         c.tile_levels, c.block, c.blocks_per_cu, c.group, c.prefix_table, c.nbuckets, ms);
         return SA_OK;
     };
     // stage 1: tile depth x workgroup shape with one bucket
@@ -196,6 +197,7 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
                 c.bucket_edge[0] = SA_MAX_READ;
                 c.sort = 1;
                 c.group = 4;
+                c.prefix_table = d->defaults.prefix_table;
                 double ms = 0;
                 rc = time_cfg(c, ms);
                 if (rc == SA_EINVAL) continue;
@@ -204,10 +206,14 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
             }
         }
     }
-    // stage 1b: block size of the work split with the best shape
-    for (int group : {1, 2, 8, 16}) {
+    // stage 1b: block size of the work split with the best shape, and the
+    // search start (prefix table or LDS tile only)
+    static const int kGroups[4] = {1, 2, 8, 16};
+    for (int variant = 0; variant < 5; variant++) {
         sa_match_cfg c = top;
-        c.group = group;
+        if (variant < 4) c.group = kGroups[variant];
+        else if (d->view.ptab_k > 0) c.prefix_table = !top.prefix_table;
+        else continue;
         double ms = 0;
         rc = time_cfg(c, ms);
         if (rc == SA_EINVAL) continue;

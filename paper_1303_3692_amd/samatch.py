@@ -39,13 +39,13 @@ class MatchCfg(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("tile_levels", ctypes.c_int), ("block", ctypes.c_int),
                 ("blocks_per_cu", ctypes.c_int), ("nbuckets", ctypes.c_int), ("bucket_edge", ctypes.c_int * 8),
                 ("sort", ctypes.c_int), ("use_graph", ctypes.c_int), ("profile", ctypes.c_int),
-                ("count", ctypes.c_int), ("group", ctypes.c_int)]
+                ("count", ctypes.c_int), ("group", ctypes.c_int), ("prefix_table", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {"kernel": self.kernel, "tile_levels": self.tile_levels, "block": self.block,
                 "blocks_per_cu": self.blocks_per_cu, "nbuckets": self.nbuckets,
                 "bucket_edge": list(self.bucket_edge)[:max(1, self.nbuckets)], "sort": self.sort,
-                "use_graph": self.use_graph, "group": self.group}
+                "use_graph": self.use_graph, "group": self.group, "prefix_table": self.prefix_table}
 
 
 class ServerOpts(ctypes.Structure):
@@ -270,10 +270,10 @@ def sa_stage_times(d: DIndex, stream=None) -> dict:
 
 def sa_probe_counts(d: DIndex, stream=None) -> dict:
     """Probe counts of the last counted batch on this stream."""
-    c = (ctypes.c_int64 * 6)()
+    c = (ctypes.c_int64 * 7)()
     _check(lib().sa_probe_counts(d.ptr, _stream_handle(stream), c), "sa_probe_counts")
     return {"global_probes": c[0], "text_words": c[1], "tile_probes": c[2], "reads": c[3], "query_words": c[4],
-            "key_words": c[5]}
+            "key_words": c[5], "table_lookups": c[6]}
 
 
 def sa_tune(d: DIndex, d_reads, d_offs, nreads: int | None = None, stream=None, cache_path: str | None = None):

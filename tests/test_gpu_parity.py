@@ -49,6 +49,7 @@ def assert_same(got, want, label=""):
 CONFIGS = [
     ("plain", dict(kernel=S.SA_KERNEL_PLAIN)),
     ("tuned-default", dict()),
+    ("tuned-no-table", dict(prefix_table=0)),
     ("tuned-t1-unsorted", dict(tile_levels=1, sort=0, block=256, blocks_per_cu=1)),
     ("tuned-t5-b512", dict(tile_levels=5, block=512, blocks_per_cu=2)),
     ("tuned-t13-b1024", dict(tile_levels=13, block=1024, blocks_per_cu=1)),
@@ -120,8 +121,6 @@ def test_tiny_texts_against_brute(device, kind):
                 r = r + "".join(rng.choice("ACGT") for _ in range(rng.randint(1, 40)))
             reads.append(r)
         check_text(text, reads, device, f"{kind}/{trial}")
-        for r in reads[:20]:
-            pass
 
 
 def test_long_and_too_long_reads(device):
@@ -202,3 +201,36 @@ def test_streams_and_reuse(device):
     torch.cuda.synchronize()
     for _, o in outs:
         assert_same(o.cpu().numpy(), want, "stream")
+
+
+@pytest.mark.parametrize("kind", ["iid", "allA", "period3", "tandem", "two-letter"])
+def test_prefix_table_edges(device, kind):
+    """Texts just above the size that gets a prefix table, whose end suffixes
+    (shorter than the table's k) are prefixes of many reads."""
+    say("case: prefix table", kind)
+    rng = random.Random(len(kind) * 7919)
+    for n in (4096, 5000, 17_000):
+        if kind == "iid":
+            text = "".join(rng.choice("ACGT") for _ in range(n))
+        elif kind == "allA":
+            text = "A" * n
+        elif kind == "period3":
+            text = ("ACG" * n)[:n]
+        elif kind == "tandem":
+            text = "".join(rng.choice("ACGT") for _ in range(n // 2)) + ("GATT" * n)[: n - n // 2]
+        else:
+            text = "".join(rng.choice("AC") for _ in range(n))
+        reads = ["", "A", "C", "G", "T", "AC", "TT"]
+        for j in range(1, 20):
+            tail = text[-j:]
+            reads += [tail, tail + "A", tail + "C", tail + "T", tail[:-1] + "N" if j > 1 else "N",
+                      "A" * j, "T" * j, tail + text[:5]]
+        for _ in range(300):
+            i = rng.randrange(n)
+            r = text[i:i + rng.randint(1, 60)]
+            if rng.random() < 0.4 and r:
+                j = rng.randrange(len(r))
+                r = r[:j] + rng.choice("ACGT") + r[j + 1:]
+            reads.append(r)
+        reads += ["".join(rng.choice("ACGT") for _ in range(rng.randint(5, 40))) for _ in range(100)]
+        check_text(text, reads, device, f"{kind}/{n}")
