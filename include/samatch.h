@@ -95,9 +95,10 @@ int sa_load(const char *path, sa_index **out);
 void sa_free(sa_index *ix);                           /* NULL is a no-op            */
 
 /* Copy the index to device `device` and keep it resident: the packed text
- * (with zero padding words after the end), the int32 SA, the first 32 bases
- * of the suffix at every SA row (8 bytes per row, so that most probes of the
- * tuned kernel never touch the text), the table of the top levels of the
+ * (with zero padding words after the end), the int32 SA, a 16-byte record per SA
+ * row holding the first 32 bases of its suffix with the suffix's position
+ * and length (so that most probes of the tuned kernel load one record and
+ * never touch the text), the table of the top levels of the
  * implicit binary-search tree that the tuned kernel stages in LDS (the tile
  * of Section IV), and, for n >= 4096, a prefix table: for every string v of
  * k = round(log4 n) bases (4 <= k <= 14), the first SA row whose suffix is

@@ -29,7 +29,7 @@ DeviceGuard::~DeviceGuard() {
 }
 
 Workspace::~Workspace() {
-    for (void *p : {(void *)b.qw, (void *)b.qlen, (void *)b.qmv, (void *)b.key[0], (void *)b.key[1],
+    for (void *p : {(void *)b.qw, (void *)b.qlm, (void *)b.key[0], (void *)b.key[1],
                     (void *)b.val[0], (void *)b.val[1], (void *)b.hist, (void *)b.digit_total,
                     (void *)b.stats, (void *)d_reads, (void *)d_offs, (void *)d_out})
         if (p) (void)hipFree(p);
@@ -54,8 +54,7 @@ int Workspace::reserve(int64_t nreads) {
     const int64_t nblocks = (c + kSortTile - 1) / kSortTile;
     hipError_t e;
     if ((e = grow((void **)&b.qw, sizeof(uint64_t) * kWMax * (size_t)c)) != hipSuccess ||
-        (e = grow((void **)&b.qlen, sizeof(int32_t) * (size_t)c)) != hipSuccess ||
-        (e = grow((void **)&b.qmv, sizeof(int32_t) * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.qlm, sizeof(int2) * (size_t)c)) != hipSuccess ||
         (e = grow((void **)&b.key[0], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
         (e = grow((void **)&b.key[1], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
         (e = grow((void **)&b.val[0], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
@@ -156,17 +155,19 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
     const bool prof = c.profile != 0;
     hipError_t e = hipSuccess;
     if (prof && (e = hipEventRecord(ws->ev[0], s)) != hipSuccess) return hip_fail(e, "event record");
-    // the plain kernel searches packed words; the tuned kernel converts each
-    // read itself and needs only the sort keys and lengths
-    if (c.kernel == SA_KERNEL_PLAIN) e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bucket_table(c), s);
-    else e = launch_keys(d_reads, d_offs, d_ends, nreads, ws->b, bucket_table(c), s);
+    e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bucket_table(c), s);
     if (e != hipSuccess) return hip_fail(e, "pack launch");
     if (prof && (e = hipEventRecord(ws->ev[1], s)) != hipSuccess) return hip_fail(e, "event record");
     const uint32_t *order = nullptr;
     if (c.kernel == SA_KERNEL_TUNED && c.sort) {
+        // The key is (length bucket << 24 | first 12 bases).  Prefix bits
+        // beyond about one group per 64-read chunk put no more lanes on
+        // shared pivots, so the sort covers the top 8, 16 or 24 prefix bits
+        // (2^bits >= nreads / 64), then the bucket byte when there is one.
+        int pbits = 8;
+        while (pbits < 24 && ((int64_t)1 << pbits) < nreads / 64) pbits += 8;
         int which = 0;
-        const int bits = c.nbuckets > 1 ? 32 : 24;
-        e = launch_sort(ws->b, nreads, bits, &which, s);
+        e = launch_sort(ws->b, nreads, 24 - pbits, c.nbuckets > 1 ? 32 : 24, &which, s);
         if (e != hipSuccess) return hip_fail(e, "sort launch");
         order = ws->b.val[which];
     }
@@ -176,8 +177,8 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         if (e != hipSuccess) return hip_fail(e, "plain search launch");
     } else {
         const int grid = std::max(1, d->cu_count * c.blocks_per_cu);
-        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, c.group, ws->b, d_reads, d_offs,
-                                order, nreads, d_out, c.count != 0, s);
+        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, c.group, ws->b, order, nreads,
+                                d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
     if (prof && (e = hipEventRecord(ws->ev[3], s)) != hipSuccess) return hip_fail(e, "event record");
@@ -215,12 +216,12 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
         (e = hipMalloc((void **)&d->d_sa, sa_bytes)) != hipSuccess ||
         (e = hipMalloc((void **)&d->d_tile_key, nodes * sizeof(uint64_t))) != hipSuccess ||
         (e = hipMalloc((void **)&d->d_tile_sa, nodes * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc((void **)&d->d_row_key, sizeof(uint64_t) * (size_t)ix->n)) != hipSuccess)
+        (e = hipMalloc((void **)&d->d_rows, sizeof(RowRec) * (size_t)ix->n)) != hipSuccess)
         return hip_fail(e, "index allocation");
     if ((e = hipMemcpy(d->d_text, ix->packed.data(), text_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(d->d_sa, ix->sa.data(), sa_bytes, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "index upload");
-    if ((e = launch_build_row_keys(d->d_text, d->d_sa, (int32_t)ix->n, d->d_row_key, nullptr)) != hipSuccess ||
+    if ((e = launch_build_rows(d->d_text, d->d_sa, (int32_t)ix->n, d->d_rows, nullptr)) != hipSuccess ||
         (e = launch_build_tile(d->d_text, d->d_sa, (int32_t)ix->n, d->tile_levels, d->d_tile_key, d->d_tile_sa,
                                nullptr)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess)
@@ -230,7 +231,7 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
     v.sa = d->d_sa;
     v.tile_key = d->d_tile_key;
     v.tile_sa = d->d_tile_sa;
-    v.row_key = d->d_row_key;
+    v.rows = d->d_rows;
     v.n = (int32_t)ix->n;
     // rows of the shortest suffixes (the last kShort text positions)
     {
@@ -286,7 +287,7 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
 sa_dindex::~sa_dindex() {
     DeviceGuard g(device);
     ws.clear();
-    for (void *p : {(void *)d_text, (void *)d_sa, (void *)d_tile_key, (void *)d_tile_sa, (void *)d_row_key,
+    for (void *p : {(void *)d_text, (void *)d_sa, (void *)d_tile_key, (void *)d_tile_sa, (void *)d_rows,
                     (void *)d_ptab})
         if (p) (void)hipFree(p);
 }

@@ -64,7 +64,7 @@ struct sa_dindex {
     int32_t *d_sa = nullptr;
     uint64_t *d_tile_key = nullptr;
     int32_t *d_tile_sa = nullptr;
-    uint64_t *d_row_key = nullptr;
+    samatch::RowRec *d_rows = nullptr;
     uint32_t *d_ptab = nullptr;
     int tile_levels = 0;  // levels stored (the kernel may use fewer)
     samatch::DevIndex view{};

@@ -9,7 +9,7 @@
 #include <map>
 #include <memory>
 
-#include "../../include/samatch.h"
+#include "samatch.h"
 
 namespace samatch {
 

@@ -12,13 +12,21 @@ constexpr int kSortBlock = 256;           // radix sort: threads per workgroup
 constexpr int kSortItems = 16;            // keys per thread per pass
 constexpr int kSortTile = kSortBlock * kSortItems;
 
+// Per SA row: first 32 bases of the suffix (zero past the text end), its
+// text position and length.
+struct alignas(16) RowRec {
+    uint64_t key;
+    int32_t pos;
+    int32_t len;
+};
+
 // Device view of a resident index, passed to kernels by value.
 struct DevIndex {
     const uint64_t *text;      // packed text, 2 bits per base, zero padded
     const int32_t *sa;         // suffix array, n entries
     const uint64_t *tile_key;  // first 32 bases of the pivot suffix of each tree node
     const int32_t *tile_sa;    // text position of each tree node's pivot suffix
-    const uint64_t *row_key;   // first 32 bases of the suffix at each SA row
+    const RowRec *rows;        // one record per SA row
     const uint32_t *ptab;      // prefix table, 4^ptab_k + 1 entries (NULL when ptab_k == 0)
     int32_t n;
     int32_t ptab_k;            // bases indexed by the prefix table (0: no table)
@@ -40,8 +48,7 @@ struct BucketTable {
 // Scratch buffers of one batch (device pointers).
 struct BatchBuffers {
     uint64_t *qw;        // nreads * kWMax packed words
-    int32_t *qlen;       // read length, -1 for a read that is not searched
-    int32_t *qmv;        // length of the ACGT prefix
+    int2 *qlm;           // per read: length (-1: not searched), length of the ACGT prefix
     uint32_t *key[2];    // sort keys (ping-pong)
     uint32_t *val[2];    // read ids (ping-pong)
     uint32_t *hist;      // 256 * sort blocks
@@ -49,8 +56,7 @@ struct BatchBuffers {
     unsigned long long *stats;  // 8 counters of the instrumented search (zeroed by pack)
 };
 
-hipError_t launch_build_row_keys(const uint64_t *text, const int32_t *sa, int32_t n, uint64_t *key,
-                                 hipStream_t s);
+hipError_t launch_build_rows(const uint64_t *text, const int32_t *sa, int32_t n, RowRec *rows, hipStream_t s);
 
 // T[v] = first SA row whose suffix is not below the k-base string v.
 hipError_t launch_build_prefix_table(const DevIndex &ix, int k, uint32_t *tab, hipStream_t s);
@@ -63,21 +69,17 @@ hipError_t launch_build_tile(const uint64_t *text, const int32_t *sa, int32_t n,
 hipError_t launch_pack(const uint8_t *reads, const int64_t *offs, const int64_t *ends, int64_t nreads,
                        const BatchBuffers &b, const BucketTable &bt, hipStream_t s);
 
-// LSD radix sort of (key, val) pairs on bits [0, bits); returns in *which the
+// LSD radix sort of (key, val) pairs on bits [lo_bit, hi_bit), 8 bits per
+// pass (stable, so lower bits keep their input order); returns in *which the
 // ping-pong slot that holds the result.
-hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *which, hipStream_t s);
+hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi_bit, int *which, hipStream_t s);
 
 // count = true runs the instrumented variant that fills b.stats.
-// Sort keys and lengths only (the tuned search converts reads itself).
-hipError_t launch_keys(const uint8_t *reads, const int64_t *offs, const int64_t *ends, int64_t nreads,
-                       const BatchBuffers &b, const BucketTable &bt, hipStream_t s);
-
-// group: 64-read chunks per block of the work split (see the kernel).  The
-// search reads the ASCII bytes of read i at reads + offs[i].
+// group: 64-read chunks per block of the work split (see the kernel).
 // use_table: start LB searches from the prefix table (when the index has one).
 hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int use_table, int block, int grid,
-                               int group, const BatchBuffers &b, const uint8_t *reads, const int64_t *offs,
-                               const uint32_t *order, int64_t nreads, void *out, bool count, hipStream_t s);
+                               int group, const BatchBuffers &b, const uint32_t *order, int64_t nreads,
+                               void *out, bool count, hipStream_t s);
 
 hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_t nreads,
                                void *out, bool count, hipStream_t s);

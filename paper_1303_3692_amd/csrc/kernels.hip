@@ -130,11 +130,10 @@ __device__ __forceinline__ int bounded_search(const DevIndex &ix, const uint64_t
                               int lcpL, int lcpR, Cnt &cnt) {
     while (R > L + 1) {
         const int piv = midpoint(L, R);
-        const int32_t p = ix.sa[piv];
-        const uint64_t key = ix.row_key[piv];
+        const RowRec row = ix.rows[piv];
         int lcp;
         cnt.key_probe();
-        const int sign = compare_keyed<W>(ix, q, plen, p, key, min_i(lcpL, lcpR), lcp, cnt);
+        const int sign = compare_keyed<W>(ix, q, plen, row.pos, row.key, min_i(lcpL, lcpR), lcp, cnt);
         const bool go_left = UPPER ? (sign < 0) : (sign <= 0);
         if (go_left) { R = piv; lcpR = lcp; }
         else { L = piv; lcpL = lcp; }
@@ -184,11 +183,10 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
     }
     while (st.R > st.L + 1) {
         const int piv = midpoint(st.L, st.R);
-        const int32_t p = ix.sa[piv];
-        const uint64_t key = ix.row_key[piv];
+        const RowRec row = ix.rows[piv];
         int lcp;
         cnt.key_probe();
-        const int sign = compare_keyed<W>(ix, q, plen, p, key, min_i(st.lcpL, st.lcpR), lcp, cnt);
+        const int sign = compare_keyed<W>(ix, q, plen, row.pos, row.key, min_i(st.lcpL, st.lcpR), lcp, cnt);
         lb_update(st, sign, piv, lcp);
     }
 }
@@ -239,22 +237,20 @@ __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const uint64
     if (hi_k == lo_k) {
         const int rl = st.L >= 0 ? st.L : 0;
         const int rr = st.R < ix.n ? st.R : ix.n - 1;
-        const int32_t pl = ix.sa[rl], pr = ix.sa[rr];
-        const uint64_t kl = ix.row_key[rl], kr = ix.row_key[rr];
+        const RowRec xl = ix.rows[rl], xr = ix.rows[rr];
         int a = 0, c = 0;
-        if (st.L >= 0) { cnt.key_probe(); compare_keyed<W>(ix, q, plen, pl, kl, 0, a, cnt); }
-        if (st.R < ix.n) { cnt.key_probe(); compare_keyed<W>(ix, q, plen, pr, kr, 0, c, cnt); }
+        if (st.L >= 0) { cnt.key_probe(); compare_keyed<W>(ix, q, plen, xl.pos, xl.key, 0, a, cnt); }
+        if (st.R < ix.n) { cnt.key_probe(); compare_keyed<W>(ix, q, plen, xr.pos, xr.key, 0, c, cnt); }
         st.lcpL = a;
         st.lcpR = c;
         return true;
     }
     while (st.R > st.L + 1) {
         const int piv = midpoint(st.L, st.R);
-        const int32_t p = ix.sa[piv];
-        const uint64_t key = ix.row_key[piv];
+        const RowRec row = ix.rows[piv];
         int lcp;
         cnt.key_probe();
-        const int sign = compare_keyed<W>(ix, q, plen, p, key, min_i(st.lcpL, st.lcpR), lcp, cnt);
+        const int sign = compare_keyed<W>(ix, q, plen, row.pos, row.key, min_i(st.lcpL, st.lcpR), lcp, cnt);
         lb_update(st, sign, piv, lcp);
     }
     return true;
@@ -329,11 +325,19 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 
 // ------------------------------------------------------------------ row keys
 
-// First 32 bases of the suffix at every SA row (zero past the text end).
-__global__ void build_row_keys_kernel(const uint64_t *__restrict__ text, const int32_t *__restrict__ sa, int32_t n,
-                                      uint64_t *__restrict__ key) {
+// One 16-byte record per SA row: the first 32 bases of the row's suffix
+// (zero past the text end) and the suffix's text position, so that a probe
+// fetches both with one load.
+__global__ void build_rows_kernel(const uint64_t *__restrict__ text, const int32_t *__restrict__ sa, int32_t n,
+                                  RowRec *__restrict__ rows) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) key[r] = text_word(text, (uint32_t)sa[r]);
+    if (r >= n) return;
+    const int32_t p = sa[r];
+    RowRec rec;
+    rec.key = text_word(text, (uint32_t)p);
+    rec.pos = p;
+    rec.len = n - p;
+    rows[r] = rec;
 }
 
 // ------------------------------------------------------------------ prefix table
@@ -343,8 +347,8 @@ __global__ void build_row_keys_kernel(const uint64_t *__restrict__ text, const i
 // sorts before every k-base string it is a proper prefix of).  It does not
 // decrease along the suffix array.
 __device__ __forceinline__ uint64_t row_order_key(const DevIndex &ix, int k, int r) {
-    const uint64_t pre = ix.row_key[r] >> (64 - 2 * k);
-    return 2 * pre + ((ix.n - ix.sa[r]) >= k ? 1u : 0u);
+    const RowRec row = ix.rows[r];
+    return 2 * (row.key >> (64 - 2 * k)) + (row.len >= k ? 1u : 0u);
 }
 
 // T[v] = first row whose order key reaches 2v + 1 (binary search per entry).
@@ -414,34 +418,28 @@ __device__ __forceinline__ uint32_t pack4(uint32_t dw, uint32_t keep, uint32_t &
     return ((codes & 3u) << 6) | ((codes >> 4) & 0x30u) | ((codes >> 14) & 0x0Cu) | ((codes >> 24) & 3u);
 }
 
-// Shared tail of both pack paths: length, ACGT-prefix length, sort key.
-__device__ __forceinline__ void pack_finish(const BatchBuffers &b, const BucketTable &bt, int64_t i, int m, int mv,
-                                            uint64_t w0) {
-    b.qlen[i] = m;
-    b.qmv[i] = mv;
-    int bucket = bt.count - 1;
-    for (int j = 0; j < bt.count; ++j)
-        if (m <= bt.edge[j]) { bucket = j; break; }
-    b.key[0][i] = ((uint32_t)bucket << 24) | (uint32_t)(w0 >> 40);
-    b.val[0][i] = (uint32_t)i;
-}
-
-__device__ __forceinline__ void pack_reject(const BatchBuffers &b, int64_t i) {
-    b.qlen[i] = -1;
-    b.qmv[i] = 0;
-    b.qw[(size_t)i * kWMax] = 0;
-    b.key[0][i] = 0;
-    b.val[0][i] = (uint32_t)i;
+// pack4 with one byte permute instead of four letter tests: the code of a
+// byte is ((c >> 1) ^ (c >> 2)) & 3 (a/A -> 0, c/C -> 1, g/G -> 2, t/T ->
+// 3), and a byte is a base exactly when, with bit 5 cleared, it equals
+// "ACGT"[code] (looked up with v_perm).  Same results as pack4.
+__device__ __forceinline__ uint32_t pack4_fast(uint32_t dw, uint32_t keep, uint32_t &bad) {
+    uint32_t codes = ((dw >> 1) ^ (dw >> 2)) & 0x03030303u;
+    const uint32_t expect = __builtin_amdgcn_perm(0u, 0x54474341u, codes);  // "ACGT"[code] per byte
+    bad = nonzero_bytes((dw & 0xDFDFDFDFu) ^ expect) & keep;
+    codes &= keep & ~((bad >> 7) * 0xFFu);
+    return ((codes & 3u) << 6) | ((codes >> 4) & 0x30u) | ((codes >> 14) & 0x0Cu) | (codes >> 24);
 }
 
 // Pack one read from global memory, fetching aligned dwords; an aligned
 // dword that holds at least one byte of the read never crosses a page, so
 // no fetch can fault.
-__device__ void pack_from_global(const uint8_t *__restrict__ reads, int64_t a, int m, uint64_t *dst, int &mv,
-                                 uint64_t &w0) {
+__device__ __forceinline__ void pack_from_global(const uint8_t *__restrict__ reads, int64_t a, int m,
+                                                 uint64_t (&dst)[kWMax + 1], int &mv, uint64_t &w0) {
     mv = m;
     uint64_t word = 0;
     int k = 0;
+#pragma unroll
+    for (int t = 0; t < kWMax; ++t) dst[t] = 0;
     const uintptr_t start = (uintptr_t)(reads + a);
     const uintptr_t stop = start + (uintptr_t)m;
     for (uintptr_t addr = start & ~(uintptr_t)3; addr < stop; addr += 4) {
@@ -457,22 +455,40 @@ __device__ void pack_from_global(const uint8_t *__restrict__ reads, int64_t a, i
             const uint32_t code = ((c >> 1) ^ (c >> 2)) & 3u;
             if (!ok && idx < mv) mv = idx;
             word |= (uint64_t)(ok ? code : 0u) << (62 - 2 * (idx & 31));
-            if ((idx & 31) == 31) { dst[k++] = word; word = 0; }
+            if ((idx & 31) == 31) {
+#pragma unroll
+                for (int t = 0; t < kWMax; ++t) dst[t] = (t == k) ? word : dst[t];
+                ++k;
+                word = 0;
+            }
         }
     }
-    if ((m & 31) != 0 || m == 0) dst[k] = word;
+    if ((m & 31) != 0 || m == 0) {
+#pragma unroll
+        for (int t = 0; t < kWMax; ++t) dst[t] = (t == k) ? word : dst[t];
+    }
     w0 = dst[0];
 }
 
 // Packing: each workgroup copies the bytes of its 256 consecutive reads
 // into LDS with coalesced, aligned 16-byte loads, then each thread packs
-// its read from LDS four bases at a time.  Reads whose bytes are not in the
-// staged span (offsets that are not contiguous, or a span larger than the
-// staging buffer) take the global path.  Read i is reads[offs[i] ..
-// offs[i+1]), or reads[offs[i] .. ends[i]) when an end array is given
-// (reads scattered over a larger buffer; always the global path).
+// its read from LDS four bases at a time into registers.  Reads whose
+// bytes are not in the staged span (offsets that are not contiguous, or a
+// span larger than the staging buffer) take the global path.  The packed
+// words then go back through LDS so that the workgroup's 256 slots of
+// kWMax words (one contiguous range of the output) are written with
+// coalesced 16-byte stores.  Read i is reads[offs[i] .. offs[i+1]), or
+// reads[offs[i] .. ends[i]) when an end array is given (reads scattered
+// over a larger buffer; always the global path).
 constexpr int kPackBlock = 256;
 constexpr int kPackStage = 48 * 1024;
+static_assert(kPackBlock * kWMax * 8 <= kPackStage, "packed slots must fit in the staging buffer");
+
+// word k of a register array, written with a run-time k (select chain)
+__device__ __forceinline__ void put_word(uint64_t (&w)[kWMax], int k, uint64_t v) {
+#pragma unroll
+    for (int t = 0; t < kWMax; ++t) w[t] = (t == k) ? v : w[t];
+}
 
 __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restrict__ reads,
                                                           const int64_t *__restrict__ offs,
@@ -495,97 +511,74 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
                 *reinterpret_cast<const uint4 *>(c);
     }
     __syncthreads();
-    if (i >= nreads) return;
-    const int64_t a = offs[i], e = ends ? ends[i] : offs[i + 1];
-    const int64_t m64 = e - a;
-    if (m64 < 0 || m64 > kMaxRead) {
-        pack_reject(b, i);
-        return;
-    }
-    const int m = (int)m64;
-    uint64_t *dst = b.qw + (size_t)i * kWMax;
-    int mv = m;
-    uint64_t w0 = 0;
-    if (staged && a >= span0 && e <= span1) {
-        const uint32_t q = (uint32_t)((uintptr_t)(reads + a) - A0);
-        const uint32_t *src = stage + (q >> 2);
-        const uint32_t sh = (q & 3u) * 8u;
-        const int ndw = (m + 3) >> 2;
-        uint64_t word = 0;
-        int k = 0;
-        uint32_t lo = src[0];
-        for (int j = 0; j < ndw; ++j) {
-            const uint32_t hi = src[j + 1];
-            const uint32_t dw = sh ? (lo >> sh) | (hi << (32u - sh)) : lo;
-            lo = hi;
-            const int rem = m - 4 * j;
-            const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u);
-            uint32_t bad;
-            word = (word << 8) | pack4(dw, keep, bad);
-            if (bad && mv == m) mv = 4 * j + (__builtin_ctz(bad) >> 3);
-            if ((j & 7) == 7) {
-                if (k == 0) w0 = word;
-                dst[k++] = word;
-                word = 0;
+    uint64_t w[kWMax];
+#pragma unroll
+    for (int t = 0; t < kWMax; ++t) w[t] = 0;
+    int m = -1, mv = 0;
+    if (i < nreads) {
+        const int64_t a = offs[i], e = ends ? ends[i] : offs[i + 1];
+        const int64_t m64 = e - a;
+        if (m64 >= 0 && m64 <= kMaxRead) {
+            m = (int)m64;
+            mv = m;
+            if (staged && a >= span0 && e <= span1) {
+                // word k from dwords 8k .. 8k+8 of the staged span, read together
+                const uint32_t q = (uint32_t)((uintptr_t)(reads + a) - A0);
+                const uint32_t *src = stage + (q >> 2);
+                const uint32_t sh = q & 3u;
+#pragma unroll
+                for (int k = 0; k < kWMax; ++k) {
+                    if (32 * k < m) {
+                        uint32_t dwv[9];
+#pragma unroll
+                        for (int t = 0; t < 9; ++t) dwv[t] = src[8 * k + t];
+                        uint32_t half[2] = {0u, 0u};
+#pragma unroll
+                        for (int jj = 0; jj < 8; ++jj) {
+                            const int rem = m - 32 * k - 4 * jj;
+                            const uint32_t dw = __builtin_amdgcn_alignbyte(dwv[jj + 1], dwv[jj], sh);
+                            const uint32_t keep =
+                                rem >= 4 ? 0xFFFFFFFFu : (rem > 0 ? ((1u << (8 * rem)) - 1u) : 0u);
+                            uint32_t bad;
+                            const uint32_t b8 = pack4_fast(dw, keep, bad);
+                            if (bad && mv == m) mv = 32 * k + 4 * jj + (__builtin_ctz(bad) >> 3);
+                            half[jj >> 2] = (half[jj >> 2] << 8) | b8;
+                        }
+                        w[k] = ((uint64_t)half[0] << 32) | half[1];
+                    }
+                }
+            } else {
+                uint64_t g[kWMax + 1];
+                pack_from_global(reads, a, m, g, mv, g[kWMax]);
+#pragma unroll
+                for (int t = 0; t < kWMax; ++t) w[t] = (32 * t < m || t == 0) ? g[t] : 0;
             }
         }
-        if ((ndw & 7) != 0) {
-            word <<= 8 * (8 - (ndw & 7));
-            if (k == 0) w0 = word;
-            dst[k] = word;
-        } else if (m == 0) {
-            dst[0] = 0;
-        }
-    } else {
-        pack_from_global(reads, a, m, dst, mv, w0);
     }
-    pack_finish(b, bt, i, m, mv, w0);
-}
-
-// Sort keys only (the tuned path converts each read inside the search
-// kernel): length, and key = (length bucket, first 12 bases).  Reads the
-// aligned dwords that hold the first bases; an aligned dword holding a byte
-// of the read never crosses a page.
-__global__ __launch_bounds__(256) void key_kernel(const uint8_t *__restrict__ reads, const int64_t *__restrict__ offs,
-                                                  const int64_t *__restrict__ ends, int64_t nreads, BatchBuffers b,
-                                                  BucketTable bt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 8) b.stats[i] = 0ull;
-    if (i >= nreads) return;
-    const int64_t a = offs[i], e = ends ? ends[i] : offs[i + 1];
-    const int64_t m64 = e - a;
-    b.val[0][i] = (uint32_t)i;
-    if (m64 < 0 || m64 > kMaxRead) {
-        b.qlen[i] = -1;
-        b.key[0][i] = 0;
-        return;
-    }
-    const int m = (int)m64;
-    const int take = m < 12 ? m : 12;
-    const uintptr_t start = (uintptr_t)(reads + a);
-    const uintptr_t stop = start + (uintptr_t)take;
-    const uintptr_t abase = start & ~(uintptr_t)3;
-    const uint32_t sh = (uint32_t)(start & 3u) * 8u;
-    uint32_t prefix = 0;
+    __syncthreads();  // the staged bytes are no longer needed
+    uint64_t *slots = reinterpret_cast<uint64_t *>(stage);
+    if (i < nreads) {
+        const int nw = m > 0 ? (m + 31) >> 5 : 1;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int rem = take - 4 * j;
-        uint32_t b8 = 0;
-        if (rem > 0) {
-            const uintptr_t p0 = abase + 4u * j, p1 = p0 + 4u;
-            const uint32_t lo = *reinterpret_cast<const uint32_t *>(p0);
-            const uint32_t hi = (sh && p1 < stop) ? *reinterpret_cast<const uint32_t *>(p1) : 0u;
-            const uint32_t dw = sh ? (lo >> sh) | (hi << (32u - sh)) : lo;
-            uint32_t bad;
-            b8 = pack4(dw, rem >= 4 ? 0xFFFFFFFFu : ((1u << (8 * rem)) - 1u), bad);
+        for (int t = 0; t < kWMax; ++t)
+            if (t < nw) slots[threadIdx.x * kWMax + t] = w[t];
+        b.qlm[i] = make_int2(m, mv);
+        if (m >= 0) {
+            int bucket = bt.count - 1;
+            for (int j = 0; j < bt.count; ++j)
+                if (m <= bt.edge[j]) { bucket = j; break; }
+            b.key[0][i] = ((uint32_t)bucket << 24) | (uint32_t)(w[0] >> 40);
+        } else {
+            b.key[0][i] = 0;
         }
-        prefix = (prefix << 8) | b8;
+        b.val[0][i] = (uint32_t)i;
     }
-    b.qlen[i] = m;
-    int bucket = bt.count - 1;
-    for (int j = 0; j < bt.count; ++j)
-        if (m <= bt.edge[j]) { bucket = j; break; }
-    b.key[0][i] = ((uint32_t)bucket << 24) | prefix;
+    __syncthreads();
+    // the workgroup's slots are one contiguous range of qw: 16-byte stores
+    const int64_t nslots = (r1 - r0) * kWMax;
+    uint4 *dst = reinterpret_cast<uint4 *>(b.qw + (size_t)r0 * kWMax);
+    const uint4 *srcv = reinterpret_cast<const uint4 *>(slots);
+    for (int64_t c = threadIdx.x; c < nslots / 2; c += kPackBlock) dst[c] = srcv[c];
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -776,70 +769,16 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(const uint32_t
 
 // ------------------------------------------------------------------ search
 
-// Convert read bytes [a, a+m) to W packed words in registers and find the
-// length of its ACGT prefix.  The bytes come in aligned 16-byte chunks, two
-// new chunks per 32 bases; only chunks that hold a byte of the read are
-// fetched (an aligned chunk never crosses a page), others read as 0.
-__device__ __forceinline__ uint4 read_chunk(uintptr_t p, uintptr_t stop) {
-    return p < stop ? *reinterpret_cast<const uint4 *>(p) : make_uint4(0u, 0u, 0u, 0u);
-}
-
-__device__ __forceinline__ uint32_t pick4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t i) {
-    return i == 0 ? a : (i == 1 ? b : (i == 2 ? c : d));
-}
-
-template <int W>
-__device__ __forceinline__ void convert_read(const uint8_t *__restrict__ reads, int64_t a, int m, uint64_t (&q)[W],
-                                             int &mv) {
-    const uintptr_t start = (uintptr_t)(reads + a);
-    const uintptr_t stop = start + (uintptr_t)m;
-    const uintptr_t base = start & ~(uintptr_t)15;
-    const uint32_t dsh = (uint32_t)(start - base) >> 2;  // dword offset of the first byte, 0..3
-    const uint32_t bsh = (uint32_t)(start & 3u);         // byte offset inside that dword
-    mv = m;
-    uint4 c0 = read_chunk(base, stop);
-#pragma unroll
-    for (int k = 0; k < W; ++k) q[k] = 0;
-    // one word at a time (rolled), so that only one word's chunks are live
-#pragma unroll 1
-    for (int k = 0; k < W; ++k) {
-        const uint4 c1 = read_chunk(base + 32u * k + 16u, stop);
-        const uint4 c2 = read_chunk(base + 32u * k + 32u, stop);
-        const uint32_t d[12] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, c2.x, c2.y, c2.z, c2.w};
-        uint32_t sel[9];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) sel[j] = pick4(d[j], d[j + 1], d[j + 2], d[j + 3], dsh);
-        uint64_t word = 0;
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-            const int rem = m - 32 * k - 4 * jj;
-            // bytes 32k+4jj .. +3 of the read
-            const uint32_t dw = __builtin_amdgcn_alignbyte(sel[jj + 1], sel[jj], bsh);
-            const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : (rem > 0 ? ((1u << (8 * rem)) - 1u) : 0u);
-            uint32_t bad;
-            const uint32_t b8 = pack4(dw, keep, bad);
-            if (bad && mv == m) mv = 32 * k + 4 * jj + (__builtin_ctz(bad) >> 3);
-            word |= (uint64_t)b8 << (56 - 8 * jj);
-        }
-#pragma unroll
-        for (int t = 0; t < W; ++t) q[t] = (t == k) ? word : q[t];
-        c0 = c2;
-    }
-}
-
 template <int W, class Cnt>
 __device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa,
-                                          int levels, bool use_table, const BatchBuffers &b,
-                                          const uint8_t *__restrict__ reads,
-                                          const int64_t *__restrict__ offs, int rid, int4 *out, Cnt &cnt) {
-    const int m = b.qlen[rid];
+                                          int levels, bool use_table, const BatchBuffers &b, int rid, int m, int mv,
+                                          int4 *out, Cnt &cnt) {
     if (m < 0) {
         out[rid] = make_int4(0, 0, 0, (int)kHitTooLong);
         return;
     }
     uint64_t q[W];
-    int mv;
-    convert_read<W>(reads, offs[rid], m, q, mv);
+    load_query<W>(b.qw, rid, q);
     out[rid] = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, cnt);
 }
 
@@ -870,10 +809,7 @@ __device__ __forceinline__ int64_t workgroup_rank() {
 // the longest read it holds.
 template <int BLOCK, bool COUNT>
 __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group,
-                                                             BatchBuffers b,
-                                                             const uint8_t *__restrict__ reads,
-                                                             const int64_t *__restrict__ offs,
-                                                             const uint32_t *__restrict__ order,
+                                                             BatchBuffers b, const uint32_t *__restrict__ order,
                                                              int64_t nreads, int4 *__restrict__ out) {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned s_next;
@@ -902,7 +838,8 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         const int64_t j = (chunk << 6) + lane;
         const bool active = j < nreads;
         const int rid = active ? (order ? (int)order[j] : (int)j) : 0;
-        const int m = active ? b.qlen[rid] : 0;
+        const int2 lm = active ? b.qlm[rid] : make_int2(0, 0);
+        const int m = lm.x;
         const int w = max_i(1, (m + 31) >> 5);
         int wc = 1;
 #pragma unroll
@@ -911,16 +848,16 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         if (!active) continue;
         if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
         switch (wc) {
-            case 1: tuned_one<1>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
-            case 2: tuned_one<2>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
-            case 3: tuned_one<3>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
-            case 4: tuned_one<4>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
-            case 5: tuned_one<5>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
-            case 6: tuned_one<6>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
-            case 7: tuned_one<7>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
-            case 8: tuned_one<8>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
-            case 9: tuned_one<9>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
-            default: tuned_one<10>(ix, s_key, s_sa, levels, use_table, b, reads, offs, rid, out, cnt); break;
+            case 1: tuned_one<1>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            case 2: tuned_one<2>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            case 3: tuned_one<3>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            case 4: tuned_one<4>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            case 5: tuned_one<5>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            case 6: tuned_one<6>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            case 7: tuned_one<7>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            case 8: tuned_one<8>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            case 9: tuned_one<9>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            default: tuned_one<10>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
         }
     }
     if constexpr (COUNT) {
@@ -959,9 +896,10 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
     using Cnt = typename std::conditional<COUNT, Count, NoCount>::type;
     Cnt cnt;
     int4 res = make_int4(0, 0, 0, (int)kHitTooLong);
-    const int m = i < nreads ? b.qlen[i] : -1;
+    const int2 lm = i < nreads ? b.qlm[i] : make_int2(-1, 0);
+    const int m = lm.x;
     if (m >= 0) {
-        const int mv = b.qmv[i];
+        const int mv = lm.y;
         uint64_t q[kWMax];
         const uint64_t *src = b.qw + (size_t)i * kWMax;
 #pragma unroll
@@ -998,8 +936,7 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
 
 template <int BLOCK, bool COUNT>
 hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int group, int grid, const BatchBuffers &b,
-                              const uint8_t *reads, const int64_t *offs, const uint32_t *order, int64_t nreads,
-                              int4 *out, hipStream_t s) {
+                              const uint32_t *order, int64_t nreads, int4 *out, hipStream_t s) {
     const size_t lds = tile_lds_bytes(levels);
     static std::atomic<bool> attr_set{false};
     if (!attr_set.load()) {
@@ -1010,15 +947,15 @@ hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int
         attr_set.store(true);
     }
     hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, use_table,
-                       group, b, reads, offs, order, nreads, out);
+                       group, b, order, nreads, out);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_build_row_keys(const uint64_t *text, const int32_t *sa, int32_t n, uint64_t *key, hipStream_t s) {
+hipError_t launch_build_rows(const uint64_t *text, const int32_t *sa, int32_t n, RowRec *rows, hipStream_t s) {
     const int64_t blocks = ((int64_t)n + 255) / 256;
-    hipLaunchKernelGGL(build_row_keys_kernel, dim3((unsigned)blocks), dim3(256), 0, s, text, sa, n, key);
+    hipLaunchKernelGGL(build_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, text, sa, n, rows);
     return hipGetLastError();
 }
 
@@ -1038,11 +975,11 @@ hipError_t launch_pack(const uint8_t *reads, const int64_t *offs, const int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *which, hipStream_t s) {
+hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi_bit, int *which, hipStream_t s) {
     int cur = 0;
     const int nblocks = (int)((nreads + kSortTile - 1) / kSortTile);
     if (nreads > 1) {
-        for (int shift = 0; shift < bits; shift += 8) {
+        for (int shift = lo_bit; shift < hi_bit; shift += 8) {
             hipLaunchKernelGGL(sort_hist_kernel, dim3(nblocks), dim3(kSortBlock), 0, s, b.key[cur], nreads, shift,
                                b.hist, nblocks);
             hipLaunchKernelGGL(sort_digit_total_kernel, dim3(256), dim3(256), 0, s, b.hist, nblocks, b.digit_total);
@@ -1059,21 +996,16 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int bits, int *whi
 }
 
 hipError_t launch_search_tuned(const DevIndex &ix, int levels, int use_table, int block, int grid, int group,
-                               const BatchBuffers &b, const uint8_t *reads, const int64_t *offs, const uint32_t *order,
-                               int64_t nreads, void *out, bool count, hipStream_t s) {
+                               const BatchBuffers &b, const uint32_t *order, int64_t nreads, void *out, bool count,
+                               hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
     if (group < 1) return hipErrorInvalidValue;
     if (count)  // counts do not depend on the workgroup shape or the work split
-        return launch_tuned_block<256, true>(ix, levels, use_table, group, grid * (block / 256), b, reads, offs, order,
-                                             nreads, o, s);
+        return launch_tuned_block<256, true>(ix, levels, use_table, group, grid * (block / 256), b, order, nreads, o, s);
     switch (block) {
-        case 256:
-            return launch_tuned_block<256, false>(ix, levels, use_table, group, grid, b, reads, offs, order, nreads, o, s);
-        case 512:
-            return launch_tuned_block<512, false>(ix, levels, use_table, group, grid, b, reads, offs, order, nreads, o, s);
-        case 1024:
-            return launch_tuned_block<1024, false>(ix, levels, use_table, group, grid, b, reads, offs, order, nreads, o,
-                                                   s);
+        case 256: return launch_tuned_block<256, false>(ix, levels, use_table, group, grid, b, order, nreads, o, s);
+        case 512: return launch_tuned_block<512, false>(ix, levels, use_table, group, grid, b, order, nreads, o, s);
+        case 1024: return launch_tuned_block<1024, false>(ix, levels, use_table, group, grid, b, order, nreads, o, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1082,14 +1014,6 @@ hipError_t launch_build_prefix_table(const DevIndex &ix, int k, uint32_t *tab, h
     const int64_t entries = ((int64_t)1 << (2 * k)) + 1;
     hipLaunchKernelGGL(build_prefix_table_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix, k,
                        entries, tab);
-    return hipGetLastError();
-}
-
-hipError_t launch_keys(const uint8_t *reads, const int64_t *offs, const int64_t *ends, int64_t nreads,
-                       const BatchBuffers &b, const BucketTable &bt, hipStream_t s) {
-    const int64_t blocks = (nreads + 255) / 256;
-    hipLaunchKernelGGL(key_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, reads, offs, ends,
-                       nreads, b, bt);
     return hipGetLastError();
 }
 
