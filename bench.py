@@ -54,6 +54,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the built-in launch defaults")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    ap.add_argument("--no-graph", action="store_true", help="launch the kernels directly instead of replaying a graph")
+    ap.add_argument("--per-length", action="store_true",
+                    help="also time one batch call per distinct read length (default for c3)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a kernel of known traffic "
                          "for scaling memory counters)")
@@ -93,7 +96,9 @@ def main():
     d_reads = torch.from_numpy(reads.data).to(dev)
     d_offs = torch.from_numpy(reads.offs).to(dev)
     d_out = torch.zeros((N, 4), dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
+    # a stream of our own: the default stream cannot be captured into a graph
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
 
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
@@ -110,6 +115,7 @@ def main():
         _, tuned_ms = S.sa_tune(d, d_reads, d_offs, stream=stream, cache_path=args.tune_cache)
         log(f"tuner: {time.perf_counter() - t:.1f}s -> {S.cfg(d).as_dict()} ({tuned_ms:.3f} ms)")
     cfg = S.cfg(d)
+    cfg.use_graph = 0 if args.no_graph else 1
 
     def run_steps(c, k):
         torch.cuda.synchronize()
@@ -175,10 +181,51 @@ def main():
                  "search_GBps_alg": alg_bytes(pcnt) / (pst["search"] * 1e-3) / 1e9}
         log(f"plain: {plain}")
 
+    # ---- one call per distinct read length (the unbatched form)
+    per_length = None
+    if args.per_length or args.config == "c3":
+        groups = []
+        for L in np.unique(lens):
+            idx = np.nonzero(lens == L)[0]
+            starts = reads.offs[idx]
+            data_l = (reads.data[starts[:, None] + np.arange(L)[None, :]].reshape(-1) if L > 0
+                      else np.zeros(1, np.uint8))
+            offs_l = np.arange(len(idx) + 1, dtype=np.int64) * int(L)
+            groups.append((torch.from_numpy(np.ascontiguousarray(data_l)).to(dev), torch.from_numpy(offs_l).to(dev),
+                           torch.zeros((len(idx), 4), dtype=torch.int32, device=dev)))
+        lc = S.cfg(d, **cfg.as_dict())
+        lc.nbuckets = 1
+        lc.bucket_edge[0] = S.SA_MAX_READ
+        lc.use_graph = 0
+
+        def per_length_steps(k):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                for g_reads, g_offs, g_out in groups:
+                    S.match_batch_dev(d, g_reads, g_offs, g_out, stream=stream, config=lc)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        per_length_steps(1)
+        pk = max(2, args.steps // 4)
+        pel = per_length_steps(pk)
+        per_length = {"calls_per_step": len(groups), "ms_per_step": round(1000.0 * pel / pk, 3),
+                      "reads_per_s": round(N * pk / pel, 1)}
+        log(f"per-length: {per_length}")
+
     B = alg_bytes(cnt)
     achieved = B / (stages["search"] * 1e-3) / 1e9
+    # HBM traffic per launch from the committed rocprofv3 counters, only when
+    # they were taken on these kernel sources and this workload
+    traffic = None
+    counters = os.path.join(ROOT, "profiles", f"search_tuned_{args.config}_counters.json")
+    if os.path.exists(counters):
+        prof = json.load(open(counters))
+        if prof.get("kernel_src") == kernel_source_hash() and prof.get("workload") == args.config:
+            traffic = round(prof["traffic_bytes"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "search_tuned_kernel", "alg_bytes_per_launch": B, "alg_bytes_per_read": round(B / N, 2),
                 "launch_ms": round(stages["search"], 4), "kernel_src": kernel_source_hash()}
 
@@ -216,6 +263,8 @@ def main():
         "index": {"dc3_s": round(t_build, 2), "upload_s": round(t_upload, 4)},
         "plain": plain,
         "speedup_vs_plain": round(value / plain["reads_per_s"], 3) if plain else None,
+        "per_length": per_length,
+        "speedup_vs_per_length": round(value / per_length["reads_per_s"], 3) if per_length else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

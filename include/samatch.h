@@ -123,7 +123,10 @@ typedef struct {
     int bucket_edge[8];  /* tuned: bucket b holds reads with m <= bucket_edge[b];
                             ascending multiples of 32, last one >= SA_MAX_READ    */
     int sort;            /* tuned: 1 = sort reads by prefix first, 0 = input order */
-    int use_graph;       /* tuned: 1 = replay the launch sequence as a hipGraph    */
+    int use_graph;       /* 1 = match_batch_dev replays the batch's launch sequence
+                            as a hipGraph captured on first use for the same
+                            buffers, size and settings (not on the null stream;
+                            up to 8 per stream are kept)                         */
     int profile;         /* 1 = record HIP events between the stages (pack, sort,
                             search) for sa_stage_times                           */
     int count;           /* 1 = run the instrumented search kernel that counts

@@ -28,7 +28,13 @@ DeviceGuard::~DeviceGuard() {
     if (prev >= 0) (void)hipSetDevice(prev);
 }
 
+void Workspace::drop_graphs() {
+    for (GraphEntry &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+}
+
 Workspace::~Workspace() {
+    drop_graphs();
     for (void *p : {(void *)b.qw, (void *)b.qlm, (void *)b.key[0], (void *)b.key[1],
                     (void *)b.val[0], (void *)b.val[1], (void *)b.hist, (void *)b.digit_total,
                     (void *)b.stats, (void *)d_reads, (void *)d_offs, (void *)d_out})
@@ -50,6 +56,7 @@ static hipError_t grow(void **p, size_t bytes) {
 
 int Workspace::reserve(int64_t nreads) {
     if (nreads <= cap) return SA_OK;
+    drop_graphs();  // captured graphs point at the buffers about to be replaced
     const int64_t c = std::max<int64_t>(nreads, 1024);
     const int64_t nblocks = (c + kSortTile - 1) / kSortTile;
     hipError_t e;
@@ -187,6 +194,48 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
     return SA_OK;
 }
 
+static bool same_cfg(const sa_match_cfg &a, const sa_match_cfg &b) { return std::memcmp(&a, &b, sizeof a) == 0; }
+
+int run_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t *d_offs, const int64_t *d_ends,
+              int64_t nreads, sa_hit *d_out, hipStream_t s, const sa_match_cfg &c) {
+    // the null stream cannot be captured; profiling and counting need eager launches
+    if (!c.use_graph || !s || c.profile || c.count)
+        return enqueue_batch(d, ws, d_reads, d_offs, d_ends, nreads, d_out, s, c);
+    int rc = ws->reserve(nreads);  // no allocation may happen during capture
+    if (rc) return rc;
+    for (GraphEntry &g : ws->graphs) {
+        if (g.reads == d_reads && g.offs == d_offs && g.ends == d_ends && g.out == d_out && g.nreads == nreads &&
+            same_cfg(g.cfg, c)) {
+            g.last_use = ++ws->graph_clock;
+            hipError_t e = hipGraphLaunch(g.exec, s);
+            return e == hipSuccess ? SA_OK : hip_fail(e, "graph launch");
+        }
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    rc = enqueue_batch(d, ws, d_reads, d_offs, d_ends, nreads, d_out, s, c);
+    e = hipStreamEndCapture(s, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiation");
+    if (ws->graphs.size() >= Workspace::kMaxGraphs) {
+        auto oldest = std::min_element(ws->graphs.begin(), ws->graphs.end(),
+                                       [](const GraphEntry &x, const GraphEntry &y) { return x.last_use < y.last_use; });
+        (void)hipGraphExecDestroy(oldest->exec);
+        ws->graphs.erase(oldest);
+    }
+    ws->graphs.push_back(GraphEntry{d_reads, d_offs, d_ends, d_out, nreads, c, exec, ++ws->graph_clock});
+    e = hipGraphLaunch(exec, s);
+    return e == hipSuccess ? SA_OK : hip_fail(e, "graph launch");
+}
+
 }  // namespace samatch
 
 extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
@@ -204,6 +253,7 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
     d->n = ix->n;
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if ((e = prepare_kernels()) != hipSuccess) return hip_fail(e, "kernel attributes");
     d->cu_count = prop.multiProcessorCount;
     std::snprintf(d->arch, sizeof d->arch, "%s", prop.gcnArchName);
     const size_t text_bytes = sizeof(uint64_t) * ix->packed.size();
@@ -318,7 +368,7 @@ extern "C" int match_batch_dev(const sa_dindex *dc, const uint8_t *d_reads, cons
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     Workspace *ws = workspace_for(d, s);
     std::lock_guard<std::mutex> lk(ws->mu);
-    return enqueue_batch(d, ws, d_reads, d_offs, nullptr, nreads, d_out, s, c);
+    return run_batch(d, ws, d_reads, d_offs, nullptr, nreads, d_out, s, c);
 }
 
 extern "C" int match_batch(const sa_dindex *dc, const char *reads, const int64_t *offs, int64_t nreads,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <vector>
 #include <memory>
 #include <mutex>
 
@@ -22,12 +23,27 @@ struct DeviceGuard {
     bool ok = true;
 };
 
+// A captured launch sequence and what it was captured for.
+struct GraphEntry {
+    const void *reads, *offs, *ends, *out;
+    int64_t nreads;
+    sa_match_cfg cfg;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+
 // Scratch of one (index, stream): device buffers of the pipeline plus pinned
 // and device staging for host batches.  Grows on demand, never shrinks.
 struct Workspace {
     ~Workspace();
     int reserve(int64_t nreads);
     int reserve_staging(int64_t nreads, int64_t nbytes);
+    void drop_graphs();
+
+    // replayable launch sequences (at most kMaxGraphs, least recently used dropped)
+    static constexpr size_t kMaxGraphs = 8;
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
 
     std::mutex mu;
     int64_t cap = 0;
@@ -51,6 +67,10 @@ int check_cfg(const sa_dindex *d, const sa_match_cfg &c);
 sa_match_cfg resolve_cfg(const sa_dindex *d, const sa_match_cfg *cfg);
 int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t *d_offs, const int64_t *d_ends,
                   int64_t nreads, sa_hit *d_out, hipStream_t s, const sa_match_cfg &c);
+// enqueue_batch through a captured graph when c.use_graph asks for it (and
+// the stream can be captured), else directly.
+int run_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t *d_offs, const int64_t *d_ends,
+              int64_t nreads, sa_hit *d_out, hipStream_t s, const sa_match_cfg &c);
 
 }  // namespace samatch
 

@@ -56,6 +56,10 @@ struct BatchBuffers {
     unsigned long long *stats;  // 8 counters of the instrumented search (zeroed by pack)
 };
 
+// Once per device before any launch (and before any graph capture): lets
+// the tuned kernel use the LDS of the deepest tile.
+hipError_t prepare_kernels();
+
 hipError_t launch_build_rows(const uint64_t *text, const int32_t *sa, int32_t n, RowRec *rows, hipStream_t s);
 
 // T[v] = first SA row whose suffix is not below the k-base string v.

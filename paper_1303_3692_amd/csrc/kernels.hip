@@ -935,23 +935,29 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
 }
 
 template <int BLOCK, bool COUNT>
+hipError_t allow_tile_lds() {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&search_tuned_kernel<BLOCK, COUNT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds_bytes(kMaxTileLevels));
+}
+
+template <int BLOCK, bool COUNT>
 hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int group, int grid, const BatchBuffers &b,
                               const uint32_t *order, int64_t nreads, int4 *out, hipStream_t s) {
     const size_t lds = tile_lds_bytes(levels);
-    static std::atomic<bool> attr_set{false};
-    if (!attr_set.load()) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&search_tuned_kernel<BLOCK, COUNT>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)tile_lds_bytes(kMaxTileLevels));
-        if (e != hipSuccess) return e;
-        attr_set.store(true);
-    }
     hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, use_table,
                        group, b, order, nreads, out);
     return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t prepare_kernels() {
+    hipError_t e;
+    if ((e = allow_tile_lds<256, false>()) != hipSuccess || (e = allow_tile_lds<512, false>()) != hipSuccess ||
+        (e = allow_tile_lds<1024, false>()) != hipSuccess || (e = allow_tile_lds<256, true>()) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
 
 hipError_t launch_build_rows(const uint64_t *text, const int32_t *sa, int32_t n, RowRec *rows, hipStream_t s) {
     const int64_t blocks = ((int64_t)n + 255) / 256;
