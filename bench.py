@@ -62,6 +62,11 @@ def main():
                          "for scaling memory counters)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1303_3692_amd", "tuning_cache.jsonl"),
                     help="autotuner cache (JSON lines); a hit skips the sweep")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark: open-loop Poisson requests over resident references")
+    ap.add_argument("--serve-refs", default="c2,c4", help="references kept resident for --serve")
+    ap.add_argument("--serve-requests", type=int, default=600, help="measured requests per load level")
+    ap.add_argument("--serve-warmup", type=int, default=100, help="warm-up requests per load level")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (reads shard across GPUs "
@@ -79,6 +84,8 @@ def main():
         B.build()
     dev = torch.device("cuda:0")
     torch.cuda.init()
+    if args.serve:
+        return serve_bench(args, np, torch, gen, S)
 
     t = time.perf_counter()
     ref, reads = gen.workload(args.config)
@@ -267,6 +274,115 @@ def main():
         "speedup_vs_per_length": round(value / per_length["reads_per_s"], 3) if per_length else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(q * (len(xs) - 1)))))
+    return xs[k]
+
+
+def serve_bench(args, np, torch, gen, S):
+    """Open-loop Poisson request streams over resident references, at three
+    loads relative to the offline rate of the same request mix through the
+    host entry point; latency runs from each request's scheduled arrival to
+    its completion (steady clock on both sides)."""
+    import threading
+
+    names = args.serve_refs.split(",")
+    refs, dix = [], []
+    for name in names:
+        t = time.perf_counter()
+        ref = gen.make_reference(name)
+        ix = S.sa_build(ref.ascii())
+        d = S.sa_upload(ix, 0)
+        del ix
+        refs.append(ref)
+        dix.append(d)
+        log(f"reference {name}: n={ref.n} ready in {time.perf_counter() - t:.1f}s")
+    mixes = [gen.ReadSpec(60 + i, 0, 30, 300, 0.3, 0.0, 0.02) if name in ("c2", "c3") else
+             gen.ReadSpec(60 + i, 0, 30, 300, 0.2, 0.01, 0.01) for i, name in enumerate(names)]
+
+    # offline rate of the mix through match_batch (host buffers in, results out)
+    total_reads, total_t = 0, 0.0
+    for i, (ref, d) in enumerate(zip(refs, dix)):
+        spec = gen.ReadSpec(mixes[i].cfg_id + 1000, 1 << 20, 30, 300, mixes[i].frac_random, mixes[i].rate_lo,
+                            mixes[i].rate_hi)
+        rd = gen.make_reads(ref, spec)
+        S.match_batch(d, rd.data, rd.offs)
+        t = time.perf_counter()
+        for _ in range(3):
+            S.match_batch(d, rd.data, rd.offs)
+        total_t += time.perf_counter() - t
+        total_reads += 3 * rd.count
+    x_off = total_reads / total_t
+    mean_size = float(np.mean(gen.request_sizes(200_000, np.random.default_rng(7))))
+    log(f"offline host-path rate on the mix: {x_off / 1e6:.1f} M reads/s; mean request {mean_size:.0f} reads")
+
+    levels = []
+    for k, rho in enumerate((0.5, 0.8, 0.95)):
+        lam = rho * x_off / mean_size
+        nreq = args.serve_warmup + args.serve_requests
+        t = time.perf_counter()
+        stream = gen.request_stream(refs, nreq, lam, seed_sub=k)
+        log(f"rho={rho}: {nreq} requests at {lam:.0f}/s generated in {time.perf_counter() - t:.1f}s")
+        srv = S.Server(dix, max_batch_reads=1 << 20, nstreams=2)
+        tickets = [None] * nreq
+        sched = [0] * nreq
+        t0 = time.monotonic_ns() + 50_000_000
+
+        # several submitting threads (the library call releases the GIL while it copies
+        # the reads), each taking every nth request at its scheduled time
+        nthreads = 4
+
+        def submitter(part):
+            for i in range(part, nreq, nthreads):
+                due = t0 + int(stream[i].t_arrival * 1e9)
+                while True:
+                    now = time.monotonic_ns()
+                    if now >= due:
+                        break
+                    time.sleep(min(0.002, (due - now) / 1e9))
+                sched[i] = due
+                tickets[i] = srv.submit(stream[i].ref, stream[i].reads.data, stream[i].reads.offs)[0]
+
+        ths = [threading.Thread(target=submitter, args=(p,)) for p in range(nthreads)]
+        for th in ths:
+            th.start()
+        done = {}
+        for i in range(nreq):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            while True:
+                rc, st = srv.poll(tickets[i], timeout_us=100_000)
+                if rc != S.SA_PENDING:
+                    done[i] = (rc, st)
+                    break
+        for th in ths:
+            th.join()
+        srv.destroy()
+        meas = range(args.serve_warmup, nreq)
+        lat = [(done[i][1]["t_done_ns"] - sched[i]) / 1e6 for i in meas if done[i][0] == S.SA_OK]
+        reads_meas = sum(stream[i].reads.count for i in meas)
+        span = (max(done[i][1]["t_done_ns"] for i in meas) - min(sched[i] for i in meas)) / 1e9
+        late = sum(1 for i in range(nreq) if done[i][1]["t_submit_ns"] - sched[i] > 5_000_000)
+        lv = {"rho": rho, "requests_per_s": round(lam, 1), "p50_ms": round(percentile(lat, 0.50), 3),
+              "p99_ms": round(percentile(lat, 0.99), 3), "served_reads_per_s": round(reads_meas / span, 1),
+              "offered_reads_per_s": round(rho * x_off, 1), "failed": sum(1 for v in done.values() if v[0] != 0),
+              "submits_late_over_5ms": late}
+        levels.append(lv)
+        log(f"rho={rho}: {lv}")
+    line = {
+        "metric": METRIC, "value": levels[-1]["served_reads_per_s"], "unit": "reads/s", "n_gpus": 1,
+        "steps": len(levels), "warmup": args.serve_warmup, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic (seeded generators, no external data)",
+        "config": {"workload": "c5: open-loop Poisson requests over the " + " and ".join(names) + " references, "
+                               "1-100,000 reads each (log-uniform), 30-300 bp", "requests_per_level": args.serve_requests},
+        "offline_reads_per_s": round(x_off, 1), "levels": levels,
     }
     print(json.dumps(line), flush=True)
 

@@ -318,21 +318,32 @@ def make_reads(ref: Reference, spec: ReadSpec, count: int | None = None,
         src = lab != RANDOM
         mut = lab == MUTATED
         if spec.len_lo == spec.len_hi and spec.exact_subs is None and spec.len_lo <= n:
-            # fixed length: whole rows at once
+            # fixed length: whole rows at once; each base of a sampled read is
+            # substituted with probability r, drawn as a binomial count of
+            # distinct uniform positions (the same distribution)
             m = spec.len_lo
-            codes2 = rng.integers(0, 4, size=(k, m), dtype=np.uint8)
+            codes2 = np.empty((k, m), dtype=np.uint8)
+            rnd = ~src
+            codes2[rnd] = rng.integers(0, 4, size=(int(rnd.sum()), m), dtype=np.uint8)
             codes2[src] = np.lib.stride_tricks.sliding_window_view(ref.codes, m)[pos[src]]
-            mask2 = rng.random((k, m), dtype=np.float32) < rates.astype(np.float32)[:, None]
-            mask2 &= mut[:, None]
-            anyhit = mask2.any(axis=1)
-            first_sub = np.where(anyhit, mask2.argmax(axis=1), m).astype(np.int32)
-            codes = codes2.reshape(-1)
-            mask = mask2.reshape(-1)
-            _substitute(codes, mask, rng)
+            cnt = np.where(mut, rng.binomial(m, rates), 0)
+            rows = np.repeat(np.arange(k), cnt)
+            cols = rng.integers(0, m, size=len(rows))
+            while len(rows):
+                flat = rows.astype(np.int64) * m + cols
+                order = np.argsort(flat, kind="stable")
+                dup = np.zeros(len(rows), dtype=bool)
+                dup[order[1:]] = flat[order[1:]] == flat[order[:-1]]
+                if not dup.any():
+                    break
+                cols[dup] = rng.integers(0, m, size=int(dup.sum()))
+            codes2[rows, cols] = (codes2[rows, cols] + rng.integers(1, 4, size=len(rows), dtype=np.uint8)) & 3
+            first_sub = np.full(k, m, dtype=np.int32)
+            np.minimum.at(first_sub, rows, cols.astype(np.int32))
             pos = np.where(src, pos, -1)
             sl = slice(max(start, lo_i) - lo_i, min(stop, hi_i) - lo_i)
             o0, o1 = offs[sl.start], offs[sl.stop]
-            parts.append((to_ascii(codes[o0:o1]), lens[sl], lab[sl], pos[sl], first_sub[sl]))
+            parts.append((to_ascii(codes2.reshape(-1)[o0:o1]), lens[sl], lab[sl], pos[sl], first_sub[sl]))
             continue
         lens32 = lens.astype(np.int32)
         rel = np.arange(total, dtype=np.int32)

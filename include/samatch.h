@@ -190,6 +190,9 @@ typedef struct {
     int64_t test_fake_free_hbm;  /* < 0: ask the device; >= 0: pretend this much is free */
     int test_echo;               /* 1: no device work, results are a deterministic echo  */
     int test_fail_batch;         /* > 0: the n-th executed batch fails (error injection) */
+    int64_t host_pool_bytes;     /* pinned host memory that submit copies reads into, so
+                                    uploads are direct DMA (0: default 1 GiB, < 0: none); a
+                                    request that does not fit is copied to pageable memory */
 } sa_server_opts;
 
 typedef struct {
@@ -203,8 +206,8 @@ typedef struct {
 int sa_server_create(const sa_dindex *const *refs, int nrefs, const sa_server_opts *opts,
                      sa_server **out);
 
-/* Queue nreads host reads against refs[ref].  The reads are copied before
- * the call returns; out[nreads] must stay valid until match_poll reports
+/* Queue nreads host reads against refs[ref].  The reads are copied (into
+ * the server's pinned pool when it has room) before the call returns; out[nreads] must stay valid until match_poll reports
  * the request finished.  *ticket identifies the request. Thread-safe. */
 int match_submit(sa_server *s, int ref, const char *reads, const int64_t *offs, int64_t nreads,
                  sa_hit *out, uint64_t *ticket);

@@ -2,7 +2,9 @@
 // many requests, admission by a device-memory budget, several streams in
 // flight, per-request scatter of results and timestamps.
 //
-// Life of a request: submit copies its reads into host memory and queues it.
+// Life of a request: submit copies its reads into pinned host memory (a
+// pool allocated once, so the upload is a direct DMA; pageable memory when
+// the pool is full) and queues it.
 // The loop admits queued requests in arrival order while the device budget
 // (free HBM minus the reserve, fixed when the server starts) has room for
 // its reads; admission copies the reads into a device arena.  Each free
@@ -86,7 +88,9 @@ struct Request {
     uint64_t ticket = 0;
     int ref = 0;
     int64_t nreads = 0;
-    std::vector<char> reads;      // host copy
+    std::vector<char> reads;      // host copy when the pinned pool had no room
+    const char *h_reads = nullptr;  // the host copy (pool or reads)
+    int64_t pool_off = -1, pool_bytes = 0;
     std::vector<int64_t> offs;    // nreads + 1, rebased to 0
     sa_hit *out = nullptr;        // caller's
     int64_t arena_off = -1, arena_bytes = 0;
@@ -127,6 +131,9 @@ struct sa_server {
     int device = 0;
     Arena arena;
     uint8_t *d_arena = nullptr;
+    Arena pool;                // pinned host pool for submitted reads (own lock)
+    char *h_pool = nullptr;
+    std::mutex pool_mu;
     hipStream_t upload_stream = nullptr;
     std::vector<Slot> slots;
 
@@ -163,6 +170,12 @@ void sa_server::finish_locked(Request *r, int status) {
         r->uploaded = nullptr;
     }
     if (r->admitted) inflight_reads -= r->nreads;
+    if (r->pool_off >= 0) {
+        std::lock_guard<std::mutex> pl(pool_mu);
+        pool.release(r->pool_off, r->pool_bytes);
+        r->pool_off = -1;
+    }
+    r->h_reads = nullptr;
     std::vector<char>().swap(r->reads);
     std::vector<int64_t>().swap(r->offs);
     cv_done.notify_all();
@@ -190,7 +203,7 @@ bool sa_server::admit_locked() {
         r->t_admit = now_ns();
         inflight_reads += r->nreads;
         if (!o.test_echo && r->nreads > 0) {
-            hipError_t e = hipMemcpyAsync(d_arena + off, r->reads.data(), (size_t)r->offs[(size_t)r->nreads],
+            hipError_t e = hipMemcpyAsync(d_arena + off, r->h_reads, (size_t)r->offs[(size_t)r->nreads],
                                           hipMemcpyHostToDevice, upload_stream);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventRecord(r->uploaded, upload_stream);
@@ -288,16 +301,20 @@ bool sa_server::launch_locked(Slot &sl) {
 }
 
 // Deterministic stand-in results for host-only tests: lo = request-local
-// read index, hi = lo + ticket, len = read length, flags = reference.
+// read index, hi = lo + ticket, len = read length, flags = reference plus
+// 256 times the byte sum of the read's host copy (mod 2^16).
 void sa_server::echo_execute(Slot &sl) {
     for (const Piece &p : sl.pieces)
         for (int64_t k = 0; k < p.count; k++) {
             const int64_t i = p.first + k;
+            const int64_t b0 = p.req->offs[(size_t)i], b1 = p.req->offs[(size_t)i + 1];
+            uint32_t sum = 0;
+            for (int64_t b = b0; b < b1; b++) sum += (uint8_t)p.req->h_reads[b];
             sa_hit h;
             h.lo = (int32_t)i;
             h.hi = (int32_t)(i + (int64_t)p.req->ticket);
-            h.len = (int32_t)(p.req->offs[(size_t)i + 1] - p.req->offs[(size_t)i]);
-            h.flags = (uint32_t)sl.ref;
+            h.len = (int32_t)(b1 - b0);
+            h.flags = (uint32_t)sl.ref | ((sum & 0xffffu) << 8);
             sl.h_out[p.pos + k] = h;
         }
 }
@@ -363,6 +380,42 @@ void sa_server::run() {
     }
 }
 
+// Release what sa_server_create allocated; safe on a partly built server.
+static void free_resources(sa_server *s) {
+    if (s->o.test_echo) {
+        for (Slot &sl : s->slots) delete[] sl.h_out;
+        delete[] s->h_pool;
+        s->h_pool = nullptr;
+        return;
+    }
+    DeviceGuard g(s->device);
+    for (Slot &sl : s->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.h_se) (void)hipHostFree(sl.h_se);
+        if (sl.h_out) (void)hipHostFree(sl.h_out);
+        if (sl.d_se) (void)hipFree(sl.d_se);
+        if (sl.d_out) (void)hipFree(sl.d_out);
+        // the indexes keep a workspace per stream; drop this stream's
+        if (sl.stream)
+            for (sa_dindex *d : s->refs) {
+                std::lock_guard<std::mutex> g2(d->mu);
+                d->ws.erase((void *)sl.stream);
+            }
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        sl = Slot{};
+    }
+    if (s->upload_stream) {
+        (void)hipStreamSynchronize(s->upload_stream);
+        (void)hipStreamDestroy(s->upload_stream);
+        s->upload_stream = nullptr;
+    }
+    if (s->d_arena) (void)hipFree(s->d_arena);
+    s->d_arena = nullptr;
+    if (s->h_pool) (void)hipHostFree(s->h_pool);
+    s->h_pool = nullptr;
+}
+
 extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const sa_server_opts *opts,
                                 sa_server **out) {
     clear_error();
@@ -375,7 +428,9 @@ extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const s
     o.max_inflight_reads = (int64_t)8 << 20;
     o.nstreams = 2;
     o.test_fake_free_hbm = -1;
+    o.host_pool_bytes = (int64_t)1 << 30;
     if (opts) {
+        if (opts->host_pool_bytes != 0) o.host_pool_bytes = std::max<int64_t>(0, opts->host_pool_bytes);
         if (opts->hbm_reserve_bytes > 0) o.hbm_reserve_bytes = opts->hbm_reserve_bytes;
         if (opts->max_batch_reads > 0) o.max_batch_reads = opts->max_batch_reads;
         if (opts->max_inflight_reads > 0) o.max_inflight_reads = opts->max_inflight_reads;
@@ -393,51 +448,75 @@ extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const s
     s->o = o;
     s->active.resize((size_t)nrefs);
     s->slots.resize((size_t)o.nstreams);
-    if (o.test_echo) {
-        s->arena.init(o.test_fake_free_hbm >= 0 ? std::max<int64_t>(0, o.test_fake_free_hbm - o.hbm_reserve_bytes)
-                                                : ((int64_t)1 << 30));
-        for (Slot &sl : s->slots) sl.h_out = new sa_hit[(size_t)o.max_batch_reads];
-    } else {
-        s->device = s->refs[0]->device;
-        for (sa_dindex *d : s->refs)
-            if (d->device != s->device) return fail(SA_EINVAL, "all indexes must be on one device");
-        DeviceGuard g(s->device);
-        if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
-        size_t free_b = 0, total_b = 0;
-        hipError_t e = hipMemGetInfo(&free_b, &total_b);
-        if (e != hipSuccess) return hip_fail(e, "hipMemGetInfo");
-        const int64_t free_hbm = o.test_fake_free_hbm >= 0 ? o.test_fake_free_hbm : (int64_t)free_b;
-        // per slot: starts/ends, results, and the pipeline scratch (~120 B per read)
-        const int64_t per_slot = o.max_batch_reads * (16 + 16 + 130);
-        const int64_t budget = free_hbm - o.hbm_reserve_bytes - per_slot * o.nstreams;
-        if (budget < (1 << 20)) return fail(SA_ENOSPC, "not enough free device memory for the server");
-        const int64_t arena_bytes = std::min<int64_t>(budget, (int64_t)16 << 30);
-        if ((e = hipMalloc((void **)&s->d_arena, (size_t)arena_bytes)) != hipSuccess)
-            return hip_fail(e, "arena allocation");
-        s->arena.init(arena_bytes);
-        if ((e = hipStreamCreateWithFlags(&s->upload_stream, hipStreamNonBlocking)) != hipSuccess)
-            return hip_fail(e, "stream creation");
-        for (Slot &sl : s->slots) {
-            if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
-                (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
-                (e = hipHostMalloc((void **)&sl.h_se, sizeof(int64_t) * 2 * (size_t)o.max_batch_reads,
-                                   hipHostMallocDefault)) != hipSuccess ||
-                (e = hipHostMalloc((void **)&sl.h_out, sizeof(sa_hit) * (size_t)o.max_batch_reads,
-                                   hipHostMallocDefault)) != hipSuccess ||
-                (e = hipMalloc((void **)&sl.d_se, sizeof(int64_t) * 2 * (size_t)o.max_batch_reads)) != hipSuccess ||
-                (e = hipMalloc((void **)&sl.d_out, sizeof(sa_hit) * (size_t)o.max_batch_reads)) != hipSuccess)
-                return hip_fail(e, "slot allocation");
-            // size every index's scratch for this stream now, not on the first batch
-            for (sa_dindex *d : s->refs) {
-                int rc = workspace_for(d, sl.stream)->reserve(o.max_batch_reads);
-                if (rc) return rc;
+    auto setup = [&]() -> int {
+        if (o.test_echo) {
+            s->arena.init(o.test_fake_free_hbm >= 0 ? std::max<int64_t>(0, o.test_fake_free_hbm - o.hbm_reserve_bytes)
+                                                    : ((int64_t)1 << 30));
+            for (Slot &sl : s->slots) sl.h_out = new sa_hit[(size_t)o.max_batch_reads];
+            if (o.host_pool_bytes > 0) {
+                s->h_pool = new (std::nothrow) char[(size_t)o.host_pool_bytes];
+                if (!s->h_pool) return fail(SA_ENOMEM, "host pool");
+                s->pool.init(o.host_pool_bytes);
+            }
+        } else {
+            s->device = s->refs[0]->device;
+            for (sa_dindex *d : s->refs)
+                if (d->device != s->device) return fail(SA_EINVAL, "all indexes must be on one device");
+            DeviceGuard g(s->device);
+            if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
+            size_t free_b = 0, total_b = 0;
+            hipError_t e = hipMemGetInfo(&free_b, &total_b);
+            if (e != hipSuccess) return hip_fail(e, "hipMemGetInfo");
+            const int64_t free_hbm = o.test_fake_free_hbm >= 0 ? o.test_fake_free_hbm : (int64_t)free_b;
+            // per slot: starts/ends, results, and the pipeline scratch (~120 B per read)
+            const int64_t per_slot = o.max_batch_reads * (16 + 16 + 130);
+            const int64_t budget = free_hbm - o.hbm_reserve_bytes - per_slot * o.nstreams;
+            if (budget < (1 << 20)) return fail(SA_ENOSPC, "not enough free device memory for the server");
+            const int64_t arena_bytes = std::min<int64_t>(budget, (int64_t)16 << 30);
+            if ((e = hipMalloc((void **)&s->d_arena, (size_t)arena_bytes)) != hipSuccess)
+                return hip_fail(e, "arena allocation");
+            s->arena.init(arena_bytes);
+            if (o.host_pool_bytes > 0) {
+                if ((e = hipHostMalloc((void **)&s->h_pool, (size_t)o.host_pool_bytes, hipHostMallocDefault)) != hipSuccess)
+                    return hip_fail(e, "pinned host pool");
+                s->pool.init(o.host_pool_bytes);
+            }
+            if ((e = hipStreamCreateWithFlags(&s->upload_stream, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "stream creation");
+            for (Slot &sl : s->slots) {
+                if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
+                    (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
+                    (e = hipHostMalloc((void **)&sl.h_se, sizeof(int64_t) * 2 * (size_t)o.max_batch_reads,
+                                       hipHostMallocDefault)) != hipSuccess ||
+                    (e = hipHostMalloc((void **)&sl.h_out, sizeof(sa_hit) * (size_t)o.max_batch_reads,
+                                       hipHostMallocDefault)) != hipSuccess ||
+                    (e = hipMalloc((void **)&sl.d_se, sizeof(int64_t) * 2 * (size_t)o.max_batch_reads)) != hipSuccess ||
+                    (e = hipMalloc((void **)&sl.d_out, sizeof(sa_hit) * (size_t)o.max_batch_reads)) != hipSuccess)
+                    return hip_fail(e, "slot allocation");
+                // size every index's scratch for this stream now, not on the first batch
+                for (sa_dindex *d : s->refs) {
+                    int rc = workspace_for(d, sl.stream)->reserve(o.max_batch_reads);
+                    if (rc) return rc;
+                }
             }
         }
+        return SA_OK;
+    };
+    if (int rc = setup()) {
+        free_resources(s.get());
+        return rc;
     }
     sa_server *raw = s.get();
     s->loop = std::thread([raw] { raw->run(); });
     *out = s.release();
     return SA_OK;
+}
+
+static void release_pool(sa_server *s, Request *r) {
+    if (r->pool_off < 0) return;
+    std::lock_guard<std::mutex> pl(s->pool_mu);
+    s->pool.release(r->pool_off, r->pool_bytes);
+    r->pool_off = -1;
 }
 
 extern "C" int match_submit(sa_server *s, int ref, const char *reads, const int64_t *offs, int64_t nreads,
@@ -459,14 +538,29 @@ extern "C" int match_submit(sa_server *s, int ref, const char *reads, const int6
     r->t_submit = now_ns();
     try {
         const int64_t base = offs[0], nbytes = offs[nreads] - offs[0];
-        r->reads.assign(reads + base, reads + base + nbytes);
+        if (s->h_pool && nbytes > 0) {
+            std::lock_guard<std::mutex> pl(s->pool_mu);
+            r->pool_off = s->pool.alloc(nbytes);
+            if (r->pool_off >= 0) r->pool_bytes = nbytes;
+        }
+        if (r->pool_off >= 0) {
+            std::memcpy(s->h_pool + r->pool_off, reads + base, (size_t)nbytes);
+            r->h_reads = s->h_pool + r->pool_off;
+        } else {
+            r->reads.assign(reads + base, reads + base + nbytes);
+            r->h_reads = r->reads.data();
+        }
         r->offs.resize((size_t)nreads + 1);
         for (int64_t i = 0; i <= nreads; i++) r->offs[(size_t)i] = offs[i] - base;
     } catch (const std::bad_alloc &) {
+        release_pool(s, r.get());
         return fail(SA_ENOMEM, "request copy");
     }
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return fail(SA_ECANCELED, "server is shutting down");
+    if (s->stop) {
+        release_pool(s, r.get());
+        return fail(SA_ECANCELED, "server is shutting down");
+    }
     r->ticket = s->next_ticket++;
     *ticket = r->ticket;
     s->queued.push_back(r.get());
@@ -528,30 +622,7 @@ extern "C" int sa_server_destroy(sa_server *s) {
         for (auto &kv : s->all)
             if (kv.second->status == SA_PENDING) s->finish_locked(kv.second.get(), SA_ECANCELED);
     }
-    if (s->o.test_echo) {
-        for (Slot &sl : s->slots) delete[] sl.h_out;
-    } else {
-        DeviceGuard g(s->device);
-        for (Slot &sl : s->slots) {
-            if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-            if (sl.done) (void)hipEventDestroy(sl.done);
-            if (sl.h_se) (void)hipHostFree(sl.h_se);
-            if (sl.h_out) (void)hipHostFree(sl.h_out);
-            if (sl.d_se) (void)hipFree(sl.d_se);
-            if (sl.d_out) (void)hipFree(sl.d_out);
-            // the indexes keep a workspace per stream; drop this stream's
-            for (sa_dindex *d : s->refs) {
-                std::lock_guard<std::mutex> g2(d->mu);
-                d->ws.erase((void *)sl.stream);
-            }
-            if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        }
-        if (s->upload_stream) {
-            (void)hipStreamSynchronize(s->upload_stream);
-            (void)hipStreamDestroy(s->upload_stream);
-        }
-        if (s->d_arena) (void)hipFree(s->d_arena);
-    }
+    free_resources(s);
     delete s;
     return SA_OK;
 }

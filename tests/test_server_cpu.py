@@ -17,10 +17,12 @@ def make_request(rng, nreads, lo=1, hi=60):
     return data, offs
 
 
-def echo_expect(offs, ticket, ref):
+def echo_expect(offs, ticket, ref, data):
     n = len(offs) - 1
     lo = np.arange(n)
-    return np.stack([lo, lo + ticket, np.diff(offs), np.full(n, ref)], axis=1).astype(np.int32)
+    csum = np.add.reduceat(np.append(data.astype(np.int64), 0), offs[:-1]) if n else np.zeros(0, np.int64)
+    csum = np.where(np.diff(offs) > 0, csum, 0) & 0xFFFF
+    return np.stack([lo, lo + ticket, np.diff(offs), ref + 256 * csum], axis=1).astype(np.int32)
 
 
 def wait_all(srv, tickets, timeout_s=20.0):
@@ -44,14 +46,34 @@ def test_echo_many_requests_are_batched_and_scattered():
         data, offs = make_request(rng, int(rng.integers(0, 200)))
         ref = i % 2
         t, out = srv.submit(ref, data, offs)
-        reqs.append((t, ref, offs, out))
+        reqs.append((t, ref, data, offs, out))
     res = wait_all(srv, [r[0] for r in reqs])
-    for t, ref, offs, out in reqs:
+    for t, ref, data, offs, out in reqs:
         rc, st = res[t]
         assert rc == S.SA_OK
         assert st["t_submit_ns"] <= st["t_admit_ns"] <= st["t_done_ns"]
         assert st["nreads"] == len(offs) - 1
-        assert (out == echo_expect(offs, t, ref)).all()
+        assert (out == echo_expect(offs, t, ref, data)).all()
+    srv.destroy()
+
+
+@pytest.mark.parametrize("pool", [-1, 4096, 0])
+def test_host_pool_full_and_absent(pool):
+    """Reads reach the executor intact whether submit copies them into the
+    pinned pool, into pageable memory (pool full or absent), or both; pool
+    space comes back when requests finish."""
+    rng = np.random.default_rng(9)
+    srv = S.Server([None], test_echo=1, host_pool_bytes=pool, max_batch_reads=50, nstreams=2)
+    for _ in range(3):
+        reqs = []
+        for i in range(40):
+            data, offs = make_request(rng, int(rng.integers(0, 80)), 1, 120)
+            t, out = srv.submit(0, data, offs)
+            reqs.append((t, data, offs, out))
+        res = wait_all(srv, [r[0] for r in reqs])
+        for t, data, offs, out in reqs:
+            assert res[t][0] == S.SA_OK
+            assert (out == echo_expect(offs, t, 0, data)).all()
     srv.destroy()
 
 
@@ -66,7 +88,7 @@ def test_budget_refuses_requests_that_never_fit():
     res = wait_all(srv, [tb, ts])
     assert res[tb][0] == S.SA_ENOSPC
     assert res[ts][0] == S.SA_OK
-    assert (out == echo_expect(small_offs, ts, 0)).all()
+    assert (out == echo_expect(small_offs, ts, 0, small_data)).all()
     srv.destroy()
 
 
@@ -101,13 +123,13 @@ def test_failed_batch_only_fails_its_requests():
     for _ in range(8):
         data, offs = make_request(rng, 10)
         t, out = srv.submit(0, data, offs)
-        reqs.append((t, offs, out))
+        reqs.append((t, data, offs, out))
     res = wait_all(srv, [r[0] for r in reqs])
-    codes = [res[t][0] for t, _, _ in reqs]
+    codes = [res[t][0] for t, _, _, _ in reqs]
     assert codes.count(S.SA_EDEVICE) >= 1
-    for (t, offs, out), rc in zip(reqs, codes):
+    for (t, data, offs, out), rc in zip(reqs, codes):
         if rc == S.SA_OK:
-            assert (out == echo_expect(offs, t, 0)).all()
+            assert (out == echo_expect(offs, t, 0, data)).all()
         else:
             assert rc == S.SA_EDEVICE
     srv.destroy()
