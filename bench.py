@@ -65,8 +65,9 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: open-loop Poisson requests over resident references")
     ap.add_argument("--serve-refs", default="c2,c4", help="references kept resident for --serve")
-    ap.add_argument("--serve-requests", type=int, default=600, help="measured requests per load level")
-    ap.add_argument("--serve-warmup", type=int, default=100, help="warm-up requests per load level")
+    ap.add_argument("--serve-requests", type=int, default=4000, help="measured requests per load level")
+    ap.add_argument("--serve-warmup", type=int, default=400, help="warm-up requests per load level")
+    ap.add_argument("--serve-pool", type=int, default=800, help="distinct requests the streams draw from")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (reads shard across GPUs "
@@ -323,13 +324,15 @@ def serve_bench(args, np, torch, gen, S):
     mean_size = float(np.mean(gen.request_sizes(200_000, np.random.default_rng(7))))
     log(f"offline host-path rate on the mix: {x_off / 1e6:.1f} M reads/s; mean request {mean_size:.0f} reads")
 
+    t = time.perf_counter()
+    pool = gen.request_pool(refs, args.serve_pool)
+    log(f"{len(pool)} distinct requests ({sum(r.count for _, r in pool)} reads) generated in "
+        f"{time.perf_counter() - t:.1f}s")
     levels = []
     for k, rho in enumerate((0.5, 0.8, 0.95)):
         lam = rho * x_off / mean_size
         nreq = args.serve_warmup + args.serve_requests
-        t = time.perf_counter()
-        stream = gen.request_stream(refs, nreq, lam, seed_sub=k)
-        log(f"rho={rho}: {nreq} requests at {lam:.0f}/s generated in {time.perf_counter() - t:.1f}s")
+        stream = gen.request_stream(refs, nreq, lam, seed_sub=k, pool=pool)
         srv = S.Server(dix, max_batch_reads=1 << 20, nstreams=2)
         tickets = [None] * nreq
         sched = [0] * nreq
@@ -381,7 +384,8 @@ def serve_bench(args, np, torch, gen, S):
         "steps": len(levels), "warmup": args.serve_warmup, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic (seeded generators, no external data)",
         "config": {"workload": "c5: open-loop Poisson requests over the " + " and ".join(names) + " references, "
-                               "1-100,000 reads each (log-uniform), 30-300 bp", "requests_per_level": args.serve_requests},
+                               "1-100,000 reads each (log-uniform), 30-300 bp", "requests_per_level": args.serve_requests,
+                   "distinct_requests": args.serve_pool},
         "offline_reads_per_s": round(x_off, 1), "levels": levels,
     }
     print(json.dumps(line), flush=True)

@@ -413,13 +413,12 @@ def request_sizes(num: int, rng: np.random.Generator, max_reads: int = 100_000) 
     return np.clip(np.floor(np.exp(rng.uniform(0.0, math.log(max_reads + 1), size=num))), 1, max_reads).astype(np.int64)
 
 
-def request_stream(refs, num: int, rate_per_s: float, max_reads: int = 100_000, seed_sub: int = 0):
-    """Open-loop Poisson stream of ``num`` requests; each names reference 0 or 1
-    (p = 1/2), carries a log-uniform number of reads of 30-300 bp drawn with that
-    reference's sampling mix (c2: 30 % random, rate U[0, 0.02]; c4: 20 % random, 1 %)."""
-    rng = rng_for(5, 4, seed_sub)
-    gaps = rng.exponential(1.0 / rate_per_s, size=num)
-    times = np.cumsum(gaps) - gaps[0]
+def request_pool(refs, num: int, max_reads: int = 100_000, seed_sub: int = 0):
+    """``num`` distinct requests, as (ref, Reads): each names reference 0 or 1
+    (p = 1/2) and carries a log-uniform number of reads of 30-300 bp drawn with
+    that reference's sampling mix (c2: 30 % random, rate U[0, 0.02]; c4: 20 %
+    random, 1 %)."""
+    rng = rng_for(5, 5, seed_sub)
     which = rng.integers(0, len(refs), size=num)
     sizes = request_sizes(num, rng, max_reads)
     mixes = [ReadSpec(50, 0, 30, 300, 0.3, 0.0, 0.02), ReadSpec(51, 0, 30, 300, 0.2, 0.01, 0.01)]
@@ -428,8 +427,23 @@ def request_stream(refs, num: int, rate_per_s: float, max_reads: int = 100_000, 
         base = mixes[int(which[i]) % 2]
         spec = ReadSpec(base.cfg_id * 1_000_003 + seed_sub * 7919 + i, int(sizes[i]), 30, 300,
                         base.frac_random, base.rate_lo, base.rate_hi)
-        out.append(Request(float(times[i]), int(which[i]), make_reads(refs[int(which[i])], spec)))
+        out.append((int(which[i]), make_reads(refs[int(which[i])], spec)))
     return out
+
+
+def request_stream(refs, num: int, rate_per_s: float, max_reads: int = 100_000, seed_sub: int = 0, pool=None):
+    """Open-loop Poisson stream of ``num`` requests at ``rate_per_s``.  Without
+    ``pool`` every request is new (``request_pool`` of size ``num``); with one,
+    each arrival takes a uniformly chosen request of the pool."""
+    rng = rng_for(5, 4, seed_sub)
+    gaps = rng.exponential(1.0 / rate_per_s, size=num)
+    times = np.cumsum(gaps) - gaps[0]
+    if pool is None:
+        pool = request_pool(refs, num, max_reads, seed_sub)
+        pick = np.arange(num)
+    else:
+        pick = rng.integers(0, len(pool), size=num)
+    return [Request(float(times[i]), pool[int(pick[i])][0], pool[int(pick[i])][1]) for i in range(num)]
 
 
 def manifest(ref: Reference, reads: Reads) -> dict:

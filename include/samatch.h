@@ -108,6 +108,25 @@ int sa_upload(const sa_index *ix, int device, sa_dindex **out);
 void sa_dfree(sa_dindex *d);
 int64_t sa_dindex_length(const sa_dindex *d);
 
+/* Resident index of text[0..n) with its suffix array built on the device
+ * (the array of Section III; the paper builds it with DC3, here the device
+ * sorts suffixes by prefix doubling with radix sorts).  The result is the
+ * same array sa_build gives and the same resident index sa_upload makes
+ * from it.  Same validation and errors as sa_build; SA_EDEVICE /
+ * SA_ENOMEM when the device fails or runs out of memory (scratch about
+ * 29 bytes per base during construction, freed before returning).  The text
+ * buffer is the caller's and is not kept. */
+int sa_build_device(const char *text, int64_t n, int device, sa_dindex **out);
+
+/* Host copy (packed text and suffix array) of a resident index, e.g. to
+ * save one built on the device with sa_save.  Free with sa_free. */
+int sa_download(const sa_dindex *d, sa_index **out);
+
+/* For an index from sa_build_device: *steps = sorting rounds (the 21-base
+ * keys, then one per doubling), *sorted_pairs = (key, value) pairs sorted
+ * over all rounds.  Both 0 for an index from sa_upload.  Nullable outputs. */
+int sa_dindex_build_info(const sa_dindex *d, int *steps, int64_t *sorted_pairs);
+
 /* ------------------------------------------------------------------ batches */
 
 enum { SA_KERNEL_TUNED = 0, SA_KERNEL_PLAIN = 1 };

@@ -18,6 +18,7 @@ SOURCES = [
     "host_index.cpp",
     "dc3.cpp",
     "kernels.hip",
+    "sa_construct.hip",
     "device.hip",
     "tune.hip",
     "server.hip",
@@ -40,7 +41,7 @@ def build_id() -> str:
     """Hash of the sources: tuned launch settings are only reused for the same kernels."""
     import hashlib
     h = hashlib.sha256()
-    for s in SOURCES + ["kernels.h", "device_state.h", "internal.h"]:
+    for s in SOURCES + ["kernels.h", "radix_sort.h", "device_state.h", "internal.h"]:
         h.update(open(os.path.join(CSRC, s), "rb").read())
     return h.hexdigest()[:12]
 

@@ -238,9 +238,12 @@ int run_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t
 
 }  // namespace samatch
 
-extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
-    clear_error();
-    if (!ix || !out) return fail(SA_EINVAL, "NULL argument");
+namespace {
+
+// Device index from the packed text and either a host suffix array
+// (host_sa) or one built here on the device.
+int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, const int32_t *host_sa,
+                sa_dindex **out) {
     *out = nullptr;
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -250,29 +253,52 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
     if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
     std::unique_ptr<sa_dindex> d(new sa_dindex);
     d->device = device;
-    d->n = ix->n;
+    d->n = n;
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
     if ((e = prepare_kernels()) != hipSuccess) return hip_fail(e, "kernel attributes");
     d->cu_count = prop.multiProcessorCount;
     std::snprintf(d->arch, sizeof d->arch, "%s", prop.gcnArchName);
-    const size_t text_bytes = sizeof(uint64_t) * ix->packed.size();
-    const size_t sa_bytes = sizeof(int32_t) * (size_t)ix->n;
+    const size_t text_bytes = sizeof(uint64_t) * packed.size();
+    const size_t sa_bytes = sizeof(int32_t) * (size_t)n;
     int levels = 0;
-    while (levels < kMaxTileLevels && ((int64_t)1 << levels) - 1 < ix->n) levels++;
+    while (levels < kMaxTileLevels && ((int64_t)1 << levels) - 1 < n) levels++;
     d->tile_levels = std::max(1, levels);
     const size_t nodes = ((size_t)1 << d->tile_levels) - 1;
     if ((e = hipMalloc((void **)&d->d_text, text_bytes)) != hipSuccess ||
         (e = hipMalloc((void **)&d->d_sa, sa_bytes)) != hipSuccess ||
         (e = hipMalloc((void **)&d->d_tile_key, nodes * sizeof(uint64_t))) != hipSuccess ||
         (e = hipMalloc((void **)&d->d_tile_sa, nodes * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc((void **)&d->d_rows, sizeof(RowRec) * (size_t)ix->n)) != hipSuccess)
+        (e = hipMalloc((void **)&d->d_rows, sizeof(RowRec) * (size_t)n)) != hipSuccess)
         return hip_fail(e, "index allocation");
-    if ((e = hipMemcpy(d->d_text, ix->packed.data(), text_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(d->d_sa, ix->sa.data(), sa_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpy(d->d_text, packed.data(), text_bytes, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "index upload");
-    if ((e = launch_build_rows(d->d_text, d->d_sa, (int32_t)ix->n, d->d_rows, nullptr)) != hipSuccess ||
-        (e = launch_build_tile(d->d_text, d->d_sa, (int32_t)ix->n, d->tile_levels, d->d_tile_key, d->d_tile_sa,
+    // rows of the shortest suffixes (the last kShort text positions), as (row, length)
+    std::vector<std::pair<int32_t, int32_t>> short_rows;
+    const int64_t cut = n - kShort;
+    if (host_sa) {
+        if ((e = hipMemcpy(d->d_sa, host_sa, sa_bytes, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "index upload");
+        for (int64_t r = 0; r < n; r++)
+            if (host_sa[r] >= cut) short_rows.emplace_back((int32_t)r, (int32_t)(n - host_sa[r]));
+    } else {
+        uint32_t *rank = nullptr;
+        if ((e = hipMalloc((void **)&rank, sizeof(uint32_t) * (size_t)n)) != hipSuccess)
+            return hip_fail(e, "rank allocation");
+        int rc = build_sa_device(d->d_text, n, d->d_sa, rank, nullptr, &d->built);
+        const int64_t first = std::max<int64_t>(0, cut);
+        std::vector<uint32_t> tail((size_t)(n - first));
+        if (rc == SA_OK &&
+            (e = hipMemcpy(tail.data(), rank + first, sizeof(uint32_t) * tail.size(), hipMemcpyDeviceToHost)) !=
+                hipSuccess)
+            rc = hip_fail(e, "rank download");
+        (void)hipFree(rank);
+        if (rc) return rc;
+        for (int64_t p = first; p < n; p++)
+            short_rows.emplace_back((int32_t)(tail[(size_t)(p - first)] - 1u), (int32_t)(n - p));
+    }
+    if ((e = launch_build_rows(d->d_text, d->d_sa, (int32_t)n, d->d_rows, nullptr)) != hipSuccess ||
+        (e = launch_build_tile(d->d_text, d->d_sa, (int32_t)n, d->tile_levels, d->d_tile_key, d->d_tile_sa,
                                nullptr)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess)
         return hip_fail(e, "tile build");
@@ -282,29 +308,22 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
     v.tile_key = d->d_tile_key;
     v.tile_sa = d->d_tile_sa;
     v.rows = d->d_rows;
-    v.n = (int32_t)ix->n;
-    // rows of the shortest suffixes (the last kShort text positions)
-    {
-        std::vector<std::pair<int32_t, int32_t>> rows;  // (row, length)
-        const int64_t cut = ix->n - kShort;
-        for (int64_t r = 0; r < ix->n; r++)
-            if (ix->sa[(size_t)r] >= cut) rows.emplace_back((int32_t)r, (int32_t)(ix->n - ix->sa[(size_t)r]));
-        std::sort(rows.begin(), rows.end());
-        v.nshort = (int32_t)rows.size();
-        for (size_t i = 0; i < rows.size(); i++) {
-            v.short_row[i] = rows[i].first;
-            v.short_len[i] = rows[i].second;
-            // first 32 bases of the suffix, zero past the end
-            const int64_t p = ix->n - rows[i].second;
-            const uint64_t lo = ix->packed[(size_t)(p >> 5)], hi = ix->packed[(size_t)(p >> 5) + 1];
-            const unsigned sh = (unsigned)(p & 31) * 2u;
-            v.short_key[i] = sh ? (lo << sh) | (hi >> (64u - sh)) : lo;
-        }
+    v.n = (int32_t)n;
+    std::sort(short_rows.begin(), short_rows.end());
+    v.nshort = (int32_t)short_rows.size();
+    for (size_t i = 0; i < short_rows.size(); i++) {
+        v.short_row[i] = short_rows[i].first;
+        v.short_len[i] = short_rows[i].second;
+        // first 32 bases of the suffix, zero past the end
+        const int64_t p = n - short_rows[i].second;
+        const uint64_t lo = packed[(size_t)(p >> 5)], hi = packed[(size_t)(p >> 5) + 1];
+        const unsigned sh = (unsigned)(p & 31) * 2u;
+        v.short_key[i] = sh ? (lo << sh) | (hi >> (64u - sh)) : lo;
     }
     // prefix table over k = log4(n) rounded, at most kMaxPrefixBases bases
     int k = 0;
-    if (ix->n >= 4096) {
-        k = (int)std::lround(std::log2((double)ix->n) / 2.0);
+    if (n >= 4096) {
+        k = (int)std::lround(std::log2((double)n) / 2.0);
         k = std::max(4, std::min(kMaxPrefixBases, k));
     }
     if (k > 0) {
@@ -331,6 +350,61 @@ extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
     c.group = 4;
     c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
     *out = d.release();
+    return SA_OK;
+}
+
+}  // namespace
+
+extern "C" int sa_upload(const sa_index *ix, int device, sa_dindex **out) {
+    clear_error();
+    if (!ix || !out) return fail(SA_EINVAL, "NULL argument");
+    return make_dindex(device, ix->n, ix->packed, ix->sa.data(), out);
+}
+
+extern "C" int sa_build_device(const char *text, int64_t n, int device, sa_dindex **out) {
+    clear_error();
+    if (!out) return fail(SA_EINVAL, "NULL argument");
+    *out = nullptr;
+    int rc = check_text(text, n);
+    if (rc) return rc;
+    std::vector<uint64_t> packed;
+    try {
+        pack_text(text, n, packed);
+    } catch (const std::bad_alloc &) {
+        return fail(SA_ENOMEM, "packing");
+    }
+    return make_dindex(device, n, packed, nullptr, out);
+}
+
+extern "C" int sa_download(const sa_dindex *d, sa_index **out) {
+    clear_error();
+    if (!d || !out) return fail(SA_EINVAL, "NULL argument");
+    *out = nullptr;
+    std::unique_ptr<sa_index> ix(new (std::nothrow) sa_index);
+    if (!ix) return fail(SA_ENOMEM, "index allocation");
+    try {
+        ix->n = d->n;
+        ix->packed.assign((size_t)((d->n + 31) / 32 + kPadWords), 0);
+        ix->sa.assign((size_t)d->n, 0);
+    } catch (const std::bad_alloc &) {
+        return fail(SA_ENOMEM, "index allocation");
+    }
+    DeviceGuard g(d->device);
+    if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
+    hipError_t e;
+    if ((e = hipMemcpy(ix->packed.data(), d->d_text, sizeof(uint64_t) * ix->packed.size(), hipMemcpyDeviceToHost)) !=
+            hipSuccess ||
+        (e = hipMemcpy(ix->sa.data(), d->d_sa, sizeof(int32_t) * ix->sa.size(), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "index download");
+    *out = ix.release();
+    return SA_OK;
+}
+
+extern "C" int sa_dindex_build_info(const sa_dindex *d, int *steps, int64_t *sorted_pairs) {
+    clear_error();
+    if (!d) return fail(SA_EINVAL, "NULL argument");
+    if (steps) *steps = d->built.steps;
+    if (sorted_pairs) *sorted_pairs = d->built.sorted_elems;
     return SA_OK;
 }
 

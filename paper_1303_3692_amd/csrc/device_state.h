@@ -72,6 +72,14 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
 int run_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t *d_offs, const int64_t *d_ends,
               int64_t nreads, sa_hit *d_out, hipStream_t s, const sa_match_cfg &c);
 
+// Suffix array construction on the device (sa_construct.hip).
+struct SaBuildInfo {
+    int steps = 0;             // sorting rounds: the 21-base keys, then each doubling
+    int64_t sorted_elems = 0;  // (key, value) pairs sorted over all rounds
+};
+int build_sa_device(const uint64_t *d_text, int64_t n, int32_t *d_sa, uint32_t *rank_out, hipStream_t s,
+                    SaBuildInfo *info);
+
 }  // namespace samatch
 
 struct sa_dindex {
@@ -87,6 +95,7 @@ struct sa_dindex {
     samatch::RowRec *d_rows = nullptr;
     uint32_t *d_ptab = nullptr;
     int tile_levels = 0;  // levels stored (the kernel may use fewer)
+    samatch::SaBuildInfo built{};  // when the suffix array was built on the device
     samatch::DevIndex view{};
     sa_match_cfg defaults{};
     std::mutex mu;

@@ -21,6 +21,11 @@ uint64_t fnv1a(uint64_t h, const void *p, size_t len) {
     return h;
 }
 
+
+}  // namespace
+
+namespace samatch {
+
 int check_text(const char *text, int64_t n) {
     if (!text) return fail(SA_EINVAL, "text is NULL");
     if (n < 1) return fail(SA_EINVAL, "reference length must be at least 1");
@@ -44,7 +49,7 @@ void pack_text(const char *text, int64_t n, std::vector<uint64_t> &out) {
     }
 }
 
-}  // namespace
+}  // namespace samatch
 
 extern "C" int sa_build(const char *text, int64_t n, sa_index **out) {
     clear_error();

@@ -33,6 +33,11 @@ inline int base_code(unsigned char c) {
     }
 }
 
+// Validates a reference (1 <= n <= 2^31-1, bytes ACGT in either case).
+int check_text(const char *text, int64_t n);
+// Packs text[0..n) into ceil(n/32) + kPadWords words.
+void pack_text(const char *text, int64_t n, std::vector<uint64_t> &out);
+
 // Suffix array of s[0..n) over integer alphabet 1..K, s padded with three
 // zeros (s[n] = s[n+1] = s[n+2] = 0).  DC3 / skew construction.
 void dc3_suffix_array(const int32_t *s, int32_t *sa, int64_t n, int32_t K);

@@ -23,7 +23,8 @@ SA_KERNEL_TUNED, SA_KERNEL_PLAIN = 0, 1
 # every extern "C" symbol the header declares
 EXPORTS = [
     "sa_build", "sa_build_from_sa", "sa_index_length", "sa_index_copy_sa", "sa_save", "sa_load", "sa_free",
-    "sa_upload", "sa_dfree", "sa_dindex_length", "sa_default_cfg", "match_batch", "match_batch_dev",
+    "sa_upload", "sa_dfree", "sa_dindex_length", "sa_build_device", "sa_download", "sa_dindex_build_info",
+    "sa_default_cfg", "match_batch", "match_batch_dev",
     "sa_stage_times", "sa_probe_counts", "sa_tune",
     "sa_server_create", "match_submit", "match_poll", "sa_server_destroy", "sa_strerror", "sa_last_error",
 ]
@@ -84,6 +85,9 @@ def lib():
             "sa_upload": ([p, i32, pp], i32),
             "sa_dfree": ([p], None),
             "sa_dindex_length": ([p], i64),
+            "sa_build_device": ([p, i64, i32, pp], i32),
+            "sa_download": ([p, pp], i32),
+            "sa_dindex_build_info": ([p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)], i32),
             "sa_default_cfg": ([p, ctypes.POINTER(MatchCfg)], i32),
             "match_batch": ([p, p, p, i64, p, p, ctypes.POINTER(MatchCfg)], i32),
             "match_batch_dev": ([p, p, p, i64, p, p, ctypes.POINTER(MatchCfg)], i32),
@@ -200,6 +204,12 @@ class DIndex:
     def __len__(self) -> int:
         return int(lib().sa_dindex_length(self._p))
 
+    def build_info(self) -> dict:
+        """Suffix sorting rounds and sorted pairs when built by sa_build_device."""
+        steps, pairs = ctypes.c_int(), ctypes.c_int64()
+        _check(lib().sa_dindex_build_info(self._p, ctypes.byref(steps), ctypes.byref(pairs)), "sa_dindex_build_info")
+        return {"steps": steps.value, "sorted_pairs": pairs.value}
+
     def default_cfg(self) -> MatchCfg:
         c = MatchCfg()
         _check(lib().sa_default_cfg(self._p, ctypes.byref(c)), "sa_default_cfg")
@@ -221,6 +231,22 @@ def sa_upload(ix: Index, device: int = 0) -> DIndex:
     out = ctypes.c_void_p()
     _check(lib().sa_upload(ix.ptr, device, ctypes.byref(out)), "sa_upload")
     return DIndex(out, device)
+
+
+def sa_build_device(text, device: int = 0) -> DIndex:
+    """Resident index whose suffix array is built on the device."""
+    buf = _bytes(text)
+    out = ctypes.c_void_p()
+    _check(lib().sa_build_device(buf.ctypes.data if len(buf) else None, len(buf), device, ctypes.byref(out)),
+           "sa_build_device")
+    return DIndex(out, device)
+
+
+def sa_download(d: DIndex) -> Index:
+    """Host copy of a resident index."""
+    out = ctypes.c_void_p()
+    _check(lib().sa_download(d.ptr, ctypes.byref(out)), "sa_download")
+    return Index(out)
 
 
 def cfg(d: DIndex | None = None, **kw) -> MatchCfg:
