@@ -27,6 +27,7 @@ Bases are returned as codes 0..3 for A, C, G, T and converted to ASCII with
 """
 from __future__ import annotations
 
+import functools
 import hashlib
 import math
 from dataclasses import dataclass, field
@@ -232,7 +233,7 @@ def make_reference(cfg: str, n: int | None = None) -> Reference:
 # --------------------------------------------------------------------------- reads
 
 
-@dataclass
+@dataclass(frozen=True)
 class ReadSpec:
     cfg_id: int
     count: int
@@ -274,6 +275,7 @@ class Reads:
 CHUNK = 1 << 16
 
 
+@functools.lru_cache(maxsize=4)
 def _class_labels(spec: ReadSpec, count: int) -> np.ndarray:
     n_rand = int(round(spec.frac_random * count))
     lab = np.full(count, COPY, dtype=np.int8)
@@ -284,6 +286,7 @@ def _class_labels(spec: ReadSpec, count: int) -> np.ndarray:
     elif spec.rate_hi > 0:
         lab[n_rand:] = MUTATED
     rng_for(spec.cfg_id, 3, 0).shuffle(lab)
+    lab.setflags(write=False)  # shared between calls
     return lab
 
 
@@ -323,9 +326,9 @@ def make_reads(ref: Reference, spec: ReadSpec, count: int | None = None,
             # distinct uniform positions (the same distribution)
             m = spec.len_lo
             codes2 = np.empty((k, m), dtype=np.uint8)
-            rnd = ~src
-            codes2[rnd] = rng.integers(0, 4, size=(int(rnd.sum()), m), dtype=np.uint8)
-            codes2[src] = np.lib.stride_tricks.sliding_window_view(ref.codes, m)[pos[src]]
+            i_rnd, i_src = np.nonzero(~src)[0], np.nonzero(src)[0]
+            codes2[i_rnd] = rng.integers(0, 4, size=(len(i_rnd), m), dtype=np.uint8)
+            codes2[i_src] = np.lib.stride_tricks.sliding_window_view(ref.codes, m)[pos[i_src]]
             cnt = np.where(mut, rng.binomial(m, rates), 0)
             rows = np.repeat(np.arange(k), cnt)
             cols = rng.integers(0, m, size=len(rows))
@@ -389,6 +392,70 @@ def make_reads(ref: Reference, spec: ReadSpec, count: int | None = None,
                  np.concatenate([p[2] for p in parts]) if parts else np.zeros(0, np.int8),
                  np.concatenate([p[3] for p in parts]) if parts else np.zeros(0, np.int64),
                  np.concatenate([p[4] for p in parts]) if parts else np.zeros(0, np.int32))
+
+
+def read_offsets(spec: ReadSpec, count: int | None = None) -> np.ndarray:
+    """Offsets [count + 1] of a batch drawn by ``spec``, without the reads
+    (each chunk's lengths are its sub-stream's first draw)."""
+    count = spec.count if count is None else count
+    offs = np.zeros(count + 1, dtype=np.int64)
+    for c in range(-(-count // CHUNK)):
+        lo_i, hi_i = c * CHUNK, min((c + 1) * CHUNK, count)
+        lens = rng_for(spec.cfg_id, 3, c + 1).integers(spec.len_lo, spec.len_hi + 1, size=hi_i - lo_i)
+        offs[lo_i + 1:hi_i + 1] = lens
+    np.cumsum(offs, out=offs)
+    return offs
+
+
+_PAR = {}
+
+
+def _fill_chunks(span):
+    """Worker: write chunks [a, b) into the shared output arrays."""
+    a, b = span
+    p = _PAR
+    lo, hi = a * CHUNK, min(b * CHUNK, p["count"])
+    r = make_reads(p["ref"], p["spec"], p["count"], lo, hi)
+    o0 = p["offs"][lo]
+    p["data"][o0:o0 + len(r.data)] = r.data
+    p["cls"][lo:hi] = r.cls
+    p["pos"][lo:hi] = r.pos
+    p["first_sub"][lo:hi] = r.first_sub
+    return hi - lo
+
+
+def make_reads_parallel(ref: Reference, spec: ReadSpec, count: int | None = None, workers: int = 8) -> Reads:
+    """``make_reads`` of the whole batch, identical output, with the chunks
+    spread over forked worker processes that write into shared anonymous
+    memory.  Call it before the process starts using a GPU: the workers are
+    forks of the caller."""
+    import mmap
+    import multiprocessing as mp
+
+    count = spec.count if count is None else count
+    nchunks = -(-count // CHUNK)
+    if workers <= 1 or nchunks < 2:
+        return make_reads(ref, spec, count)
+    offs = read_offsets(spec, count)
+    _class_labels(spec, count)  # drawn once, inherited by the workers
+
+    def shared(n, dtype):
+        nbytes = max(1, n * np.dtype(dtype).itemsize)
+        return np.frombuffer(mmap.mmap(-1, nbytes), dtype=dtype)[:n]
+
+    out = {"data": shared(int(offs[-1]), np.uint8), "cls": shared(count, np.int8), "pos": shared(count, np.int64),
+           "first_sub": shared(count, np.int32)}
+    _PAR.clear()
+    _PAR.update(ref=ref, spec=spec, count=count, offs=offs, **out)
+    step = max(1, nchunks // (4 * workers))
+    spans = [(a, min(a + step, nchunks)) for a in range(0, nchunks, step)]
+    try:
+        with mp.get_context("fork").Pool(min(workers, len(spans))) as pool:
+            done = sum(pool.map(_fill_chunks, spans))
+    finally:
+        _PAR.clear()
+    assert done == count
+    return Reads(out["data"], offs, out["cls"], out["pos"], out["first_sub"])
 
 
 def workload(cfg: str, n: int | None = None, count: int | None = None):
