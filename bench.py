@@ -43,7 +43,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h"):
+    for f in ("kernels.hip", "kernels.h", "radix_sort.h"):
         h.update(open(os.path.join(ROOT, "paper_1303_3692_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a kernel of known traffic "
                          "for scaling memory counters)")
+    ap.add_argument("--gen-workers", type=int, default=8,
+                    help="processes that generate the reads (1: in this process, e.g. under a profiler)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1303_3692_amd", "tuning_cache.jsonl"),
                     help="autotuner cache (JSON lines); a hit skips the sweep")
     ap.add_argument("--serve", action="store_true",
@@ -85,7 +87,15 @@ def main():
         # inputs first: the generator forks workers, before this process uses the GPU
         t = time.perf_counter()
         ref = gen.make_reference(args.config)
-        reads = gen.make_reads_parallel(ref, gen.READ_SPECS[args.config], workers=min(8, os.cpu_count() or 1))
+        last = [time.perf_counter()]
+
+        def progress(done, count):
+            if time.perf_counter() - last[0] > 10 or done == count:
+                last[0] = time.perf_counter()
+                log(f"  reads generated: {done:,} of {count:,}")
+
+        reads = gen.make_reads_parallel(ref, gen.READ_SPECS[args.config],
+                                        workers=min(args.gen_workers, os.cpu_count() or 1), progress=progress)
         text = ref.ascii()
         log(f"workload {args.config}: n={ref.n} reads={reads.count} ({time.perf_counter() - t:.1f}s)")
 
@@ -351,7 +361,7 @@ def serve_bench(args, np, torch, gen, S):
 
         # several submitting threads (the library call releases the GIL while it copies
         # the reads), each taking every nth request at its scheduled time
-        nthreads = 4
+        nthreads = 8
 
         def submitter(part):
             for i in range(part, nreq, nthreads):

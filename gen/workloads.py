@@ -424,17 +424,19 @@ def _fill_chunks(span):
     return hi - lo
 
 
-def make_reads_parallel(ref: Reference, spec: ReadSpec, count: int | None = None, workers: int = 8) -> Reads:
+def make_reads_parallel(ref: Reference, spec: ReadSpec, count: int | None = None, workers: int = 8,
+                        progress=None) -> Reads:
     """``make_reads`` of the whole batch, identical output, with the chunks
     spread over forked worker processes that write into shared anonymous
-    memory.  Call it before the process starts using a GPU: the workers are
-    forks of the caller."""
+    memory (workers <= 1: the same spans in this process).  Call it before
+    the process starts using a GPU: the workers are forks of the caller.
+    ``progress(done, count)``, if given, is called as spans finish."""
     import mmap
     import multiprocessing as mp
 
     count = spec.count if count is None else count
     nchunks = -(-count // CHUNK)
-    if workers <= 1 or nchunks < 2:
+    if nchunks < 2:
         return make_reads(ref, spec, count)
     offs = read_offsets(spec, count)
     _class_labels(spec, count)  # drawn once, inherited by the workers
@@ -447,11 +449,30 @@ def make_reads_parallel(ref: Reference, spec: ReadSpec, count: int | None = None
            "first_sub": shared(count, np.int32)}
     _PAR.clear()
     _PAR.update(ref=ref, spec=spec, count=count, offs=offs, **out)
-    step = max(1, nchunks // (4 * workers))
+    step = max(1, nchunks // (4 * max(1, workers)))
     spans = [(a, min(a + step, nchunks)) for a in range(0, nchunks, step)]
+    done = 0
     try:
-        with mp.get_context("fork").Pool(min(workers, len(spans))) as pool:
-            done = sum(pool.map(_fill_chunks, spans))
+        if workers <= 1:
+            for sp in spans:
+                done += _fill_chunks(sp)
+                if progress:
+                    progress(done, count)
+        else:
+            # close + join: the workers finish their last task and leave on
+            # their own (no signals)
+            pool = mp.get_context("fork").Pool(min(workers, len(spans)))
+            try:
+                for n in pool.imap_unordered(_fill_chunks, spans):
+                    done += n
+                    if progress:
+                        progress(done, count)
+                pool.close()
+            except BaseException:
+                pool.terminate()
+                raise
+            finally:
+                pool.join()
     finally:
         _PAR.clear()
     assert done == count
