@@ -239,6 +239,27 @@ def main():
                       "reads_per_s": round(N * pk / pel, 1)}
         log(f"per-length: {per_length}")
 
+    # ---- locate (positions of exact reads, at most 16 per read) on this step's hits
+    loc_offs = torch.zeros(N + 1, dtype=torch.int64, device=dev)
+    try:
+        S.locate_dev(d, d_out, 16, 0, loc_offs, torch.zeros(1, dtype=torch.int32, device=dev), stream=stream)
+    except S.SaError as err:
+        if err.code != S.SA_ENOSPC:
+            raise
+    total = int(loc_offs[-1].item())
+    loc_pos = torch.zeros(max(1, total), dtype=torch.int32, device=dev)
+    S.locate_dev(d, d_out, 16, 0, loc_offs, loc_pos, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        S.locate_dev(d, d_out, 16, 0, loc_offs, loc_pos, stream=stream)
+    torch.cuda.synchronize()
+    loc_ms = (time.perf_counter() - t) / 5 * 1000
+    locate = {"cap": 16, "positions": total, "ms": round(loc_ms, 4),
+              "positions_per_s": round(total / (loc_ms * 1e-3), 1)}
+    log(f"locate: {locate}")
+    del loc_offs, loc_pos
+
     B = alg_bytes(cnt)
     achieved = B / (stages["search"] * 1e-3) / 1e9
     # HBM traffic per launch from the committed rocprofv3 counters, only when
@@ -296,6 +317,7 @@ def main():
         "speedup_vs_plain": round(value / plain["reads_per_s"], 3) if plain else None,
         "per_length": per_length,
         "speedup_vs_per_length": round(value / per_length["reads_per_s"], 3) if per_length else None,
+        "locate": locate,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

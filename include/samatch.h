@@ -199,6 +199,32 @@ int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[7]);
 int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_offs, int64_t nreads,
             void *hip_stream, const char *cache_path, sa_match_cfg *best, double *best_ms);
 
+/* ------------------------------------------------------------------ locate */
+
+/* Text positions of the occurrences (Section IV lists a read's occurrences
+ * as the suffix-array entries of its row interval).  A read is selected when
+ * its hit is exact (min_len == 0), or when its matched length h.len >=
+ * min_len (min_len > 0, which also locates the longest matched prefix of
+ * reads that do not occur).  A selected read emits SA[h.lo], SA[h.lo + 1],
+ * ... for its first min(h.hi - h.lo, cap) rows, in suffix-array order;
+ * other reads emit nothing.
+ *
+ * Device form: d_hits[nreads] as written by match_batch_dev; d_offs
+ * [nreads + 1] (int64) receives CSR offsets, so read i's positions are
+ * d_pos[d_offs[i] .. d_offs[i + 1]).  *total receives d_offs[nreads].  When
+ * *total > pos_capacity the offsets are still written, no position is, and
+ * the call returns SA_ENOSPC (call again with a buffer of *total entries).
+ * Enqueued on hip_stream; waits for it to read the total, the positions are
+ * written asynchronously after return.  SA_EINVAL for a selected hit whose
+ * interval is not inside [0, n].  Allocates a small scratch per call. */
+int sa_locate_dev(const sa_dindex *d, const sa_hit *d_hits, int64_t nreads, int32_t cap, int32_t min_len,
+                  int64_t *d_offs, int32_t *d_pos, int64_t pos_capacity, void *hip_stream, int64_t *total);
+
+/* Host form of sa_locate_dev: hits, offs and pos are host buffers; waits
+ * for completion. */
+int sa_locate(const sa_dindex *d, const sa_hit *hits, int64_t nreads, int32_t cap, int32_t min_len,
+              int64_t *offs, int32_t *pos, int64_t pos_capacity, int64_t *total);
+
 /* ------------------------------------------------------------------ serving */
 
 typedef struct {

@@ -30,3 +30,11 @@ def match(text: str, read: str) -> tuple[int, int, int, int]:
 
 def rows_of(text: str, sa: list[int], lo: int, hi: int) -> set[int]:
     return {sa[k] for k in range(lo, hi)}
+
+
+def occurrences(text: str, read: str) -> list[int]:
+    """Every text position where the read occurs, in the order of the
+    suffixes that start there."""
+    t, p = text.upper(), read.upper()
+    occ = [i for i in range(len(t)) if t.startswith(p, i)]
+    return sorted(occ, key=lambda i: t[i:])

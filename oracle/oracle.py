@@ -4,7 +4,9 @@
 construction of Section III); ``match`` runs the per-read LB / RB binary
 searches of Section IV plus the longest-matched-prefix step; ``scan_one``
 recomputes one read's result from the definitions by visiting every text
-position, without a suffix array.
+position, without a suffix array; ``locate`` lists the occurrences of each
+selected read as the suffix-array entries of its interval (Section IV lists
+the occurrences of a read that way).
 """
 from __future__ import annotations
 
@@ -114,6 +116,23 @@ def scan_one(text, read) -> tuple[int, int, int, int]:
     if lib().oracle_scan_one(t.ctypes.data, len(t), buf.ctypes.data, len(p), out.ctypes.data) != 0:
         raise ValueError("scan failed")
     return tuple(int(x) for x in out)
+
+
+def locate(sa, res, cap: int, min_len: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """CSR (offsets int64[N+1], positions int32) of each read's occurrences:
+    a read is selected when its result is exact (min_len == 0) or its matched
+    length is at least min_len (min_len > 0); a selected read lists
+    SA[lo], SA[lo+1], ... for its first min(hi - lo, cap) rows, in SA order.
+    ``res`` is ``match``'s (N, 4) output {lo, hi, l, exact}."""
+    sa = np.asarray(sa)
+    res = np.asarray(res, dtype=np.int64).reshape(-1, 4)
+    lo, hi, ln, ex = res[:, 0], res[:, 1], res[:, 2], res[:, 3]
+    sel = (ln >= min_len) if min_len > 0 else (ex != 0)
+    count = np.where(sel, np.minimum(hi - lo, cap), 0)
+    offs = np.zeros(len(res) + 1, dtype=np.int64)
+    np.cumsum(count, out=offs[1:])
+    rows = np.repeat(lo, count) + (np.arange(offs[-1]) - np.repeat(offs[:-1], count))
+    return offs, sa[rows].astype(np.int32)
 
 
 def max_threads() -> int:

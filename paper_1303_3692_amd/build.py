@@ -20,6 +20,7 @@ SOURCES = [
     "kernels.hip",
     "sa_construct.hip",
     "device.hip",
+    "locate.hip",
     "tune.hip",
     "server.hip",
 ]

@@ -12,13 +12,21 @@ constexpr int kSortBlock = 256;           // radix sort: threads per workgroup
 constexpr int kSortItems = 16;            // keys per thread per pass
 constexpr int kSortTile = kSortBlock * kSortItems;
 
-// Per SA row: first 32 bases of the suffix (zero past the text end), its
-// text position and length.
-struct alignas(16) RowRec {
-    uint64_t key;
+// Per SA row: the suffix's text position and length, then its first
+// 32 * kRecWords bases as aligned 2-bit words (zero past the text end).  A
+// probe loads the first 16 bytes (position, length, word 0) and further
+// words only while they keep matching, from the same line.
+#ifndef SAMATCH_REC_WORDS
+#define SAMATCH_REC_WORDS 7
+#endif
+constexpr int kRecWords = SAMATCH_REC_WORDS;
+static_assert(kRecWords == 1 || kRecWords == 3 || kRecWords == 7, "row records are 16, 32 or 64 bytes");
+struct alignas(8 + 8 * kRecWords) RowRec {
     int32_t pos;
     int32_t len;
+    uint64_t key[kRecWords];
 };
+static_assert(sizeof(RowRec) == 8 + 8 * kRecWords, "row record layout");
 
 // Device view of a resident index, passed to kernels by value.
 struct DevIndex {

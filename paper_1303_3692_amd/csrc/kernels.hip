@@ -40,6 +40,7 @@ struct NoCount {
     __device__ __forceinline__ void key_probe() {}
     __device__ __forceinline__ void tile_probe() {}
     __device__ __forceinline__ void text_words(uint32_t, uint32_t) {}
+    __device__ __forceinline__ void rec_word() {}
 };
 struct Count {
     uint32_t global = 0, words = 0, tile = 0, keys = 0, table = 0;
@@ -47,6 +48,7 @@ struct Count {
     __device__ __forceinline__ void global_probe() { ++global; }
     __device__ __forceinline__ void key_probe() { ++global; ++keys; }
     __device__ __forceinline__ void tile_probe() { ++tile; }
+    __device__ __forceinline__ void rec_word() { ++keys; }
     // bases [first, end) of the text were compared
     __device__ __forceinline__ void text_words(uint32_t first, uint32_t end) {
         if (end > first) words += ((end - 1) >> 5) - (first >> 5) + 1;
@@ -100,20 +102,66 @@ __device__ __forceinline__ int compare_from(const uint64_t *__restrict__ text, i
     return sign;
 }
 
-// Probe of one row whose first 32 bases (key) and text position p are in
-// hand: when fewer than 32 bases are known to match (h < 32) the key
-// decides unless it ties over all its bases with more to compare; the text
-// is read only from word 1 (or from word h/32 when h >= 32).
+// First 16 bytes of a row record: position, length, word 0 (one load).
+struct RowHead {
+    int32_t pos;
+    int32_t len;
+    uint64_t key0;
+};
+
+__device__ __forceinline__ RowHead row_head(const RowRec *__restrict__ rows, int r) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(rows + r);
+    RowHead h;
+    h.pos = (int32_t)v.x;
+    h.len = (int32_t)v.y;
+    h.key0 = ((uint64_t)v.w << 32) | v.z;
+    return h;
+}
+
+// Probe of one suffix (text position p) whose first 32 bases (key0) are in
+// hand, with h bases known to match: like compare_from, but word 0 comes
+// from key0 and words 1 .. kRecWords-1 from the row record (rec; NULL for
+// a node of the LDS tile), loaded only while the words before them tie;
+// later words come from the text.
 template <int W, class Cnt>
-__device__ __forceinline__ int compare_keyed(const DevIndex &ix, const uint64_t (&q)[W], int plen, int32_t p,
-                                             uint64_t key, int h, int &lcp, Cnt &cnt) {
-    if (h >= 32) return compare_from<W>(ix.text, ix.n, q, plen, p, h >> 5, lcp, cnt);
+__device__ __forceinline__ int compare_row(const DevIndex &ix, const uint64_t (&q)[W], int plen,
+                                           const RowRec *__restrict__ rec, int32_t p, uint64_t key0, int h,
+                                           int &lcp, Cnt &cnt) {
     const int lim = min_i(plen, ix.n - p);
-    const uint64_t x = q[0] ^ key;
-    const int mm = (int)(__clzll((long long)x) >> 1);
-    if (x != 0 && mm < lim) { lcp = mm; return q[0] > key ? 1 : -1; }
-    if (lim <= 32) { lcp = lim; return lim == plen ? 0 : 1; }
-    return compare_from<W>(ix.text, ix.n, q, plen, p, 1, lcp, cnt);
+    const int k0 = h >> 5;
+    int res = lim;
+    int sign = (lim == plen) ? 0 : 1;
+    bool done = false;
+    uint32_t text_first = 0, text_end = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        if (!done && k >= k0 && (k << 5) < lim) {
+            uint64_t t;
+            if (k == 0) {
+                t = key0;
+            } else if (rec != nullptr && k < kRecWords) {
+                t = reinterpret_cast<const uint64_t *>(rec)[1 + k];  // word k of the record
+                cnt.rec_word();
+            } else {
+                t = text_word(ix.text, (uint32_t)p + ((uint32_t)k << 5));
+                if (text_end == 0) text_first = (uint32_t)p + ((uint32_t)k << 5);
+                text_end = (uint32_t)p + (uint32_t)min_i(lim, (k << 5) + 32);
+            }
+            const uint64_t x = q[k] ^ t;
+            if (x) {
+                const int mm = (k << 5) + (int)(__clzll((long long)x) >> 1);
+                if (mm < lim) {
+                    res = mm;
+                    sign = q[k] > t ? 1 : -1;
+                }
+                done = true;
+                if (text_end) text_end = (uint32_t)p + (uint32_t)min_i(lim, mm + 1);
+            }
+        }
+    }
+    lcp = res;
+    cnt.text_words(text_first, text_end);
+    return sign;
 }
 
 __device__ __forceinline__ int midpoint(int L, int R) {
@@ -131,10 +179,10 @@ __device__ __forceinline__ int bounded_search(const DevIndex &ix, const uint64_t
                               int lcpL, int lcpR, Cnt &cnt) {
     while (R > L + 1) {
         const int piv = midpoint(L, R);
-        const RowRec row = ix.rows[piv];
+        const RowHead row = row_head(ix.rows, piv);
         int lcp;
         cnt.key_probe();
-        const int sign = compare_keyed<W>(ix, q, plen, row.pos, row.key, min_i(lcpL, lcpR), lcp, cnt);
+        const int sign = compare_row<W>(ix, q, plen, ix.rows + piv, row.pos, row.key0, min_i(lcpL, lcpR), lcp, cnt);
         const bool go_left = UPPER ? (sign < 0) : (sign <= 0);
         if (go_left) { R = piv; lcpR = lcp; }
         else { L = piv; lcpL = lcp; }
@@ -177,17 +225,18 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
         const int32_t p = s_sa[node];
         int lcp;
         cnt.tile_probe();
-        const int sign = compare_keyed<W>(ix, q, plen, p, key, min_i(st.lcpL, st.lcpR), lcp, cnt);
+        const int sign = compare_row<W>(ix, q, plen, nullptr, p, key, min_i(st.lcpL, st.lcpR), lcp, cnt);
         const int piv = midpoint(st.L, st.R);
         lb_update(st, sign, piv, lcp);
         node = 2 * node + (sign <= 0 ? 1 : 2);
     }
     while (st.R > st.L + 1) {
         const int piv = midpoint(st.L, st.R);
-        const RowRec row = ix.rows[piv];
+        const RowHead row = row_head(ix.rows, piv);
         int lcp;
         cnt.key_probe();
-        const int sign = compare_keyed<W>(ix, q, plen, row.pos, row.key, min_i(st.lcpL, st.lcpR), lcp, cnt);
+        const int sign =
+            compare_row<W>(ix, q, plen, ix.rows + piv, row.pos, row.key0, min_i(st.lcpL, st.lcpR), lcp, cnt);
         lb_update(st, sign, piv, lcp);
     }
 }
@@ -238,20 +287,21 @@ __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const uint64
     if (hi_k == lo_k) {
         const int rl = st.L >= 0 ? st.L : 0;
         const int rr = st.R < ix.n ? st.R : ix.n - 1;
-        const RowRec xl = ix.rows[rl], xr = ix.rows[rr];
+        const RowHead xl = row_head(ix.rows, rl), xr = row_head(ix.rows, rr);
         int a = 0, c = 0;
-        if (st.L >= 0) { cnt.key_probe(); compare_keyed<W>(ix, q, plen, xl.pos, xl.key, 0, a, cnt); }
-        if (st.R < ix.n) { cnt.key_probe(); compare_keyed<W>(ix, q, plen, xr.pos, xr.key, 0, c, cnt); }
+        if (st.L >= 0) { cnt.key_probe(); compare_row<W>(ix, q, plen, ix.rows + rl, xl.pos, xl.key0, 0, a, cnt); }
+        if (st.R < ix.n) { cnt.key_probe(); compare_row<W>(ix, q, plen, ix.rows + rr, xr.pos, xr.key0, 0, c, cnt); }
         st.lcpL = a;
         st.lcpR = c;
         return true;
     }
     while (st.R > st.L + 1) {
         const int piv = midpoint(st.L, st.R);
-        const RowRec row = ix.rows[piv];
+        const RowHead row = row_head(ix.rows, piv);
         int lcp;
         cnt.key_probe();
-        const int sign = compare_keyed<W>(ix, q, plen, row.pos, row.key, min_i(st.lcpL, st.lcpR), lcp, cnt);
+        const int sign =
+            compare_row<W>(ix, q, plen, ix.rows + piv, row.pos, row.key0, min_i(st.lcpL, st.lcpR), lcp, cnt);
         lb_update(st, sign, piv, lcp);
     }
     return true;
@@ -326,18 +376,19 @@ __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 
 // ------------------------------------------------------------------ row keys
 
-// One 16-byte record per SA row: the first 32 bases of the row's suffix
-// (zero past the text end) and the suffix's text position, so that a probe
-// fetches both with one load.
+// One record per SA row: the suffix's text position and length and its
+// first 32 * kRecWords bases (zero past the text end), so that a probe
+// fetches position and bases from one line.
 __global__ void build_rows_kernel(const uint64_t *__restrict__ text, const int32_t *__restrict__ sa, int32_t n,
                                   RowRec *__restrict__ rows) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const int32_t p = sa[r];
     RowRec rec;
-    rec.key = text_word(text, (uint32_t)p);
     rec.pos = p;
     rec.len = n - p;
+#pragma unroll
+    for (int k = 0; k < kRecWords; ++k) rec.key[k] = text_word(text, (uint32_t)p + ((uint32_t)k << 5));
     rows[r] = rec;
 }
 
@@ -348,8 +399,8 @@ __global__ void build_rows_kernel(const uint64_t *__restrict__ text, const int32
 // sorts before every k-base string it is a proper prefix of).  It does not
 // decrease along the suffix array.
 __device__ __forceinline__ uint64_t row_order_key(const DevIndex &ix, int k, int r) {
-    const RowRec row = ix.rows[r];
-    return 2 * (row.key >> (64 - 2 * k)) + (row.len >= k ? 1u : 0u);
+    const RowHead row = row_head(ix.rows, r);
+    return 2 * (row.key0 >> (64 - 2 * k)) + (row.len >= k ? 1u : 0u);
 }
 
 // T[v] = first row whose order key reaches 2v + 1 (binary search per entry).

@@ -26,6 +26,7 @@ EXPORTS = [
     "sa_upload", "sa_dfree", "sa_dindex_length", "sa_build_device", "sa_download", "sa_dindex_build_info",
     "sa_default_cfg", "match_batch", "match_batch_dev",
     "sa_stage_times", "sa_probe_counts", "sa_tune",
+    "sa_locate_dev", "sa_locate",
     "sa_server_create", "match_submit", "match_poll", "sa_server_destroy", "sa_strerror", "sa_last_error",
 ]
 
@@ -94,6 +95,8 @@ def lib():
             "sa_stage_times": ([p, p, ctypes.POINTER(ctypes.c_double)], i32),
             "sa_probe_counts": ([p, p, ctypes.POINTER(ctypes.c_int64)], i32),
             "sa_tune": ([p, p, p, i64, p, ctypes.c_char_p, ctypes.POINTER(MatchCfg), ctypes.POINTER(ctypes.c_double)], i32),
+            "sa_locate_dev": ([p, p, i64, i32, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_int64)], i32),
+            "sa_locate": ([p, p, i64, i32, i32, p, p, i64, ctypes.POINTER(ctypes.c_int64)], i32),
             "sa_server_create": ([ctypes.POINTER(ctypes.c_void_p), i32, ctypes.POINTER(ServerOpts), pp], i32),
             "match_submit": ([p, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_uint64)], i32),
             "match_poll": ([p, ctypes.c_uint64, i64, ctypes.POINTER(ReqStats)], i32),
@@ -301,6 +304,36 @@ def sa_probe_counts(d: DIndex, stream=None) -> dict:
     _check(lib().sa_probe_counts(d.ptr, _stream_handle(stream), c), "sa_probe_counts")
     return {"global_probes": c[0], "text_words": c[1], "tile_probes": c[2], "reads": c[3], "query_words": c[4],
             "key_words": c[5], "table_lookups": c[6]}
+
+
+def locate(d: DIndex, hits, cap: int, min_len: int = 0):
+    """Host locate: (offs int64[N+1], positions int32[offs[-1]]) for hits (N, 4)."""
+    hits = np.ascontiguousarray(hits, dtype=np.int32).reshape(-1, 4)
+    n = len(hits)
+    offs = np.zeros(n + 1, dtype=np.int64)
+    total = ctypes.c_int64()
+    hp = hits.ctypes.data if n else None
+    rc = lib().sa_locate(d.ptr, hp, n, cap, min_len, offs.ctypes.data, None, 0, ctypes.byref(total))
+    if rc != SA_ENOSPC:
+        _check(rc, "sa_locate")
+    pos = np.zeros(max(total.value, 1), dtype=np.int32)
+    if total.value:
+        _check(lib().sa_locate(d.ptr, hp, n, cap, min_len, offs.ctypes.data, pos.ctypes.data, total.value,
+                               ctypes.byref(total)), "sa_locate")
+    return offs, pos[:total.value]
+
+
+def locate_dev(d: DIndex, d_hits, cap: int, min_len: int, d_offs, d_pos, nreads: int | None = None,
+               stream=None) -> int:
+    """Device locate into torch buffers; returns the total (SaError SA_ENOSPC
+    when d_pos is too small: the offsets are written regardless)."""
+    n = d_hits.shape[0] if nreads is None else nreads
+    total = ctypes.c_int64()
+    cap_pos = d_pos.numel() if d_pos is not None else 0
+    _check(lib().sa_locate_dev(d.ptr, d_hits.data_ptr(), n, cap, min_len, d_offs.data_ptr(),
+                               d_pos.data_ptr() if d_pos is not None else None, cap_pos, _stream_handle(stream),
+                               ctypes.byref(total)), "sa_locate_dev")
+    return total.value
 
 
 def sa_tune(d: DIndex, d_reads, d_offs, nreads: int | None = None, stream=None, cache_path: str | None = None):

@@ -69,6 +69,47 @@ def test_section4_occurrences(sa_example):
     assert sorted(sa_example[lo:hi]) == sorted(P["occ"]["a"])
 
 
+def test_section4_locate_lists_occurrences_in_printed_order(sa_example):
+    """Section IV prints the positions of P = a as 9, 0, 5: the SA entries of
+    its interval in row order."""
+    data, offs = oracle.pack_reads(["a", "ggtac", "tt"])
+    res = oracle.match(T, sa_example, data, offs)
+    loffs, pos = oracle.locate(sa_example, res, cap=100)
+    assert list(pos[loffs[0]:loffs[1]]) == P["occ"]["a"]
+    assert list(pos[loffs[1]:loffs[2]]) == [2]
+    assert loffs[3] == loffs[2]  # "tt" does not occur: nothing listed
+    loffs, pos = oracle.locate(sa_example, res, cap=2)
+    assert list(pos[loffs[0]:loffs[1]]) == P["occ"]["a"][:2]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_locate_against_brute(seed):
+    """Exact reads list every occurrence in suffix order (cap permitting);
+    with min_len, reads that do not occur list the occurrences of their
+    longest matched prefix."""
+    rng = random.Random(seed)
+    text = "".join(rng.choice("AC" if seed % 2 else "ACGT") for _ in range(rng.randint(1, 60)))
+    sa = oracle.sa_build(text)
+    reads = []
+    for _ in range(80):
+        i = rng.randrange(len(text))
+        r = text[i:i + rng.randint(0, 8)]
+        if rng.random() < 0.4 and r:
+            j = rng.randrange(len(r))
+            r = r[:j] + rng.choice("ACGT") + r[j + 1:]
+        reads.append(r)
+    data, offs = oracle.pack_reads(reads)
+    res = oracle.match(text, sa, data, offs)
+    for cap in (1, 3, 1000):
+        for min_len in (0, 1, 3):
+            loffs, pos = oracle.locate(sa, res, cap=cap, min_len=min_len)
+            for k, r in enumerate(reads):
+                lo, hi, ln, ex = res[k]
+                sel = ln >= min_len if min_len else ex == 1
+                want = brute.occurrences(text, r[:ln])[:cap] if sel else []
+                assert list(pos[loffs[k]:loffs[k + 1]]) == want, (text, r, cap, min_len)
+
+
 # --------------------------------------------------------------- brute force
 
 
