@@ -50,8 +50,11 @@ enum {
     SA_ENOTFOUND = -10     /* unknown ticket                                  */
 };
 
-/* Longest read the search kernels take (10 packed 64-bit words). */
-#define SA_MAX_READ 320
+/* Longest read the search kernels take (32 packed 64-bit words: the
+ * paper's 1024-base queries, Section V).  Reads of up to 320 bases are
+ * searched with their words in registers; longer ones are packed into LDS
+ * and searched from there by a kernel of their own. */
+#define SA_MAX_READ 1024
 
 typedef struct sa_index sa_index;     /* host index: n, 2-bit packed text, int32 SA */
 typedef struct sa_dindex sa_dindex;   /* the same index resident in device memory    */
@@ -140,7 +143,7 @@ typedef struct {
     int blocks_per_cu;   /* tuned: persistent workgroups per compute unit          */
     int nbuckets;        /* tuned: length buckets (1..8)                           */
     int bucket_edge[8];  /* tuned: bucket b holds reads with m <= bucket_edge[b];
-                            ascending multiples of 32, last one >= SA_MAX_READ    */
+                            ascending; the last bucket takes every longer read   */
     int sort;            /* tuned: 1 = sort reads by prefix first, 0 = input order */
     int use_graph;       /* 1 = match_batch_dev replays the batch's launch sequence
                             as a hipGraph captured on first use for the same

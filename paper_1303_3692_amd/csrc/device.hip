@@ -165,7 +165,9 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
     e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bucket_table(c), s);
     if (e != hipSuccess) return hip_fail(e, "pack launch");
     if (prof && (e = hipEventRecord(ws->ev[1], s)) != hipSuccess) return hip_fail(e, "event record");
-    const uint32_t *order = nullptr;
+    const uint32_t *order = nullptr, *sorted_key = nullptr;
+    int key_shift = 0;
+    uint32_t key_mask = 0;
     if (c.kernel == SA_KERNEL_TUNED && c.sort) {
         // The key is (length bucket << 24 | first 12 bases).  Prefix bits
         // beyond about one group per 64-read chunk put no more lanes on
@@ -174,9 +176,15 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         int pbits = 8;
         while (pbits < 24 && ((int64_t)1 << pbits) < nreads / 64) pbits += 8;
         int which = 0;
-        e = launch_sort(ws->b, nreads, 24 - pbits, c.nbuckets > 1 ? 32 : 24, &which, s);
+        const int lo_bit = 24 - pbits, hi_bit = c.nbuckets > 1 ? 32 : 24;
+        e = launch_sort(ws->b, nreads, lo_bit, hi_bit, &which, s);
         if (e != hipSuccess) return hip_fail(e, "sort launch");
-        order = ws->b.val[which];
+        if (nreads > 1) {
+            order = ws->b.val[which];
+            sorted_key = ws->b.key[which];
+            key_shift = lo_bit;
+            key_mask = hi_bit - lo_bit >= 32 ? 0xFFFFFFFFu : ((1u << (hi_bit - lo_bit)) - 1u);
+        }
     }
     if (prof && (e = hipEventRecord(ws->ev[2], s)) != hipSuccess) return hip_fail(e, "event record");
     if (c.kernel == SA_KERNEL_PLAIN) {
@@ -188,6 +196,11 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
                                 d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
+    // reads longer than kShortMax: their own kernel, over the tail of the sorted order
+    const uint32_t long_field = (long_read_key(c.nbuckets) >> key_shift) & key_mask;
+    e = launch_search_long(d->view, d_reads, d_offs, ws->b, order, sorted_key, key_shift, key_mask, long_field,
+                           c.prefix_table, std::max(1, d->cu_count * 8), nreads, d_out, c.count != 0, s);
+    if (e != hipSuccess) return hip_fail(e, "long-read search launch");
     if (prof && (e = hipEventRecord(ws->ev[3], s)) != hipSuccess) return hip_fail(e, "event record");
     ws->profiled = prof;
     ws->counted = c.count != 0;

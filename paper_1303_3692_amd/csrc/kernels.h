@@ -4,9 +4,13 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "samatch.h"
+
 namespace samatch {
 
-constexpr int kWMax = 10;                 // packed words per read slot (SA_MAX_READ / 32)
+constexpr int kWMax = 10;                 // packed words per read slot of the short-read path
+constexpr int kShortMax = kWMax * 32;     // longest read of the short-read path (320 bases)
+constexpr int kLongWords = SA_MAX_READ / 32;  // words of a read on the long-read path
 constexpr int kMaxTileLevels = 13;        // 8191 nodes x 12 B = 96 KiB of LDS
 constexpr int kSortBlock = 256;           // radix sort: threads per workgroup
 constexpr int kSortItems = 16;            // keys per thread per pass
@@ -95,6 +99,20 @@ hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int use_tabl
 
 hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_t nreads,
                                void *out, bool count, hipStream_t s);
+
+// Reads of kShortMax + 1 .. SA_MAX_READ bases (pack marks them, the kernels
+// above skip them): packed in LDS by one wave per 64 reads and searched from
+// there.  order / sorted_key: the sort's result (NULL when unsorted); the
+// long reads sort last, from the first row whose key bits
+// [key_shift, key_shift + bits(key_mask)) reach long_field.
+// Read i starts at reads[offs[i]] (offs holds the start array in gather mode).
+hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b, const uint32_t *order, const uint32_t *sorted_key,
+                              int key_shift, uint32_t key_mask, uint32_t long_field, int use_table, int grid,
+                              int64_t nreads, void *out, bool count, hipStream_t s);
+
+// Sort key of a long read: the last bucket and an all-ones prefix, so that
+// long reads sort after every other read.
+__host__ __device__ inline uint32_t long_read_key(int nbuckets) { return ((uint32_t)(nbuckets - 1) << 24) | 0xFFFFFFu; }
 
 // Dynamic LDS bytes of the tuned kernel for a tile depth.
 inline size_t tile_lds_bytes(int levels) {

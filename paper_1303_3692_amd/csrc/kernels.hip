@@ -24,7 +24,6 @@ namespace {
 
 constexpr uint32_t kHitExact = 1u;
 constexpr uint32_t kHitTooLong = 2u;
-constexpr int kMaxRead = kWMax * 32;
 
 // ------------------------------------------------------------------ helpers
 
@@ -123,8 +122,8 @@ __device__ __forceinline__ RowHead row_head(const RowRec *__restrict__ rows, int
 // from key0 and words 1 .. kRecWords-1 from the row record (rec; NULL for
 // a node of the LDS tile), loaded only while the words before them tie;
 // later words come from the text.
-template <int W, class Cnt>
-__device__ __forceinline__ int compare_row(const DevIndex &ix, const uint64_t (&q)[W], int plen,
+template <int W, class Q, class Cnt>
+__device__ __forceinline__ int compare_row(const DevIndex &ix, const Q &q, int plen,
                                            const RowRec *__restrict__ rec, int32_t p, uint64_t key0, int h,
                                            int &lcp, Cnt &cnt) {
     const int lim = min_i(plen, ix.n - p);
@@ -174,8 +173,8 @@ __device__ __forceinline__ int midpoint(int L, int R) {
 // starts comparing at that word.  UPPER = false: first row whose suffix is
 // not below P[0..plen) (LB); UPPER = true: first row strictly above every
 // extension of P[0..plen) (RB + 1).
-template <int W, bool UPPER, class Cnt>
-__device__ __forceinline__ int bounded_search(const DevIndex &ix, const uint64_t (&q)[W], int plen, int L, int R,
+template <int W, bool UPPER, class Q, class Cnt>
+__device__ __forceinline__ int bounded_search(const DevIndex &ix, const Q &q, int plen, int L, int R,
                               int lcpL, int lcpR, Cnt &cnt) {
     while (R > L + 1) {
         const int piv = midpoint(L, R);
@@ -214,9 +213,9 @@ __device__ __forceinline__ void lb_update(LbState &st, int sign, int piv, int lc
 // from (-1, n) visit nodes of one fixed implicit binary tree; their pivot
 // suffixes (first 32 bases and text position) sit in LDS.  A probe that
 // ties on all 32 staged bases continues in global memory at word 1.
-template <int W, class Cnt>
+template <int W, class Q, class Cnt>
 __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
-                          const uint64_t (&q)[W], int plen, LbState &st, Cnt &cnt) {
+                          const Q &q, int plen, LbState &st, Cnt &cnt) {
     st.L = -1; st.R = ix.n; st.lcpL = 0; st.lcpR = 0;
     st.Llt = -1; st.lcpLlt = 0; st.Rlt = ix.n; st.lcpRlt = 0;
     int node = 0;
@@ -273,8 +272,8 @@ __device__ __forceinline__ int short_at(const DevIndex &ix, int row) {
 // bound inside, the other bound's common-prefix length (below k) never
 // decides anything and starts as 0; when the bracket is empty, both
 // neighbours are probed for their exact common-prefix lengths.
-template <int W, class Cnt>
-__device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const uint64_t (&q)[W], int plen, LbState &st,
+template <int W, class Q, class Cnt>
+__device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, int plen, LbState &st,
                                                 Cnt &cnt) {
     const int K = ix.ptab_k;
     const uint32_t v = (uint32_t)(q[0] >> (64 - 2 * K));
@@ -343,9 +342,9 @@ __device__ __forceinline__ void table_interval(const DevIndex &ix, uint64_t q0, 
 // search confined to (LB, Rlt]; other reads take the longest matched prefix
 // l = max(lcpL, lcpR) from the two rows around the insertion point and find
 // the interval of P[0..l) inside the bounds the LB search already bracketed.
-template <int W, class Cnt>
+template <int W, class Q, class Cnt>
 __device__ __forceinline__ int4 match_read(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
-                           bool use_table, const uint64_t (&q)[W], int m, int mv, Cnt &cnt) {
+                           bool use_table, const Q &q, int m, int mv, Cnt &cnt) {
     LbState st;
     const bool via_table = use_table && ix.ptab_k > 0 && mv >= ix.ptab_k && lb_search_table<W>(ix, q, mv, st, cnt);
     if (!via_table) lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, cnt);
@@ -570,7 +569,10 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
     if (i < nreads) {
         const int64_t a = offs[i], e = ends ? ends[i] : offs[i + 1];
         const int64_t m64 = e - a;
-        if (m64 >= 0 && m64 <= kMaxRead) {
+        if (m64 > kShortMax && m64 <= SA_MAX_READ) {
+            m = (int)m64;  // long read: packed and searched by the long-read kernel
+            mv = -1;
+        } else if (m64 >= 0 && m64 <= kShortMax) {
             m = (int)m64;
             mv = m;
             if (staged && a >= span0 && e <= span1) {
@@ -615,7 +617,9 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
         for (int t = 0; t < kWMax; ++t)
             if (t < nw) slots[threadIdx.x * kWMax + t] = w[t];
         b.qlm[i] = make_int2(m, mv);
-        if (m >= 0) {
+        if (m >= 0 && mv < 0) {
+            b.key[0][i] = long_read_key(bt.count);
+        } else if (m >= 0) {
             int bucket = bt.count - 1;
             for (int j = 0; j < bt.count; ++j)
                 if (m <= bt.edge[j]) { bucket = j; break; }
@@ -706,12 +710,13 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         const int rid = active ? (order ? (int)order[j] : (int)j) : 0;
         const int2 lm = active ? b.qlm[rid] : make_int2(0, 0);
         const int m = lm.x;
+        const bool short_read = active && !(m >= 0 && lm.y < 0);  // long reads are the long kernel's
         const int w = max_i(1, (m + 31) >> 5);
         int wc = 1;
 #pragma unroll
         for (int t = 2; t <= kWMax; ++t)
-            if (wave_ballot(active && w >= t)) wc = t;
-        if (!active) continue;
+            if (wave_ballot(short_read && w >= t)) wc = t;
+        if (!short_read) continue;
         if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
         switch (wc) {
             case 1: tuned_one<1>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
@@ -764,7 +769,8 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
     int4 res = make_int4(0, 0, 0, (int)kHitTooLong);
     const int2 lm = i < nreads ? b.qlm[i] : make_int2(-1, 0);
     const int m = lm.x;
-    if (m >= 0) {
+    const bool long_read = m >= 0 && lm.y < 0;  // the long kernel's
+    if (m >= 0 && !long_read) {
         const int mv = lm.y;
         uint64_t q[kWMax];
         const uint64_t *src = b.qw + (size_t)i * kWMax;
@@ -791,12 +797,12 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
                             l == m ? (int)kHitExact : 0);
         }
     }
-    if (i < nreads) out[i] = res;
+    if (i < nreads && !long_read) out[i] = res;
     if constexpr (COUNT) {
         wave_add(&b.stats[0], cnt.global);
         wave_add(&b.stats[1], cnt.words);
-        wave_add(&b.stats[3], m >= 0 ? 1u : 0u);
-        wave_add(&b.stats[4], m >= 0 ? (uint32_t)max_i(1, (m + 31) >> 5) : 0u);
+        wave_add(&b.stats[3], m >= 0 && !long_read ? 1u : 0u);
+        wave_add(&b.stats[4], m >= 0 && !long_read ? (uint32_t)max_i(1, (m + 31) >> 5) : 0u);
     }
 }
 
@@ -813,6 +819,111 @@ hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int
     hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, use_table,
                        group, b, order, nreads, out);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ long reads
+
+// Query words in LDS, read on demand by the comparisons.
+struct LdsQuery {
+    const uint64_t *p;
+    __device__ __forceinline__ uint64_t operator[](int k) const { return p[k]; }
+};
+
+// One wave per workgroup.  Long reads sort last: each workgroup finds where
+// they start, then takes 64-row chunks from there.  For every long read of
+// a chunk the whole wave packs it into that lane's LDS slot, 16 bases per
+// lane from aligned dword loads (an aligned dword holding a byte of the
+// read never crosses a page); then each lane searches its own read with
+// the query read from LDS.
+template <bool COUNT>
+__global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint8_t *__restrict__ reads,
+                                                         const int64_t *__restrict__ offs, BatchBuffers b,
+                                                         const uint32_t *__restrict__ order,
+                                                         const uint32_t *__restrict__ sorted_key, int key_shift,
+                                                         uint32_t key_mask, uint32_t long_field, int use_table_i,
+                                                         int64_t nreads, int4 *__restrict__ out) {
+    __shared__ uint64_t slot[64][kLongWords];
+    __shared__ int64_t s_first;
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+        int64_t lo = 0, hi = nreads;  // first sorted row whose key field reaches long_field
+        if (sorted_key) {
+            while (lo < hi) {
+                const int64_t mid = lo + ((hi - lo) >> 1);
+                if (((sorted_key[mid] >> key_shift) & key_mask) >= long_field) hi = mid;
+                else lo = mid + 1;
+            }
+        }
+        s_first = lo;
+    }
+    __syncthreads();
+    const int64_t first = s_first;
+    const int64_t nchunks = (nreads - first + 63) >> 6;
+    using Cnt = typename std::conditional<COUNT, Count, NoCount>::type;
+    Cnt cnt;
+    uint32_t nsearched = 0, nqwords = 0;
+    const bool use_table = use_table_i != 0;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t j = first + (c << 6) + lane;
+        const bool act = j < nreads;
+        const int rid = act ? (order ? (int)order[j] : (int)j) : 0;
+        const int2 lm = act ? b.qlm[rid] : make_int2(-1, 0);
+        const bool is_long = act && lm.x >= 0 && lm.y < 0;
+        uint64_t todo = wave_ballot(is_long);
+        if (!todo) continue;
+        int mv_mine = lm.x;
+        while (todo) {
+            const int src = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int r = __shfl(rid, src, 64);
+            const int m = __shfl(lm.x, src, 64);
+            const int64_t a = offs[r];
+            const int b0 = 16 * lane;
+            uint32_t half = 0;
+            int bad_at = 0x7FFFFFFF;
+            if (b0 < m) {
+                const uintptr_t x0 = (uintptr_t)(reads + a + b0);
+                const uintptr_t base = x0 & ~(uintptr_t)3;
+                const uint32_t sh = (uint32_t)(x0 & 3u);
+                const uintptr_t stop = (uintptr_t)(reads + a + m);
+                uint32_t dw[5];
+#pragma unroll
+                for (int t = 0; t < 5; ++t)
+                    dw[t] = base + 4u * t < stop ? *reinterpret_cast<const uint32_t *>(base + 4u * t) : 0u;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int rem = m - b0 - 4 * jj;
+                    const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : (rem > 0 ? ((1u << (8 * rem)) - 1u) : 0u);
+                    uint32_t bad;
+                    const uint32_t b8 = pack4_fast(__builtin_amdgcn_alignbyte(dw[jj + 1], dw[jj], sh), keep, bad);
+                    if (bad && bad_at == 0x7FFFFFFF) bad_at = b0 + 4 * jj + (int)(__builtin_ctz(bad) >> 3);
+                    half = (half << 8) | b8;
+                }
+            }
+            // bases 32k .. 32k+15 (lane 2k) are the high half of word k
+            reinterpret_cast<uint32_t *>(&slot[src][lane >> 1])[(lane & 1) ? 0 : 1] = half;
+            int first_bad = bad_at;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) first_bad = min_i(first_bad, __shfl_xor(first_bad, o, 64));
+            if (lane == src) mv_mine = min_i(m, first_bad);
+        }
+        __syncthreads();  // the slots are written; one wave, so this orders LDS only
+        if (is_long) {
+            const LdsQuery q{slot[lane]};
+            if (COUNT) { nsearched++; nqwords += (uint32_t)((lm.x + 31) >> 5); }
+            out[rid] = match_read<kLongWords>(ix, nullptr, nullptr, 0, use_table, q, lm.x, mv_mine, cnt);
+        }
+        __syncthreads();  // before the next chunk rewrites the slots
+    }
+    if constexpr (COUNT) {
+        wave_add(&b.stats[0], cnt.global);
+        wave_add(&b.stats[1], cnt.words);
+        wave_add(&b.stats[2], cnt.tile);
+        wave_add(&b.stats[3], nsearched);
+        wave_add(&b.stats[4], nqwords);
+        wave_add(&b.stats[5], cnt.keys);
+        wave_add(&b.stats[6], cnt.table);
+    }
 }
 
 }  // namespace
@@ -871,6 +982,20 @@ hipError_t launch_build_prefix_table(const DevIndex &ix, int k, uint32_t *tab, h
     const int64_t entries = ((int64_t)1 << (2 * k)) + 1;
     hipLaunchKernelGGL(build_prefix_table_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix, k,
                        entries, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b, const uint32_t *order, const uint32_t *sorted_key,
+                              int key_shift, uint32_t key_mask, uint32_t long_field, int use_table, int grid,
+                              int64_t nreads, void *out, bool count, hipStream_t s) {
+    int4 *o = static_cast<int4 *>(out);
+    const dim3 g((unsigned)(grid > 0 ? grid : 1));
+    if (count)
+        hipLaunchKernelGGL(search_long_kernel<true>, g, dim3(64), 0, s, ix, reads, offs, b, order, sorted_key,
+                           key_shift, key_mask, long_field, use_table, nreads, o);
+    else
+        hipLaunchKernelGGL(search_long_kernel<false>, g, dim3(64), 0, s, ix, reads, offs, b, order, sorted_key,
+                           key_shift, key_mask, long_field, use_table, nreads, o);
     return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsamatch.so")
 SA_OK, SA_PENDING = 0, 1
 SA_EINVAL, SA_EALPHABET, SA_ETOOBIG, SA_ENOMEM, SA_EDEVICE = -1, -2, -3, -4, -5
 SA_ENOSPC, SA_ECANCELED, SA_EIO, SA_EFORMAT, SA_ENOTFOUND = -6, -7, -8, -9, -10
-SA_MAX_READ = 320
+SA_MAX_READ = 1024
 SA_HIT_EXACT, SA_HIT_TOOLONG = 1, 2
 SA_KERNEL_TUNED, SA_KERNEL_PLAIN = 0, 1
 

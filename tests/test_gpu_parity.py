@@ -129,25 +129,36 @@ def test_long_and_too_long_reads(device):
     text = ref.ascii().tobytes().decode()
     rng = np.random.default_rng(3)
     reads = []
-    for m in [31, 32, 33, 63, 64, 65, 255, 256, 257, 300, 319, 320]:
+    # 1-320 bases: words in registers; 321-1024: the long-read kernel (LDS)
+    for m in [31, 32, 33, 63, 64, 65, 255, 256, 257, 300, 319, 320, 321, 352, 400, 511, 512, 513, 777, 1000,
+              1023, 1024]:
         for _ in range(8):
             p = int(rng.integers(0, ref.n - m))
             r = text[p:p + m]
-            if rng.random() < 0.5:
+            u = rng.random()
+            if u < 0.4:
                 j = int(rng.integers(0, m))
                 r = r[:j] + "ACGT"[(ref.codes[p + j] + 1) % 4] + r[j + 1:]
+            elif u < 0.5:
+                j = int(rng.integers(0, m))
+                r = r[:j] + "N" + r[j + 1:]
+            elif u < 0.6:
+                r = "".join(rng.choice(list("ACGT"), size=m))
             reads.append(r)
     reads.append(text[-40:] + "ACGT")  # runs off the end of the text
     reads.append(text[-320:])
+    reads.append(text[-700:] + "ACGTACGT")
+    reads.append(text[-1024:])
+    reads.append(text[1000:2000].lower())
     check_text(text, reads, device, "long")
-    # 321 bases: flagged, not searched (device path); refused (host path)
+    # 1025 bases: flagged, not searched (device path); refused (host path)
     ix = S.sa_build(text)
     d = S.sa_upload(ix, 0)
-    data, offs = oracle.pack_reads(["ACGT", "A" * 321, "GG"])
+    data, offs = oracle.pack_reads(["ACGT", "A" * 1025, "GG", text[5000:5900]])
     got = run_dev(d, data[:-1], offs, device)
     assert tuple(got[1]) == (0, 0, 0, S.SA_HIT_TOOLONG)
-    want = oracle.match(text, oracle.sa_build(text), *oracle.pack_reads(["ACGT", "GG"]))
-    assert_same(got[[0, 2]], want, "around a long read")
+    want = oracle.match(text, oracle.sa_build(text), *oracle.pack_reads(["ACGT", "GG", text[5000:5900]]))
+    assert_same(got[[0, 2, 3]], want, "around a too-long read")
     with pytest.raises(S.SaError) as e:
         S.match_batch(d, data[:-1], offs)
     assert e.value.code == S.SA_ETOOBIG

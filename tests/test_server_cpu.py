@@ -137,9 +137,9 @@ def test_failed_batch_only_fails_its_requests():
 
 def test_submit_validation_and_unknown_ticket():
     srv = S.Server([None], test_echo=1)
-    data = np.frombuffer(b"A" * 400, dtype=np.uint8)
+    data = np.frombuffer(b"A" * 1100, dtype=np.uint8)
     with pytest.raises(S.SaError) as e:
-        srv.submit(0, data, np.array([0, 400]))
+        srv.submit(0, data, np.array([0, S.SA_MAX_READ + 1]))
     assert e.value.code == S.SA_ETOOBIG
     with pytest.raises(S.SaError) as e:
         srv.submit(5, data, np.array([0, 4]))
