@@ -23,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
+    "paper": "10 Mbp order-3 Markov reference (GC 0.41) + 5% tandem repeats; 2,097,152 queries x 1024 bp "
+             "(50% sampled at 0-1% substitutions, 50% random)",
     "c1": "1 Mbp i.i.d. reference; 100,000 reads x 25 bp (50% copied, a quarter of those with 1-2 substitutions, "
           "50% random)",
     "c2": "16 Mbp order-3 Markov reference (GC 0.41) + 5% tandem repeats; 4,000,000 reads x 100 bp "
@@ -67,6 +69,9 @@ def main():
                     help="processes that generate the reads (1: in this process, e.g. under a profiler)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1303_3692_amd", "tuning_cache.jsonl"),
                     help="autotuner cache (JSON lines); a hit skips the sweep")
+    ap.add_argument("--paper", action="store_true",
+                    help="paper-shape workload: 10 Mbp reference, 1024-base queries, sets of 512 to 2,097,152; "
+                         "input / kernel / output / total per set (the columns of the paper's Table V)")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: open-loop Poisson requests over resident references")
     ap.add_argument("--serve-refs", default="c2,c4", help="references kept resident for --serve")
@@ -83,6 +88,8 @@ def main():
 
     import gen
 
+    if args.paper:
+        args.config = "paper"
     if not args.serve:
         # inputs first: the generator forks workers, before this process uses the GPU
         t = time.perf_counter()
@@ -110,6 +117,8 @@ def main():
     torch.cuda.init()
     if args.serve:
         return serve_bench(args, np, torch, gen, S)
+    if args.paper:
+        return paper_bench(args, np, torch, gen, S, ref, reads, text)
 
     t = time.perf_counter()
     d = S.sa_build_device(text, 0)
@@ -330,6 +339,88 @@ def percentile(xs, q):
         return None
     k = min(len(xs) - 1, max(0, int(round(q * (len(xs) - 1)))))
     return xs[k]
+
+
+def paper_bench(args, np, torch, gen, S, ref, reads, text):
+    """The paper's experiment shape (Section V, Table V): one 10^7-base
+    reference, query sets of 512 .. 2,097,152 reads of 1024 bases.  Per set:
+    input (host-to-device copy of the reads from pinned memory), kernel (the
+    whole device pipeline), output (device-to-host copy of the 16-byte
+    results) and total, each the median of 5 runs timed with HIP events on
+    one stream.  The index is resident (built once, timed apart)."""
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    d = S.sa_build_device(text, 0)
+    t_index = time.perf_counter() - t
+    log(f"index built on the device in {t_index:.2f}s")
+    N = reads.count
+    h_reads = torch.from_numpy(reads.data).pin_memory()
+    h_offs = torch.from_numpy(reads.offs).pin_memory()
+    d_reads = torch.empty(len(reads.data), dtype=torch.uint8, device=dev)
+    d_offs = torch.empty(N + 1, dtype=torch.int64, device=dev)
+    d_out = torch.empty((N, 4), dtype=torch.int32, device=dev)
+    h_out = torch.empty((N, 4), dtype=torch.int32).pin_memory()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    d_reads.copy_(h_reads)
+    d_offs.copy_(h_offs)
+    t = time.perf_counter()
+    _, tuned_ms = S.sa_tune(d, d_reads, d_offs, stream=stream, cache_path=args.tune_cache)
+    log(f"tuner: {time.perf_counter() - t:.1f}s -> {S.cfg(d).as_dict()} ({tuned_ms:.3f} ms)")
+    cfg = S.cfg(d)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    rows = []
+    Q = 512
+    while Q <= N:
+        nb = int(reads.offs[Q])
+        samples = []
+        for rep in range(6):
+            ev[0].record(stream)
+            d_reads[:nb].copy_(h_reads[:nb], non_blocking=True)
+            d_offs[:Q + 1].copy_(h_offs[:Q + 1], non_blocking=True)
+            ev[1].record(stream)
+            S.match_batch_dev(d, d_reads, d_offs[:Q + 1], d_out, nreads=Q, stream=stream, config=cfg)
+            ev[2].record(stream)
+            h_out[:Q].copy_(d_out[:Q], non_blocking=True)
+            ev[3].record(stream)
+            stream.synchronize()
+            if rep:
+                samples.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]),
+                                ev[0].elapsed_time(ev[3])])
+        med = [sorted(x[k] for x in samples)[len(samples) // 2] for k in range(4)]
+        rows.append({"queries": Q, "input_ms": round(med[0], 4), "kernel_ms": round(med[1], 4),
+                     "output_ms": round(med[2], 4), "total_ms": round(med[3], 4),
+                     "kernel_queries_per_s": round(Q / (med[1] * 1e-3), 1),
+                     "total_queries_per_s": round(Q / (med[3] * 1e-3), 1)})
+        log(f"Q={Q}: {rows[-1]}")
+        Q *= 2
+    out = h_out.numpy()
+    # parity on a sample, the oracle searching the device array after checking it
+    from oracle import oracle
+    osa = S.sa_download(d).suffix_array()
+    assert oracle.sa_check(text, osa) == 0, "device suffix array failed the oracle's check"
+    ns = min(N, 65536)
+    threads = oracle.max_threads()
+    t = time.perf_counter()
+    want = oracle.match(text, osa, reads.data[:reads.offs[ns]], reads.offs[:ns + 1], nthreads=threads)
+    t_match = time.perf_counter() - t
+    same = bool((want[:, :3] == out[:ns, :3]).all() and (want[:, 3] == (out[:ns, 3] & 1)).all())
+    assert same, "device results differ from the oracle on the sample"
+    cpu = {"value": round(ns / t_match, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
+           "sample": f"the first {ns:,} of {N:,} queries; oracle search phase only", "matches_gpu": same}
+    log(f"cpu oracle: {cpu}")
+    last = rows[-1]
+    line = {
+        "metric": "queries/s, whole device pipeline, 1024-base queries (the paper's Table V shape)",
+        "value": last["kernel_queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+        "ms_per_step": last["kernel_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic (seeded generators, no external data)",
+        "config": {"workload": f"paper: {WORKLOADS['paper']}", "reference_bp": ref.n, "launch": cfg.as_dict()},
+        "exact_fraction": round(float((out[:, 3] & 1).mean()), 5),
+        "index": {"device_build_s": round(t_index, 3)},
+        "sets": rows, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def serve_bench(args, np, torch, gen, S):

@@ -221,6 +221,14 @@ def make_reference(cfg: str, n: int | None = None) -> Reference:
         codes = markov_sequence(n, P, pi, rng_for(2, 0))
         arrays = add_tandem_repeats(codes, 0.05, rng_for(2, 2))
         return Reference("c2", codes, {"model": "markov3+tandem", "tandem_arrays": len(arrays)})
+    if cfg == "paper":
+        # the paper's reference is 10^7 bases of a human chromosome contig
+        # (Section V); the c2 recipe stands in for it, with its own seeds
+        n = 10_000_000 if n is None else n
+        P, pi = markov_table(rng_for(6, 1))
+        codes = markov_sequence(n, P, pi, rng_for(6, 0))
+        arrays = add_tandem_repeats(codes, 0.05, rng_for(6, 2))
+        return Reference("paper", codes, {"model": "markov3+tandem", "tandem_arrays": len(arrays)})
     if cfg == "c4":
         n = 250_000_000 if n is None else n
         P, pi = markov_table(rng_for(4, 1))
@@ -250,6 +258,10 @@ READ_SPECS = {
     "c2": ReadSpec(2, 4_000_000, 100, 100, 0.3, 0.0, 0.02),
     "c3": ReadSpec(3, 4_000_000, 20, 300, 0.3, 0.0, 0.02),
     "c4": ReadSpec(4, 64_000_000, 150, 150, 0.2, 0.01, 0.01),
+    # Section V: 1024-base queries, 512 to 2,097,152 per set, from the human
+    # contig and a mouse contig; half sampled from the reference at 0-1 %
+    # substitutions, half random (standing in for the unrelated genome)
+    "paper": ReadSpec(6, 2_097_152, 1024, 1024, 0.5, 0.0, 0.01),
 }
 
 
