@@ -279,10 +279,14 @@ def main():
         prof = json.load(open(counters))
         if prof.get("kernel_src") == kernel_source_hash() and prof.get("workload") == args.config:
             traffic = round(prof["traffic_bytes"])
+    touched = cnt["touched_bytes"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "search_tuned_kernel", "alg_bytes_per_launch": B, "alg_bytes_per_read": round(B / N, 2),
-                "launch_ms": round(stages["search"], 4), "kernel_src": kernel_source_hash()}
+                "launch_ms": round(stages["search"], 4), "kernel_src": kernel_source_hash(),
+                # bytes touched: 64-byte segments addressed per wave access, counted by the instrumented kernel
+                "touched_bytes_per_launch": touched, "touched_GBps": round(touched / (stages["search"] * 1e-3) / 1e9, 2),
+                "touched_frac": round(touched / (stages["search"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
 
     # ---- CPU baseline: the oracle's search phase on the host cores, on a
     # bounded sample of the batch (its first reads)
@@ -319,7 +323,9 @@ def main():
         "exact_fraction": round(exact, 5),
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "probes_per_read": {"global": round(cnt["global_probes"] / N, 3), "lds": round(cnt["tile_probes"] / N, 3),
-                            "text_words": round(cnt["text_words"] / N, 3), "key_words": round(cnt["key_words"] / N, 3)},
+                            "text_words": round(cnt["text_words"] / N, 3), "key_words": round(cnt["key_words"] / N, 3),
+                            "table_lookups": round(cnt["table_lookups"] / N, 3),
+                            "touched_bytes": round(cnt["touched_bytes"] / N, 1)},
         "index": {"device_build_s": round(t_index, 3), "sort_rounds": built["steps"],
                   "sorted_pairs": built["sorted_pairs"]},
         "plain": plain,

@@ -186,12 +186,15 @@ int match_batch_dev(const sa_dindex *d, const uint8_t *d_reads, const int64_t *d
 int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]);
 
 /* Counts of the last batch enqueued with cfg.count on this (index, stream):
- * c[0] global-memory probes (one SA entry each), c[1] 64-bit text words
+ * c[0] global-memory probes (one SA row each), c[1] 64-bit text words
  * those probes compare, c[2] probes answered from the LDS tile, c[3] reads
- * searched, c[4] packed query words loaded, c[5] probes that also loaded
- * the 8-byte row key (first 32 bases of the row's suffix), c[6] prefix-table
- * lookups (two adjacent 4-byte entries each).  Waits for that batch. */
-int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[7]);
+ * searched, c[4] packed query words loaded, c[5] 8-byte words loaded from
+ * row records (the first 32 bases of each probe included), c[6]
+ * prefix-table lookups (two adjacent 4-byte entries each), c[7] bytes
+ * touched by the search kernels: for every global load or store of a wave,
+ * the distinct 64-byte segments its active lanes address, times 64.
+ * Waits for that batch. */
+int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[8]);
 
 /* Autotuner: time candidate configurations (tile depth, workgroups per CU,
  * block size, bucket edges) on the given device batch, keep the fastest as

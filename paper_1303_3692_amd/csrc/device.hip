@@ -523,7 +523,7 @@ extern "C" int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]
     return SA_OK;
 }
 
-extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[7]) {
+extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[8]) {
     clear_error();
     if (!d || !c) return fail(SA_EINVAL, "NULL argument");
     DeviceGuard g(d->device);
@@ -535,6 +535,6 @@ extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[7
     hipError_t e = hipMemcpyAsync(h, ws->b.stats, sizeof h, hipMemcpyDeviceToHost, static_cast<hipStream_t>(hip_stream));
     if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "counter download");
-    for (int i = 0; i < 7; i++) c[i] = (int64_t)h[i];
+    for (int i = 0; i < 8; i++) c[i] = (int64_t)h[i];
     return SA_OK;
 }

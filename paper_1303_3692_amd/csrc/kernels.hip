@@ -40,9 +40,30 @@ struct NoCount {
     __device__ __forceinline__ void tile_probe() {}
     __device__ __forceinline__ void text_words(uint32_t, uint32_t) {}
     __device__ __forceinline__ void rec_word() {}
+    __device__ __forceinline__ void touch(const void *, int) {}
 };
+// touch(p, bytes): one global access of this lane; the 64-byte segments
+// that the wave's active lanes address together are added to `touched`
+// (credited to the first active lane), the bytes-touched measure of a
+// wave instruction.
 struct Count {
     uint32_t global = 0, words = 0, tile = 0, keys = 0, table = 0;
+    unsigned long long touched = 0;
+    __device__ __forceinline__ void touch(const void *p, int bytes) {
+        const uint64_t a = (uint64_t)(uintptr_t)p;
+        const uint64_t s0 = a >> 6;
+        const uint64_t active = __ballot(1);
+        uint64_t todo = active;
+        uint32_t segs = 0;
+        while (todo) {
+            const int l = __ffsll((unsigned long long)todo) - 1;
+            const uint64_t seg = __shfl(s0, l, 64);
+            todo &= ~__ballot(s0 == seg);
+            ++segs;
+        }
+        segs += (uint32_t)__popcll(__ballot(((a + (uint64_t)bytes - 1) >> 6) != s0));  // straddling lanes
+        if ((threadIdx.x & 63) == __ffsll((unsigned long long)active) - 1) touched += 64ull * segs;
+    }
     __device__ __forceinline__ void table_probe() { ++table; }
     __device__ __forceinline__ void global_probe() { ++global; }
     __device__ __forceinline__ void key_probe() { ++global; ++keys; }
@@ -66,6 +87,13 @@ __device__ __forceinline__ uint64_t text_word(const uint64_t *__restrict__ text,
     return (lo << sh) | ((hi >> 1) >> (63u - sh));
 }
 
+template <class Cnt>
+__device__ __forceinline__ uint64_t text_word(const uint64_t *__restrict__ text, uint32_t b, Cnt &cnt) {
+    cnt.touch(text + (b >> 5), 8);
+    cnt.touch(text + (b >> 5) + 1, 8);
+    return text_word(text, b);
+}
+
 // Compare the query P[0..plen) with the suffix at text position p, skipping
 // the first 32*k0 bases (known to match).  Returns -1 when P sorts before
 // the suffix, 0 when P[0..plen) is a prefix of it, +1 when P sorts after it
@@ -84,7 +112,7 @@ __device__ __forceinline__ int compare_from(const uint64_t *__restrict__ text, i
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         if (!done && k >= k0 && (k << 5) < lim) {
-            const uint64_t t = text_word(text, (uint32_t)p + ((uint32_t)k << 5));
+            const uint64_t t = text_word(text, (uint32_t)p + ((uint32_t)k << 5), cnt);
             const uint64_t x = q[k] ^ t;
             if (x) {
                 const int mm = (k << 5) + (int)(__clzll((long long)x) >> 1);
@@ -141,8 +169,9 @@ __device__ __forceinline__ int compare_row(const DevIndex &ix, const Q &q, int p
             } else if (rec != nullptr && k < kRecWords) {
                 t = reinterpret_cast<const uint64_t *>(rec)[1 + k];  // word k of the record
                 cnt.rec_word();
+                cnt.touch(reinterpret_cast<const uint64_t *>(rec) + 1 + k, 8);
             } else {
-                t = text_word(ix.text, (uint32_t)p + ((uint32_t)k << 5));
+                t = text_word(ix.text, (uint32_t)p + ((uint32_t)k << 5), cnt);
                 if (text_end == 0) text_first = (uint32_t)p + ((uint32_t)k << 5);
                 text_end = (uint32_t)p + (uint32_t)min_i(lim, (k << 5) + 32);
             }
@@ -179,6 +208,7 @@ __device__ __forceinline__ int bounded_search(const DevIndex &ix, const Q &q, in
     while (R > L + 1) {
         const int piv = midpoint(L, R);
         const RowHead row = row_head(ix.rows, piv);
+        cnt.touch(ix.rows + piv, 16);
         int lcp;
         cnt.key_probe();
         const int sign = compare_row<W>(ix, q, plen, ix.rows + piv, row.pos, row.key0, min_i(lcpL, lcpR), lcp, cnt);
@@ -232,6 +262,7 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
     while (st.R > st.L + 1) {
         const int piv = midpoint(st.L, st.R);
         const RowHead row = row_head(ix.rows, piv);
+        cnt.touch(ix.rows + piv, 16);
         int lcp;
         cnt.key_probe();
         const int sign =
@@ -279,6 +310,7 @@ __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, 
     const uint32_t v = (uint32_t)(q[0] >> (64 - 2 * K));
     const int lo_k = (int)ix.ptab[v];
     const int hi_k = (int)ix.ptab[v + 1];
+    cnt.touch(ix.ptab + v, 8);
     cnt.table_probe();
     if (short_rows_in(ix, lo_k, hi_k)) return false;
     st.L = lo_k - 1; st.R = hi_k; st.lcpL = 0; st.lcpR = 0;
@@ -287,6 +319,8 @@ __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, 
         const int rl = st.L >= 0 ? st.L : 0;
         const int rr = st.R < ix.n ? st.R : ix.n - 1;
         const RowHead xl = row_head(ix.rows, rl), xr = row_head(ix.rows, rr);
+        cnt.touch(ix.rows + rl, 16);
+        cnt.touch(ix.rows + rr, 16);
         int a = 0, c = 0;
         if (st.L >= 0) { cnt.key_probe(); compare_row<W>(ix, q, plen, ix.rows + rl, xl.pos, xl.key0, 0, a, cnt); }
         if (st.R < ix.n) { cnt.key_probe(); compare_row<W>(ix, q, plen, ix.rows + rr, xr.pos, xr.key0, 0, c, cnt); }
@@ -297,6 +331,7 @@ __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, 
     while (st.R > st.L + 1) {
         const int piv = midpoint(st.L, st.R);
         const RowHead row = row_head(ix.rows, piv);
+        cnt.touch(ix.rows + piv, 16);
         int lcp;
         cnt.key_probe();
         const int sign =
@@ -318,6 +353,8 @@ __device__ __forceinline__ void table_interval(const DevIndex &ix, uint64_t q0, 
     const uint32_t w = ulo + (1u << (2 * (K - l)));
     lo = (int)ix.ptab[ulo];
     hi = (int)ix.ptab[w];
+    cnt.touch(ix.ptab + ulo, 4);
+    cnt.touch(ix.ptab + w, 4);
     cnt.table_probe();
     for (;;) {
         const int si = lo > 0 ? short_at(ix, lo - 1) : -1;
@@ -649,7 +686,17 @@ __device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_
     }
     uint64_t q[W];
     load_query<W>(b.qw, rid, q);
+#pragma unroll
+    for (int k = 0; k < W; ++k) cnt.touch(b.qw + (size_t)rid * kWMax + k, 8);
     out[rid] = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, cnt);
+    cnt.touch(out + rid, 16);
+}
+
+// Sum a per-lane 64-bit count over the wave and add it to a global counter.
+__device__ __forceinline__ void wave_add64(unsigned long long *dst, unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
 }
 
 // Sum a per-lane count over the wave and add it to a global counter.
@@ -709,6 +756,10 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         const bool active = j < nreads;
         const int rid = active ? (order ? (int)order[j] : (int)j) : 0;
         const int2 lm = active ? b.qlm[rid] : make_int2(0, 0);
+        if (COUNT && active) {
+            if (order) cnt.touch(order + j, 4);
+            cnt.touch(b.qlm + rid, 8);
+        }
         const int m = lm.x;
         const bool short_read = active && !(m >= 0 && lm.y < 0);  // long reads are the long kernel's
         const int w = max_i(1, (m + 31) >> 5);
@@ -739,6 +790,7 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         wave_add(&b.stats[4], nqwords);
         wave_add(&b.stats[5], cnt.keys);
         wave_add(&b.stats[6], cnt.table);
+        wave_add64(&b.stats[7], cnt.touched);
     }
 }
 
@@ -754,6 +806,7 @@ __device__ __forceinline__ int plain_search(const DevIndex &ix, const uint64_t (
         const int piv = midpoint(L, R);
         int lcp;
         cnt.global_probe();
+        cnt.touch(ix.sa + piv, 4);
         const int sign = compare_from<kWMax>(ix.text, ix.n, q, plen, ix.sa[piv], 0, lcp, cnt);
         if (UPPER ? (sign < 0) : (sign <= 0)) R = piv; else L = piv;
     }
@@ -768,6 +821,7 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
     Cnt cnt;
     int4 res = make_int4(0, 0, 0, (int)kHitTooLong);
     const int2 lm = i < nreads ? b.qlm[i] : make_int2(-1, 0);
+    if (COUNT && i < nreads) cnt.touch(b.qlm + i, 8);
     const int m = lm.x;
     const bool long_read = m >= 0 && lm.y < 0;  // the long kernel's
     if (m >= 0 && !long_read) {
@@ -776,6 +830,9 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
         const uint64_t *src = b.qw + (size_t)i * kWMax;
 #pragma unroll
         for (int k = 0; k < kWMax; ++k) q[k] = (k << 5) < m ? src[k] : 0ull;
+#pragma unroll
+        for (int k = 0; k < kWMax; ++k)
+            if ((k << 5) < m) cnt.touch(src + k, 8);
         const int lo = plain_search<false>(ix, q, mv, cnt);
         int hi = lo;
         if (mv == m) hi = plain_search<true>(ix, q, m, cnt);
@@ -785,11 +842,13 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
             int l = 0, lcp;
             if (lo > 0) {
                 cnt.global_probe();
+                cnt.touch(ix.sa + lo - 1, 4);
                 compare_from<kWMax>(ix.text, ix.n, q, mv, ix.sa[lo - 1], 0, lcp, cnt);
                 l = max_i(l, lcp);
             }
             if (lo < ix.n) {
                 cnt.global_probe();
+                cnt.touch(ix.sa + lo, 4);
                 compare_from<kWMax>(ix.text, ix.n, q, mv, ix.sa[lo], 0, lcp, cnt);
                 l = max_i(l, lcp);
             }
@@ -797,12 +856,16 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
                             l == m ? (int)kHitExact : 0);
         }
     }
-    if (i < nreads && !long_read) out[i] = res;
+    if (i < nreads && !long_read) {
+        out[i] = res;
+        cnt.touch(out + i, 16);
+    }
     if constexpr (COUNT) {
         wave_add(&b.stats[0], cnt.global);
         wave_add(&b.stats[1], cnt.words);
         wave_add(&b.stats[3], m >= 0 && !long_read ? 1u : 0u);
         wave_add(&b.stats[4], m >= 0 && !long_read ? (uint32_t)max_i(1, (m + 31) >> 5) : 0u);
+        wave_add64(&b.stats[7], cnt.touched);
     }
 }
 
@@ -868,6 +931,10 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         const bool act = j < nreads;
         const int rid = act ? (order ? (int)order[j] : (int)j) : 0;
         const int2 lm = act ? b.qlm[rid] : make_int2(-1, 0);
+        if (COUNT && act) {
+            if (order) cnt.touch(order + j, 4);
+            cnt.touch(b.qlm + rid, 8);
+        }
         const bool is_long = act && lm.x >= 0 && lm.y < 0;
         uint64_t todo = wave_ballot(is_long);
         if (!todo) continue;
@@ -888,8 +955,10 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
                 const uintptr_t stop = (uintptr_t)(reads + a + m);
                 uint32_t dw[5];
 #pragma unroll
-                for (int t = 0; t < 5; ++t)
+                for (int t = 0; t < 5; ++t) {
                     dw[t] = base + 4u * t < stop ? *reinterpret_cast<const uint32_t *>(base + 4u * t) : 0u;
+                    if (base + 4u * t < stop) cnt.touch(reinterpret_cast<const void *>(base + 4u * t), 4);
+                }
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const int rem = m - b0 - 4 * jj;
@@ -912,6 +981,7 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
             const LdsQuery q{slot[lane]};
             if (COUNT) { nsearched++; nqwords += (uint32_t)((lm.x + 31) >> 5); }
             out[rid] = match_read<kLongWords>(ix, nullptr, nullptr, 0, use_table, q, lm.x, mv_mine, cnt);
+            cnt.touch(out + rid, 16);
         }
         __syncthreads();  // before the next chunk rewrites the slots
     }
@@ -923,6 +993,7 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         wave_add(&b.stats[4], nqwords);
         wave_add(&b.stats[5], cnt.keys);
         wave_add(&b.stats[6], cnt.table);
+        wave_add64(&b.stats[7], cnt.touched);
     }
 }
 

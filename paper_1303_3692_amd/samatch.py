@@ -300,10 +300,10 @@ def sa_stage_times(d: DIndex, stream=None) -> dict:
 
 def sa_probe_counts(d: DIndex, stream=None) -> dict:
     """Probe counts of the last counted batch on this stream."""
-    c = (ctypes.c_int64 * 7)()
+    c = (ctypes.c_int64 * 8)()
     _check(lib().sa_probe_counts(d.ptr, _stream_handle(stream), c), "sa_probe_counts")
     return {"global_probes": c[0], "text_words": c[1], "tile_probes": c[2], "reads": c[3], "query_words": c[4],
-            "key_words": c[5], "table_lookups": c[6]}
+            "key_words": c[5], "table_lookups": c[6], "touched_bytes": c[7]}
 
 
 def locate(d: DIndex, hits, cap: int, min_len: int = 0):
