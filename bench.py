@@ -374,6 +374,7 @@ def paper_bench(args, np, torch, gen, S, ref, reads, text):
     _, tuned_ms = S.sa_tune(d, d_reads, d_offs, stream=stream, cache_path=args.tune_cache)
     log(f"tuner: {time.perf_counter() - t:.1f}s -> {S.cfg(d).as_dict()} ({tuned_ms:.3f} ms)")
     cfg = S.cfg(d)
+    cfg.use_graph = 1  # one captured launch sequence per set size
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     rows = []
     Q = 512

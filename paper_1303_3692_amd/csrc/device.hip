@@ -61,7 +61,7 @@ int Workspace::reserve(int64_t nreads) {
     const int64_t nblocks = (c + kSortTile - 1) / kSortTile;
     hipError_t e;
     if ((e = grow((void **)&b.qw, sizeof(uint64_t) * kWMax * (size_t)c)) != hipSuccess ||
-        (e = grow((void **)&b.qlm, sizeof(int2) * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.qlm, sizeof(int4) * (size_t)c)) != hipSuccess ||
         (e = grow((void **)&b.key[0], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
         (e = grow((void **)&b.key[1], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
         (e = grow((void **)&b.val[0], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||

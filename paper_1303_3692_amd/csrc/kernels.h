@@ -19,9 +19,12 @@ constexpr int kSortTile = kSortBlock * kSortItems;
 // Per SA row: the suffix's text position and length, then its first
 // 32 * kRecWords bases as aligned 2-bit words (zero past the text end).  A
 // probe loads the first 16 bytes (position, length, word 0) and further
-// words only while they keep matching, from the same line.
+// words only while they keep matching, from the same line.  One word (16
+// bytes per row) is the default: on MI355X the 32- and 64-byte records cut
+// the bytes touched per read by 8-10 % but made the search 3-5 % slower
+// (a 2-4x larger array caches worse).
 #ifndef SAMATCH_REC_WORDS
-#define SAMATCH_REC_WORDS 7
+#define SAMATCH_REC_WORDS 1
 #endif
 constexpr int kRecWords = SAMATCH_REC_WORDS;
 static_assert(kRecWords == 1 || kRecWords == 3 || kRecWords == 7, "row records are 16, 32 or 64 bytes");
@@ -60,7 +63,8 @@ struct BucketTable {
 // Scratch buffers of one batch (device pointers).
 struct BatchBuffers {
     uint64_t *qw;        // nreads * kWMax packed words
-    int2 *qlm;           // per read: length (-1: not searched), length of the ACGT prefix
+    int4 *qlm;           // per read: length (-1: not searched), length of the ACGT prefix (-1: long
+                         // read), offset of its packed words in its workgroup's region of qw
     uint32_t *key[2];    // sort keys (ping-pong)
     uint32_t *val[2];    // read ids (ping-pong)
     uint32_t *hist;      // 256 * sort blocks

@@ -402,10 +402,9 @@ __device__ __forceinline__ int4 match_read(const DevIndex &ix, const uint64_t *s
 }
 
 template <int W>
-__device__ __forceinline__ void load_query(const uint64_t *__restrict__ qw, int rid, uint64_t (&q)[W]) {
-    const uint64_t *src = qw + (size_t)rid * kWMax;
+__device__ __forceinline__ void load_query(const uint64_t *__restrict__ src, int nw, uint64_t (&q)[W]) {
 #pragma unroll
-    for (int k = 0; k < W; ++k) q[k] = src[k];
+    for (int k = 0; k < W; ++k) q[k] = k < nw ? src[k] : 0ull;
 }
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
@@ -646,14 +645,20 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
             }
         }
     }
+    // the words of the workgroup's searched reads, back to back from the
+    // start of its region of qw (256 * kWMax words): read i's run starts at
+    // word `wo` of the region
+    __shared__ uint32_t scan_tmp[kPackBlock / 64];
+    const int nw = (i < nreads && m >= 0 && mv >= 0) ? (m > 0 ? (m + 31) >> 5 : 1) : 0;
+    uint32_t wo;
+    const uint32_t run_words = block_exclusive_scan((uint32_t)nw, wo, scan_tmp);
     __syncthreads();  // the staged bytes are no longer needed
     uint64_t *slots = reinterpret_cast<uint64_t *>(stage);
     if (i < nreads) {
-        const int nw = m > 0 ? (m + 31) >> 5 : 1;
 #pragma unroll
         for (int t = 0; t < kWMax; ++t)
-            if (t < nw) slots[threadIdx.x * kWMax + t] = w[t];
-        b.qlm[i] = make_int2(m, mv);
+            if (t < nw) slots[wo + t] = w[t];
+        b.qlm[i] = make_int4(m, mv, (int)wo, 0);
         if (m >= 0 && mv < 0) {
             b.key[0][i] = long_read_key(bt.count);
         } else if (m >= 0) {
@@ -667,11 +672,17 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
         b.val[0][i] = (uint32_t)i;
     }
     __syncthreads();
-    // the workgroup's slots are one contiguous range of qw: 16-byte stores
-    const int64_t nslots = (r1 - r0) * kWMax;
+    // 16-byte stores of the used words only (an odd count rounds up within
+    // the region, whose size is even)
     uint4 *dst = reinterpret_cast<uint4 *>(b.qw + (size_t)r0 * kWMax);
     const uint4 *srcv = reinterpret_cast<const uint4 *>(slots);
-    for (int64_t c = threadIdx.x; c < nslots / 2; c += kPackBlock) dst[c] = srcv[c];
+    for (uint32_t c = threadIdx.x; c < (run_words + 1) / 2; c += kPackBlock) dst[c] = srcv[c];
+}
+
+// First word of read rid's packed words in qw (its workgroup's region plus
+// its offset there, as the pack kernel laid them out).
+__device__ __forceinline__ const uint64_t *query_words(const uint64_t *qw, int rid, int wo) {
+    return qw + (size_t)(rid & ~(kPackBlock - 1)) * kWMax + wo;
 }
 
 // ------------------------------------------------------------------ search
@@ -679,15 +690,18 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
 template <int W, class Cnt>
 __device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa,
                                           int levels, bool use_table, const BatchBuffers &b, int rid, int m, int mv,
-                                          int4 *out, Cnt &cnt) {
+                                          int wo, int4 *out, Cnt &cnt) {
     if (m < 0) {
         out[rid] = make_int4(0, 0, 0, (int)kHitTooLong);
         return;
     }
     uint64_t q[W];
-    load_query<W>(b.qw, rid, q);
+    const uint64_t *src = query_words(b.qw, rid, wo);
+    const int nw = m > 0 ? (m + 31) >> 5 : 1;
+    load_query<W>(src, nw, q);
 #pragma unroll
-    for (int k = 0; k < W; ++k) cnt.touch(b.qw + (size_t)rid * kWMax + k, 8);
+    for (int k = 0; k < W; ++k)
+        if (k < nw) cnt.touch(src + k, 8);
     out[rid] = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, cnt);
     cnt.touch(out + rid, 16);
 }
@@ -755,10 +769,10 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         const int64_t j = (chunk << 6) + lane;
         const bool active = j < nreads;
         const int rid = active ? (order ? (int)order[j] : (int)j) : 0;
-        const int2 lm = active ? b.qlm[rid] : make_int2(0, 0);
+        const int4 lm = active ? b.qlm[rid] : make_int4(0, 0, 0, 0);
         if (COUNT && active) {
             if (order) cnt.touch(order + j, 4);
-            cnt.touch(b.qlm + rid, 8);
+            cnt.touch(b.qlm + rid, 16);
         }
         const int m = lm.x;
         const bool short_read = active && !(m >= 0 && lm.y < 0);  // long reads are the long kernel's
@@ -770,16 +784,16 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         if (!short_read) continue;
         if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
         switch (wc) {
-            case 1: tuned_one<1>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
-            case 2: tuned_one<2>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
-            case 3: tuned_one<3>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
-            case 4: tuned_one<4>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
-            case 5: tuned_one<5>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
-            case 6: tuned_one<6>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
-            case 7: tuned_one<7>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
-            case 8: tuned_one<8>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
-            case 9: tuned_one<9>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
-            default: tuned_one<10>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, out, cnt); break;
+            case 1: tuned_one<1>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            case 2: tuned_one<2>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            case 3: tuned_one<3>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            case 4: tuned_one<4>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            case 5: tuned_one<5>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            case 6: tuned_one<6>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            case 7: tuned_one<7>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            case 8: tuned_one<8>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            case 9: tuned_one<9>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            default: tuned_one<10>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
         }
     }
     if constexpr (COUNT) {
@@ -820,14 +834,14 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
     using Cnt = typename std::conditional<COUNT, Count, NoCount>::type;
     Cnt cnt;
     int4 res = make_int4(0, 0, 0, (int)kHitTooLong);
-    const int2 lm = i < nreads ? b.qlm[i] : make_int2(-1, 0);
-    if (COUNT && i < nreads) cnt.touch(b.qlm + i, 8);
+    const int4 lm = i < nreads ? b.qlm[i] : make_int4(-1, 0, 0, 0);
+    if (COUNT && i < nreads) cnt.touch(b.qlm + i, 16);
     const int m = lm.x;
     const bool long_read = m >= 0 && lm.y < 0;  // the long kernel's
     if (m >= 0 && !long_read) {
         const int mv = lm.y;
         uint64_t q[kWMax];
-        const uint64_t *src = b.qw + (size_t)i * kWMax;
+        const uint64_t *src = query_words(b.qw, (int)i, lm.z);
 #pragma unroll
         for (int k = 0; k < kWMax; ++k) q[k] = (k << 5) < m ? src[k] : 0ull;
 #pragma unroll
@@ -930,10 +944,10 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         const int64_t j = first + (c << 6) + lane;
         const bool act = j < nreads;
         const int rid = act ? (order ? (int)order[j] : (int)j) : 0;
-        const int2 lm = act ? b.qlm[rid] : make_int2(-1, 0);
+        const int4 lm = act ? b.qlm[rid] : make_int4(-1, 0, 0, 0);
         if (COUNT && act) {
             if (order) cnt.touch(order + j, 4);
-            cnt.touch(b.qlm + rid, 8);
+            cnt.touch(b.qlm + rid, 16);
         }
         const bool is_long = act && lm.x >= 0 && lm.y < 0;
         uint64_t todo = wave_ballot(is_long);
