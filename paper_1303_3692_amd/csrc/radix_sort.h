@@ -17,20 +17,34 @@ namespace {  // each translation unit that sorts gets its own copy
 
 static_assert(kSortBlock == 256, "the scatter kernel's digit loops assume one digit per thread");
 
+// Keys per workgroup tile: 16 per thread for 32-bit keys, 8 for 64-bit keys
+// (the scatter stages a tile's input and output in LDS).
+template <class K>
+struct SortTile {
+    static constexpr int items = sizeof(K) == 4 ? 16 : 8;
+    static constexpr int size = kSortBlock * items;
+};
+static_assert(SortTile<uint32_t>::size == kSortTile, "batch histograms are sized with kSortTile");
+
 // Per-block digit counts, digit-major: hist[d * nblocks + block].
 template <class K>
 __global__ __launch_bounds__(kSortBlock) void sort_hist_kernel(const K *__restrict__ keys, int64_t n, int shift,
                                                                uint32_t *hist, int nblocks) {
+    constexpr int kItems = SortTile<K>::items;
     __shared__ uint32_t h[kSortBlock / 64][256];
     const int t = threadIdx.x, wave = t >> 6;
     for (int i = t; i < (kSortBlock / 64) * 256; i += kSortBlock) (&h[0][0])[i] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
-    for (int r = 0; r < kSortItems; ++r) {
+    const int64_t base = (int64_t)blockIdx.x * SortTile<K>::size;
+    K k[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {  // all loads in flight before the counting
         const int64_t i = base + r * kSortBlock + t;
-        if (i < n) atomicAdd(&h[wave][(uint32_t)(keys[i] >> shift) & 255u], 1u);
+        k[r] = i < n ? keys[i] : K(0);
     }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+        if (base + r * kSortBlock + t < n) atomicAdd(&h[wave][(uint32_t)(k[r] >> shift) & 255u], 1u);
     __syncthreads();
     for (int d = t; d < 256; d += kSortBlock) {
         uint32_t s = 0;
@@ -113,39 +127,63 @@ __device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, bool valid) {
     return peers;
 }
 
-// Stable scatter of one tile of kSortTile keys.  Each wave owns a contiguous
-// quarter of the tile, taken 64 keys per round in input order; lanes with
-// the same digit are ranked by lane order.  Sweep 1 counts digits per wave;
-// a block scan turns the counts into each wave's first slot per digit
-// inside the tile; sweep 2 places every key in an LDS copy of the tile,
-// ordered by digit; the tile is then written out so that consecutive
-// threads store consecutive addresses of one digit's run.
+// Stable scatter of one tile of keys.  The tile's keys and values are first
+// copied into LDS with 16-byte loads, all in flight together.  Each wave
+// owns a contiguous quarter of the tile, taken 64 keys per round in input
+// order; lanes with the same digit are ranked by lane order.  Sweep 1
+// counts digits per wave; a block scan turns the counts into each wave's
+// first slot per digit inside the tile; sweep 2 places every key in a
+// second LDS copy of the tile, ordered by digit; the tile is then written
+// out so that consecutive threads store consecutive addresses of one
+// digit's run.
 template <class K>
 __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(const K *__restrict__ kin,
                                                                   const uint32_t *__restrict__ vin,
                                                                   K *__restrict__ kout, uint32_t *__restrict__ vout,
                                                                   int64_t n, int shift,
                                                                   const uint32_t *__restrict__ hist, int nblocks) {
+    constexpr int kTile = SortTile<K>::size;
     constexpr int kWaves = kSortBlock / 64;
-    constexpr int kPerWave = kSortTile / kWaves;
-    __shared__ K s_key[kSortTile];
-    __shared__ uint32_t s_val[kSortTile];
+    constexpr int kPerWave = kTile / kWaves;
+    __shared__ __align__(16) K in_key[kTile];
+    __shared__ __align__(16) uint32_t in_val[kTile];
+    __shared__ K s_key[kTile];
+    __shared__ uint32_t s_val[kTile];
     __shared__ uint32_t wslot[kWaves][256];  // per wave: count, then next slot per digit
     __shared__ uint32_t loc[256];            // first slot of each digit in the tile
     __shared__ uint32_t gbase[256];          // global position of the tile's first key of each digit
     __shared__ uint32_t scan_tmp[kWaves];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+    const int count = (int)((n - tile0) < kTile ? (n - tile0) : kTile);
+    if (count == kTile) {
+        // a full tile starts at a multiple of kTile elements: 16-byte aligned
+        const uint4 *ks = reinterpret_cast<const uint4 *>(kin + tile0);
+        const uint4 *vs = reinterpret_cast<const uint4 *>(vin + tile0);
+        uint4 *kd = reinterpret_cast<uint4 *>(in_key);
+        uint4 *vd = reinterpret_cast<uint4 *>(in_val);
+        constexpr int kKeyVecs = kTile * (int)sizeof(K) / 16, kValVecs = kTile * 4 / 16;
+#pragma unroll
+        for (int c = 0; c < kKeyVecs / kSortBlock; ++c) kd[c * kSortBlock + t] = ks[c * kSortBlock + t];
+#pragma unroll
+        for (int c = 0; c < kValVecs / kSortBlock; ++c) vd[c * kSortBlock + t] = vs[c * kSortBlock + t];
+    } else {
+        for (int p = t; p < count; p += kSortBlock) {
+            in_key[p] = kin[tile0 + p];
+            in_val[p] = vin[tile0 + p];
+        }
+    }
     for (int i = t; i < kWaves * 256; i += kSortBlock) (&wslot[0][0])[i] = 0;
     for (int d = t; d < 256; d += kSortBlock) gbase[d] = hist[(size_t)d * nblocks + blockIdx.x];
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * kPerWave;
+    const int base = wave * kPerWave;
     // sweep 1: digit counts per wave
 #pragma unroll 1
     for (int r = 0; r < kPerWave / 64; ++r) {
-        const int64_t i = base + r * 64 + lane;
-        const bool valid = i < n;
-        const K key = valid ? kin[i] : K(0);
+        const int p = base + r * 64 + lane;
+        const bool valid = p < count;
+        const K key = valid ? in_key[p] : K(0);
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         const uint64_t peers = same_digit_lanes(d, valid);
         if (valid && __popcll(peers & lt_mask) == 0) wslot[wave][d] += (uint32_t)__popcll(peers);
@@ -169,20 +207,19 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(const K *__res
         }
     }
     __syncthreads();
-    // sweep 2: place keys in the LDS tile, stable within each digit (the
-    // tile's keys are read again; they are still in cache)
+    // sweep 2: place keys in the second LDS tile, stable within each digit
 #pragma unroll 1
     for (int r = 0; r < kPerWave / 64; ++r) {
-        const int64_t i = base + r * 64 + lane;
-        const bool valid = i < n;
-        const K key = valid ? kin[i] : K(0);
+        const int p = base + r * 64 + lane;
+        const bool valid = p < count;
+        const K key = valid ? in_key[p] : K(0);
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         const uint64_t peers = same_digit_lanes(d, valid);
         const int rank = __popcll(peers & lt_mask);
         if (valid) {
             const uint32_t pos = wslot[wave][d] + (uint32_t)rank;
             s_key[pos] = key;
-            s_val[pos] = vin[i];
+            s_val[pos] = in_val[p];
         }
         __builtin_amdgcn_wave_barrier();
         if (valid && rank == 0) wslot[wave][d] += (uint32_t)__popcll(peers);
@@ -190,8 +227,6 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(const K *__res
     }
     __syncthreads();
     // write out: runs of one digit go to consecutive addresses
-    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
-    const int count = (int)((n - tile0) < kSortTile ? (n - tile0) : kSortTile);
     for (int p = t; p < count; p += kSortBlock) {
         const K k = s_key[p];
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
@@ -201,9 +236,15 @@ __global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(const K *__res
     }
 }
 
+// Histogram words radix_sort_pairs<K> needs for n keys.
+template <class K>
+inline size_t sort_hist_words(int64_t n) {
+    return 256 * (size_t)((n + SortTile<K>::size - 1) / SortTile<K>::size);
+}
+
 // Sort n pairs by key bits [lo_bit, hi_bit), starting from (k0, v0) with
 // (k1, v1) as the other buffer; *which = 0 when the result is in (k0, v0),
-// 1 when it is in (k1, v1).  hist holds 256 * ceil(n / kSortTile) counts,
+// 1 when it is in (k1, v1).  hist holds sort_hist_words<K>(n) counts,
 // digit_total 256.  n < 2^32.
 template <class K>
 hipError_t radix_sort_pairs(K *k0, uint32_t *v0, K *k1, uint32_t *v1, uint32_t *hist, uint32_t *digit_total,
@@ -211,7 +252,7 @@ hipError_t radix_sort_pairs(K *k0, uint32_t *v0, K *k1, uint32_t *v1, uint32_t *
     K *key[2] = {k0, k1};
     uint32_t *val[2] = {v0, v1};
     int cur = 0;
-    const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+    const int nblocks = (int)((n + SortTile<K>::size - 1) / SortTile<K>::size);
     if (n > 1) {
         for (int shift = lo_bit; shift < hi_bit; shift += 8) {
             hipLaunchKernelGGL(sort_hist_kernel<K>, dim3(nblocks), dim3(kSortBlock), 0, s, key[cur], n, shift, hist,

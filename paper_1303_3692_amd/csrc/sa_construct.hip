@@ -20,7 +20,7 @@
 // kernels), so every key uses ranks of h-prefixes.
 //
 // Device memory: keys 2 x 8n, values 2 x 4n, kept rows 2 x 4n, rank 4n,
-// sort histograms 256 x 4 x ceil(n / 4096) bytes.
+// sort histograms 256 x 4 x ceil(n / 2048) bytes.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -225,7 +225,6 @@ __global__ __launch_bounds__(kScanBlock) void sa_flags_apply_kernel(
 int build_sa_device(const uint64_t *d_text, int64_t n, int32_t *d_sa, uint32_t *rank_out, hipStream_t s,
                     SaBuildInfo *info) {
     if (n < 1 || n > INT32_MAX) return fail(SA_EINVAL, "text length out of range for device construction");
-    const int64_t tiles_sort = (n + kSortTile - 1) / kSortTile;
     const int64_t tiles_scan = (n + kScanTile - 1) / kScanTile;
     uint64_t *key[2] = {nullptr, nullptr};
     uint32_t *val[2] = {nullptr, nullptr}, *row[2] = {nullptr, nullptr};
@@ -245,7 +244,7 @@ int build_sa_device(const uint64_t *d_text, int64_t n, int32_t *d_sa, uint32_t *
     }
     if (rank_out) rank = rank_out;
     else alloc((void **)&rank, sizeof(uint32_t) * (size_t)n);
-    alloc((void **)&hist, sizeof(uint32_t) * 256 * (size_t)tiles_sort);
+    alloc((void **)&hist, sizeof(uint32_t) * sort_hist_words<uint64_t>(n));
     alloc((void **)&digit_total, sizeof(uint32_t) * 256);
     alloc((void **)&tmax, sizeof(uint32_t) * (size_t)tiles_scan);
     alloc((void **)&tsum, sizeof(uint32_t) * (size_t)tiles_scan);
