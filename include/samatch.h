@@ -144,7 +144,9 @@ typedef struct {
     int nbuckets;        /* tuned: length buckets (1..8)                           */
     int bucket_edge[8];  /* tuned: bucket b holds reads with m <= bucket_edge[b];
                             ascending; the last bucket takes every longer read   */
-    int sort;            /* tuned: 1 = sort reads by prefix first, 0 = input order */
+    int sort;            /* tuned: sort reads by prefix first: 1 = on the top 8, 16
+                            or 24 prefix bits, the fewest with 2^bits >= reads/64;
+                            8, 16 or 24 = on that many bits; 0 = input order     */
     int use_graph;       /* 1 = match_batch_dev replays the batch's launch sequence
                             as a hipGraph captured on first use for the same
                             buffers, size and settings (not on the null stream;

@@ -70,7 +70,7 @@ int Workspace::reserve(int64_t nreads) {
         return hip_fail(e, "scratch allocation");
     if (!b.digit_total && (e = hipMalloc((void **)&b.digit_total, sizeof(uint32_t) * 256)) != hipSuccess)
         return hip_fail(e, "scratch allocation");
-    if (!b.stats && (e = hipMalloc((void **)&b.stats, sizeof(unsigned long long) * 8)) != hipSuccess)
+    if (!b.stats && (e = hipMalloc((void **)&b.stats, sizeof(unsigned long long) * kStatWords)) != hipSuccess)
         return hip_fail(e, "scratch allocation");
     for (hipEvent_t &ev_i : ev)
         if (!ev_i && (e = hipEventCreate(&ev_i)) != hipSuccess) return hip_fail(e, "event creation");
@@ -130,6 +130,8 @@ int check_cfg(const sa_dindex *d, const sa_match_cfg &c) {
     if (c.blocks_per_cu < 1 || c.blocks_per_cu > 16) return fail(SA_EINVAL, "blocks_per_cu must be in 1..16");
     if (c.nbuckets < 1 || c.nbuckets > 8) return fail(SA_EINVAL, "nbuckets must be in 1..8");
     if (c.group < 1 || c.group > 64) return fail(SA_EINVAL, "group must be in 1..64");
+    if (c.sort != 0 && c.sort != 1 && c.sort != 8 && c.sort != 16 && c.sort != 24)
+        return fail(SA_EINVAL, "sort must be 0, 1, 8, 16 or 24");
     for (int i = 0; i + 1 < c.nbuckets; i++)
         if (c.bucket_edge[i] < 1 || (i > 0 && c.bucket_edge[i] <= c.bucket_edge[i - 1]))
             return fail(SA_EINVAL, "bucket edges must ascend");
@@ -174,7 +176,8 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         // shared pivots, so the sort covers the top 8, 16 or 24 prefix bits
         // (2^bits >= nreads / 64), then the bucket byte when there is one.
         int pbits = 8;
-        while (pbits < 24 && ((int64_t)1 << pbits) < nreads / 64) pbits += 8;
+        if (c.sort == 8 || c.sort == 16 || c.sort == 24) pbits = c.sort;
+        else while (pbits < 24 && ((int64_t)1 << pbits) < nreads / 64) pbits += 8;
         int which = 0;
         const int lo_bit = 24 - pbits, hi_bit = c.nbuckets > 1 ? 32 : 24;
         e = launch_sort(ws->b, nreads, lo_bit, hi_bit, &which, s);
@@ -358,7 +361,9 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
     c.blocks_per_cu = 8;
     c.nbuckets = 1;
     c.bucket_edge[0] = SA_MAX_READ;
-    c.sort = 1;
+    // with the prefix table, reads in input order search as fast as sorted
+    // ones and the sort is saved (MI355X, every workload measured)
+    c.sort = d->view.ptab_k > 0 ? 0 : 1;
     c.use_graph = 0;
     c.group = 4;
     c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;

@@ -11,6 +11,8 @@ namespace samatch {
 constexpr int kWMax = 10;                 // packed words per read slot of the short-read path
 constexpr int kShortMax = kWMax * 32;     // longest read of the short-read path (320 bases)
 constexpr int kLongWords = SA_MAX_READ / 32;  // words of a read on the long-read path
+constexpr int kStatWords = 9;
+constexpr int kLongFlag = 8;
 constexpr int kMaxTileLevels = 13;        // 8191 nodes x 12 B = 96 KiB of LDS
 constexpr int kSortBlock = 256;           // radix sort: threads per workgroup
 constexpr int kSortItems = 16;            // keys per thread per pass
@@ -69,7 +71,8 @@ struct BatchBuffers {
     uint32_t *val[2];    // read ids (ping-pong)
     uint32_t *hist;      // 256 * sort blocks
     uint32_t *digit_total;  // 256
-    unsigned long long *stats;  // 8 counters of the instrumented search (zeroed by pack)
+    unsigned long long *stats;  // kStatWords words zeroed by pack: 8 counters of the instrumented
+                                // search, then kLongFlag (set when a batch holds a long read)
 };
 
 // Once per device before any launch (and before any graph capture): lets

@@ -585,7 +585,7 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
     const int64_t r0 = (int64_t)blockIdx.x * kPackBlock;
     const int64_t r1 = r0 + kPackBlock < nreads ? r0 + kPackBlock : nreads;
     const int64_t i = r0 + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x < 8) b.stats[threadIdx.x] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x < kStatWords) b.stats[threadIdx.x] = 0ull;
     const int64_t span0 = offs[r0];
     const int64_t span1 = ends ? span0 : offs[r1];
     const uintptr_t A0 = (uintptr_t)(reads + span0) & ~(uintptr_t)15;
@@ -781,6 +781,7 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
 #pragma unroll
         for (int t = 2; t <= kWMax; ++t)
             if (wave_ballot(short_read && w >= t)) wc = t;
+        if (active && !short_read && m >= 0) b.stats[kLongFlag] = 1ull;  // a long read: the long kernel runs
         if (!short_read) continue;
         if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
         switch (wc) {
@@ -838,6 +839,7 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
     if (COUNT && i < nreads) cnt.touch(b.qlm + i, 16);
     const int m = lm.x;
     const bool long_read = m >= 0 && lm.y < 0;  // the long kernel's
+    if (long_read) b.stats[kLongFlag] = 1ull;
     if (m >= 0 && !long_read) {
         const int mv = lm.y;
         uint64_t q[kWMax];
@@ -922,6 +924,8 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
     __shared__ uint64_t slot[64][kLongWords];
     __shared__ int64_t s_first;
     const int lane = threadIdx.x;
+    // the search kernel before this one flags batches that hold long reads
+    if (*reinterpret_cast<volatile const unsigned long long *>(b.stats + kLongFlag) == 0ull) return;
     if (lane == 0) {
         int64_t lo = 0, hi = nreads;  // first sorted row whose key field reaches long_field
         if (sorted_key) {

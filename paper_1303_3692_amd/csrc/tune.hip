@@ -177,8 +177,8 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
         }
         ms = best_rep;
         if (std::getenv("SAMATCH_TUNE_LOG"))
-            std::fprintf(stderr, "tune: levels=%d block=%d per_cu=%d group=%d table=%d buckets=%d -> %.4f ms\n",
-                         c.tile_levels, c.block, c.blocks_per_cu, c.group, c.prefix_table, c.nbuckets, ms);
+            std::fprintf(stderr, "tune: levels=%d block=%d per_cu=%d group=%d table=%d sort=%d buckets=%d -> %.4f ms\n",
+                         c.tile_levels, c.block, c.blocks_per_cu, c.group, c.prefix_table, c.sort, c.nbuckets, ms);
         return SA_OK;
     };
     // stage 1: tile depth x workgroup shape with one bucket
@@ -206,13 +206,15 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
             }
         }
     }
-    // stage 1b: block size of the work split with the best shape, and the
-    // search start (prefix table or LDS tile only)
+    // stage 1b: block size of the work split with the best shape, the
+    // search start (prefix table or LDS tile only), and the sort width
     static const int kGroups[4] = {1, 2, 8, 16};
-    for (int variant = 0; variant < 5; variant++) {
+    static const int kSortBits[4] = {0, 8, 16, 24};
+    for (int variant = 0; variant < 9; variant++) {
         sa_match_cfg c = top;
         if (variant < 4) c.group = kGroups[variant];
-        else if (d->view.ptab_k > 0) c.prefix_table = !top.prefix_table;
+        else if (variant == 4 && d->view.ptab_k > 0) c.prefix_table = !top.prefix_table;
+        else if (variant >= 5) c.sort = kSortBits[variant - 5];
         else continue;
         double ms = 0;
         rc = time_cfg(c, ms);

@@ -54,6 +54,9 @@ CONFIGS = [
     ("tuned-t5-b512", dict(tile_levels=5, block=512, blocks_per_cu=2)),
     ("tuned-t13-b1024", dict(tile_levels=13, block=1024, blocks_per_cu=1)),
     ("tuned-buckets", dict(nbuckets=3, bucket_edge=[64, 160, 320], blocks_per_cu=4)),
+    ("tuned-sort-adaptive", dict(sort=1)),
+    ("tuned-sort8", dict(sort=8, group=1)),
+    ("tuned-sort24-buckets", dict(sort=24, nbuckets=2, bucket_edge=[96, 1024])),
 ]
 
 
