@@ -61,7 +61,7 @@ int Workspace::reserve(int64_t nreads) {
     const int64_t nblocks = (c + kSortTile - 1) / kSortTile;
     hipError_t e;
     if ((e = grow((void **)&b.qw, sizeof(uint64_t) * kWMax * (size_t)c)) != hipSuccess ||
-        (e = grow((void **)&b.qlm, sizeof(int4) * (size_t)c)) != hipSuccess ||
+        (e = grow((void **)&b.qlm, sizeof(int2) * (size_t)c)) != hipSuccess ||
         (e = grow((void **)&b.key[0], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
         (e = grow((void **)&b.key[1], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
         (e = grow((void **)&b.val[0], sizeof(uint32_t) * (size_t)c)) != hipSuccess ||
@@ -164,7 +164,9 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
     const bool prof = c.profile != 0;
     hipError_t e = hipSuccess;
     if (prof && (e = hipEventRecord(ws->ev[0], s)) != hipSuccess) return hip_fail(e, "event record");
-    e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bucket_table(c), s);
+    BucketTable bt = bucket_table(c);
+    bt.keys = (c.kernel == SA_KERNEL_TUNED && c.sort) ? 1 : 0;
+    e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bt, s);
     if (e != hipSuccess) return hip_fail(e, "pack launch");
     if (prof && (e = hipEventRecord(ws->ev[1], s)) != hipSuccess) return hip_fail(e, "event record");
     const uint32_t *order = nullptr, *sorted_key = nullptr;

@@ -60,13 +60,13 @@ constexpr int kMaxPrefixBases = 14;
 struct BucketTable {
     int count;     // 1..8
     int edge[8];   // bucket b: m <= edge[b]
+    int keys;      // 1: pack writes sort keys and read ids (the reads get sorted)
 };
 
 // Scratch buffers of one batch (device pointers).
 struct BatchBuffers {
     uint64_t *qw;        // nreads * kWMax packed words
-    int4 *qlm;           // per read: length (-1: not searched), length of the ACGT prefix (-1: long
-                         // read), offset of its packed words in its workgroup's region of qw
+    int2 *qlm;           // per read: length, ACGT-prefix length, word offset (see ReadLen)
     uint32_t *key[2];    // sort keys (ping-pong)
     uint32_t *val[2];    // read ids (ping-pong)
     uint32_t *hist;      // 256 * sort blocks

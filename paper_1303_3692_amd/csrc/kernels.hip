@@ -480,6 +480,28 @@ __global__ void build_tile_kernel(const uint64_t *__restrict__ text, const int32
     tsa[j] = p;
 }
 
+// ------------------------------------------------------------------ per-read record
+
+// The pack kernel's 8-byte record of a read: its length m (-1: not
+// searched), then one word holding the length of its ACGT prefix plus one
+// (0: a long read, for the long-read kernel) in the low 16 bits and the
+// offset of its packed words in its workgroup's region of qw in the high 16.
+struct ReadLen {
+    int m, mv, wo;
+};
+
+__device__ __forceinline__ int2 encode_len(int m, int mv, int wo) {
+    return make_int2(m, (int)(((uint32_t)wo << 16) | (uint32_t)(mv + 1)));
+}
+
+__device__ __forceinline__ ReadLen decode_len(int2 v) {
+    ReadLen r;
+    r.m = v.x;
+    r.mv = (int)((uint32_t)v.y & 0xFFFFu) - 1;
+    r.wo = (int)((uint32_t)v.y >> 16);
+    return r;
+}
+
 // ------------------------------------------------------------------ pack
 
 // Per-byte flags (0x80 in each byte) of the four bytes of x that are not
@@ -658,18 +680,20 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
 #pragma unroll
         for (int t = 0; t < kWMax; ++t)
             if (t < nw) slots[wo + t] = w[t];
-        b.qlm[i] = make_int4(m, mv, (int)wo, 0);
-        if (m >= 0 && mv < 0) {
-            b.key[0][i] = long_read_key(bt.count);
-        } else if (m >= 0) {
-            int bucket = bt.count - 1;
-            for (int j = 0; j < bt.count; ++j)
-                if (m <= bt.edge[j]) { bucket = j; break; }
-            b.key[0][i] = ((uint32_t)bucket << 24) | (uint32_t)(w[0] >> 40);
-        } else {
-            b.key[0][i] = 0;
+        b.qlm[i] = encode_len(m, mv, (int)wo);
+        if (bt.keys) {  // sort keys, only when the reads are sorted
+            if (m >= 0 && mv < 0) {
+                b.key[0][i] = long_read_key(bt.count);
+            } else if (m >= 0) {
+                int bucket = bt.count - 1;
+                for (int j = 0; j < bt.count; ++j)
+                    if (m <= bt.edge[j]) { bucket = j; break; }
+                b.key[0][i] = ((uint32_t)bucket << 24) | (uint32_t)(w[0] >> 40);
+            } else {
+                b.key[0][i] = 0;
+            }
+            b.val[0][i] = (uint32_t)i;
         }
-        b.val[0][i] = (uint32_t)i;
     }
     __syncthreads();
     // 16-byte stores of the used words only (an odd count rounds up within
@@ -769,13 +793,13 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         const int64_t j = (chunk << 6) + lane;
         const bool active = j < nreads;
         const int rid = active ? (order ? (int)order[j] : (int)j) : 0;
-        const int4 lm = active ? b.qlm[rid] : make_int4(0, 0, 0, 0);
+        const ReadLen lm = decode_len(active ? b.qlm[rid] : encode_len(0, 0, 0));
         if (COUNT && active) {
             if (order) cnt.touch(order + j, 4);
-            cnt.touch(b.qlm + rid, 16);
+            cnt.touch(b.qlm + rid, 8);
         }
-        const int m = lm.x;
-        const bool short_read = active && !(m >= 0 && lm.y < 0);  // long reads are the long kernel's
+        const int m = lm.m;
+        const bool short_read = active && !(m >= 0 && lm.mv < 0);  // long reads are the long kernel's
         const int w = max_i(1, (m + 31) >> 5);
         int wc = 1;
 #pragma unroll
@@ -785,16 +809,16 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         if (!short_read) continue;
         if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
         switch (wc) {
-            case 1: tuned_one<1>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
-            case 2: tuned_one<2>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
-            case 3: tuned_one<3>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
-            case 4: tuned_one<4>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
-            case 5: tuned_one<5>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
-            case 6: tuned_one<6>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
-            case 7: tuned_one<7>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
-            case 8: tuned_one<8>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
-            case 9: tuned_one<9>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
-            default: tuned_one<10>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.y, lm.z, out, cnt); break;
+            case 1: tuned_one<1>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
+            case 2: tuned_one<2>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
+            case 3: tuned_one<3>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
+            case 4: tuned_one<4>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
+            case 5: tuned_one<5>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
+            case 6: tuned_one<6>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
+            case 7: tuned_one<7>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
+            case 8: tuned_one<8>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
+            case 9: tuned_one<9>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
+            default: tuned_one<10>(ix, s_key, s_sa, levels, use_table, b, rid, m, lm.mv, lm.wo, out, cnt); break;
         }
     }
     if constexpr (COUNT) {
@@ -835,15 +859,15 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
     using Cnt = typename std::conditional<COUNT, Count, NoCount>::type;
     Cnt cnt;
     int4 res = make_int4(0, 0, 0, (int)kHitTooLong);
-    const int4 lm = i < nreads ? b.qlm[i] : make_int4(-1, 0, 0, 0);
-    if (COUNT && i < nreads) cnt.touch(b.qlm + i, 16);
-    const int m = lm.x;
-    const bool long_read = m >= 0 && lm.y < 0;  // the long kernel's
+    const ReadLen lm = decode_len(i < nreads ? b.qlm[i] : encode_len(-1, 0, 0));
+    if (COUNT && i < nreads) cnt.touch(b.qlm + i, 8);
+    const int m = lm.m;
+    const bool long_read = m >= 0 && lm.mv < 0;  // the long kernel's
     if (long_read) b.stats[kLongFlag] = 1ull;
     if (m >= 0 && !long_read) {
-        const int mv = lm.y;
+        const int mv = lm.mv;
         uint64_t q[kWMax];
-        const uint64_t *src = query_words(b.qw, (int)i, lm.z);
+        const uint64_t *src = query_words(b.qw, (int)i, lm.wo);
 #pragma unroll
         for (int k = 0; k < kWMax; ++k) q[k] = (k << 5) < m ? src[k] : 0ull;
 #pragma unroll
@@ -948,20 +972,20 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         const int64_t j = first + (c << 6) + lane;
         const bool act = j < nreads;
         const int rid = act ? (order ? (int)order[j] : (int)j) : 0;
-        const int4 lm = act ? b.qlm[rid] : make_int4(-1, 0, 0, 0);
+        const ReadLen lm = decode_len(act ? b.qlm[rid] : encode_len(-1, 0, 0));
         if (COUNT && act) {
             if (order) cnt.touch(order + j, 4);
-            cnt.touch(b.qlm + rid, 16);
+            cnt.touch(b.qlm + rid, 8);
         }
-        const bool is_long = act && lm.x >= 0 && lm.y < 0;
+        const bool is_long = act && lm.m >= 0 && lm.mv < 0;
         uint64_t todo = wave_ballot(is_long);
         if (!todo) continue;
-        int mv_mine = lm.x;
+        int mv_mine = lm.m;
         while (todo) {
             const int src = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
             const int r = __shfl(rid, src, 64);
-            const int m = __shfl(lm.x, src, 64);
+            const int m = __shfl(lm.m, src, 64);
             const int64_t a = offs[r];
             const int b0 = 16 * lane;
             uint32_t half = 0;
@@ -997,8 +1021,8 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         __syncthreads();  // the slots are written; one wave, so this orders LDS only
         if (is_long) {
             const LdsQuery q{slot[lane]};
-            if (COUNT) { nsearched++; nqwords += (uint32_t)((lm.x + 31) >> 5); }
-            out[rid] = match_read<kLongWords>(ix, nullptr, nullptr, 0, use_table, q, lm.x, mv_mine, cnt);
+            if (COUNT) { nsearched++; nqwords += (uint32_t)((lm.m + 31) >> 5); }
+            out[rid] = match_read<kLongWords>(ix, nullptr, nullptr, 0, use_table, q, lm.m, mv_mine, cnt);
             cnt.touch(out + rid, 16);
         }
         __syncthreads();  // before the next chunk rewrites the slots
