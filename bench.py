@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--paper", action="store_true",
                     help="paper-shape workload: 10 Mbp reference, 1024-base queries, sets of 512 to 2,097,152; "
                          "input / kernel / output / total per set (the columns of the paper's Table V)")
+    ap.add_argument("--st", action="store_true",
+                    help="suffix-tree comparison on the --config workload: the flattened suffix tree's search beside "
+                         "the suffix-array path, results compared, index sizes")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: open-loop Poisson requests over resident references")
     ap.add_argument("--serve-refs", default="c2,c4", help="references kept resident for --serve")
@@ -119,6 +122,8 @@ def main():
         return serve_bench(args, np, torch, gen, S)
     if args.paper:
         return paper_bench(args, np, torch, gen, S, ref, reads, text)
+    if args.st:
+        return st_bench(args, np, torch, gen, S, ref, reads, text)
 
     t = time.perf_counter()
     d = S.sa_build_device(text, 0)
@@ -426,6 +431,60 @@ def paper_bench(args, np, torch, gen, S, ref, reads, text):
         "exact_fraction": round(float((out[:, 3] & 1).mean()), 5),
         "index": {"device_build_s": round(t_index, 3)},
         "sets": rows, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def st_bench(args, np, torch, gen, S, ref, reads, text):
+    """The paper's comparison (Sections III and V): the same reads searched
+    through a flattened suffix tree and through the suffix array, device
+    time per batch with HIP events on one stream, results compared read by
+    read, and the device bytes of each index as searched."""
+    dev = torch.device("cuda:0")
+    d = S.sa_build_device(text, 0)
+    t = time.perf_counter()
+    st = S.st_build(S.sa_download(d))
+    t_st = time.perf_counter() - t
+    sd = S.st_upload(st, d)
+    log(f"suffix tree: {st.node_count()} nodes, built on the host in {t_st:.1f}s")
+    N = reads.count
+    d_reads = torch.from_numpy(reads.data).to(dev)
+    d_offs = torch.from_numpy(reads.offs).to(dev)
+    out_sa = torch.zeros((N, 4), dtype=torch.int32, device=dev)
+    out_st = torch.zeros((N, 4), dtype=torch.int32, device=dev)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    S.sa_tune(d, d_reads, d_offs, stream=stream, cache_path=args.tune_cache)
+    cfg = S.cfg(d)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, k):
+        fn()
+        ev[0].record(stream)
+        for _ in range(k):
+            fn()
+        ev[1].record(stream)
+        stream.synchronize()
+        return ev[0].elapsed_time(ev[1]) / k
+
+    ms_sa = timed(lambda: S.match_batch_dev(d, d_reads, d_offs, out_sa, stream=stream, config=cfg), args.steps)
+    ms_st = timed(lambda: S.st_match_batch_dev(sd, d_reads, d_offs, out_st, stream=stream), args.steps)
+    same = bool((out_sa.cpu().numpy() == out_st.cpu().numpy()).all())
+    assert same, "suffix-tree and suffix-array results differ"
+    sa_bytes = 4 * ref.n + 8 * ((ref.n + 31) // 32)
+    line = {
+        "metric": "reads/s: flattened suffix tree vs suffix array, same reads, identical results",
+        "value": round(N / (ms_st * 1e-3), 1), "unit": "reads/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(ms_st, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic (seeded generators, no external data)",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "reference_bp": ref.n},
+        "suffix_tree": {"ms_per_batch": round(ms_st, 4), "reads_per_s": round(N / (ms_st * 1e-3), 1),
+                        "nodes": st.node_count(), "device_bytes": st.device_bytes(),
+                        "host_build_s": round(t_st, 2)},
+        "suffix_array": {"ms_per_batch": round(ms_sa, 4), "reads_per_s": round(N / (ms_sa * 1e-3), 1),
+                         "device_bytes_sa_and_text": sa_bytes, "launch": cfg.as_dict()},
+        "sa_bytes_over_st_bytes": round(sa_bytes / st.device_bytes(), 4),
+        "identical": same,
     }
     print(json.dumps(line), flush=True)
 

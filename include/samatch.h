@@ -233,6 +233,37 @@ int sa_locate_dev(const sa_dindex *d, const sa_hit *d_hits, int64_t nreads, int3
 int sa_locate(const sa_dindex *d, const sa_hit *hits, int64_t nreads, int32_t cap, int32_t min_len,
               int64_t *offs, int32_t *pos, int64_t pos_capacity, int64_t *total);
 
+/* ------------------------------------------------------------ suffix tree */
+
+/* The suffix tree the paper compares the suffix array with (Sections III
+ * and V; it transmits the tree to the GPU as a flattened array and gives
+ * no layout).  Built on the host from a host index (its suffix array and
+ * the LCP array) as the tree of lcp-intervals, flattened into 32-byte nodes
+ * {lb, rb, depth, 0, child[a], child[c], child[g], child[t]}: the node's
+ * suffix-array rows [lb, rb) share `depth` leading bases; child[b] is the
+ * node index of the child continuing with base b, -2 - row for a leaf, -1
+ * for none.  The search walks it from the root and gives the same
+ * (lo, hi, len, flags) as match_batch. */
+typedef struct st_index st_index;    /* host tree                                  */
+typedef struct st_dindex st_dindex;  /* the same tree resident in device memory    */
+
+int st_build(const sa_index *ix, st_index **out);
+void st_free(st_index *t);
+int64_t st_node_count(const st_index *t);
+int32_t st_root(const st_index *t);
+/* Copies the nodes (st_node_count x 8 int32) into out. */
+int st_copy_nodes(const st_index *t, int32_t *out);
+/* Device bytes of the tree as searched: nodes, suffix array, 2-bit text. */
+int64_t st_index_bytes(const st_index *t);
+/* Uploads the nodes; the search reads the text and suffix array of d, which
+ * must be an index of the same text and must outlive the tree. */
+int st_upload(const st_index *t, const sa_dindex *d, st_dindex **out);
+void st_dfree(st_dindex *s);
+/* Device batch as match_batch_dev (reads of up to SA_MAX_READ bases; longer
+ * ones get SA_HIT_TOOLONG), one read per lane in input order.  Async. */
+int st_match_batch_dev(const st_dindex *s, const uint8_t *d_reads, const int64_t *d_offs, int64_t nreads,
+                       sa_hit *d_out, void *hip_stream);
+
 /* ------------------------------------------------------------------ serving */
 
 typedef struct {

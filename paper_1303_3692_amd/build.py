@@ -17,6 +17,7 @@ SOURCES = [
     "errors.cpp",
     "host_index.cpp",
     "dc3.cpp",
+    "suffix_tree.cpp",
     "kernels.hip",
     "sa_construct.hip",
     "device.hip",

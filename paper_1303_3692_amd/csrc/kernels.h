@@ -37,6 +37,14 @@ struct alignas(8 + 8 * kRecWords) RowRec {
 };
 static_assert(sizeof(RowRec) == 8 + 8 * kRecWords, "row record layout");
 
+// Node of the flattened suffix tree: its run of suffix-array rows [lb, rb),
+// the bases its suffixes share (depth), and per base a, c, g, t the child
+// that continues with it (node index, leaf -2 - row, or -1).
+struct alignas(16) StNode {
+    int32_t lb, rb, depth, pad;
+    int32_t child[4];
+};
+
 // Device view of a resident index, passed to kernels by value.
 struct DevIndex {
     const uint64_t *text;      // packed text, 2 bits per base, zero padded
@@ -116,6 +124,12 @@ hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_
 hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b, const uint32_t *order, const uint32_t *sorted_key,
                               int key_shift, uint32_t key_mask, uint32_t long_field, int use_table, int grid,
                               int64_t nreads, void *out, bool count, hipStream_t s);
+
+// Suffix-tree search, one read per lane, reads in input order, each packed
+// into LDS by its wave (reads of up to SA_MAX_READ bases).
+hipError_t launch_search_st(const uint64_t *text, const int32_t *sa, int32_t n, const StNode *nodes, int32_t root,
+                            const uint8_t *reads, const int64_t *offs, int64_t nreads, void *out, int grid,
+                            hipStream_t s);
 
 // Sort key of a long read: the last bucket and an all-ones prefix, so that
 // long reads sort after every other read.

@@ -101,9 +101,9 @@ __device__ __forceinline__ uint64_t text_word(const uint64_t *__restrict__ text,
 // length, capped at min(plen, n - p).  The word loop is unrolled over all W
 // words and predicated, so the query stays in registers (a run-time index
 // into q would move it to scratch memory).
-template <int W, class Cnt>
+template <int W, class Q, class Cnt>
 __device__ __forceinline__ int compare_from(const uint64_t *__restrict__ text, int32_t n,
-                                            const uint64_t (&q)[W], int plen, int32_t p, int k0,
+                                            const Q &q, int plen, int32_t p, int k0,
                                             int &lcp, Cnt &cnt) {
     const int lim = min_i(plen, n - p);
     int res = lim;
@@ -932,6 +932,43 @@ struct LdsQuery {
     __device__ __forceinline__ uint64_t operator[](int k) const { return p[k]; }
 };
 
+// The whole wave packs one read of m <= SA_MAX_READ bases at reads[a..a+m)
+// into dst[0 .. 32): lane l converts bases 16l .. 16l+15 from aligned dword
+// loads (an aligned dword that holds a byte of the read never crosses a
+// page) and writes its half word.  Returns this lane's first non-ACGT base
+// (0x7FFFFFFF if none); the caller takes the minimum over the wave.
+template <class Cnt>
+__device__ __forceinline__ int wave_pack_read(const uint8_t *__restrict__ reads, int64_t a, int m, uint64_t *dst,
+                                              int lane, Cnt &cnt) {
+    const int b0 = 16 * lane;
+    uint32_t half = 0;
+    int bad_at = 0x7FFFFFFF;
+    if (b0 < m) {
+        const uintptr_t x0 = (uintptr_t)(reads + a + b0);
+        const uintptr_t base = x0 & ~(uintptr_t)3;
+        const uint32_t sh = (uint32_t)(x0 & 3u);
+        const uintptr_t stop = (uintptr_t)(reads + a + m);
+        uint32_t dw[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            dw[t] = base + 4u * t < stop ? *reinterpret_cast<const uint32_t *>(base + 4u * t) : 0u;
+            if (base + 4u * t < stop) cnt.touch(reinterpret_cast<const void *>(base + 4u * t), 4);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int rem = m - b0 - 4 * jj;
+            const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : (rem > 0 ? ((1u << (8 * rem)) - 1u) : 0u);
+            uint32_t bad;
+            const uint32_t b8 = pack4_fast(__builtin_amdgcn_alignbyte(dw[jj + 1], dw[jj], sh), keep, bad);
+            if (bad && bad_at == 0x7FFFFFFF) bad_at = b0 + 4 * jj + (int)(__builtin_ctz(bad) >> 3);
+            half = (half << 8) | b8;
+        }
+    }
+    // bases 32k .. 32k+15 (lane 2k) are the high half of word k
+    reinterpret_cast<uint32_t *>(dst + (lane >> 1))[(lane & 1) ? 0 : 1] = half;
+    return bad_at;
+}
+
 // One wave per workgroup.  Long reads sort last: each workgroup finds where
 // they start, then takes 64-row chunks from there.  For every long read of
 // a chunk the whole wave packs it into that lane's LDS slot, 16 bases per
@@ -986,33 +1023,7 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
             todo &= todo - 1;
             const int r = __shfl(rid, src, 64);
             const int m = __shfl(lm.m, src, 64);
-            const int64_t a = offs[r];
-            const int b0 = 16 * lane;
-            uint32_t half = 0;
-            int bad_at = 0x7FFFFFFF;
-            if (b0 < m) {
-                const uintptr_t x0 = (uintptr_t)(reads + a + b0);
-                const uintptr_t base = x0 & ~(uintptr_t)3;
-                const uint32_t sh = (uint32_t)(x0 & 3u);
-                const uintptr_t stop = (uintptr_t)(reads + a + m);
-                uint32_t dw[5];
-#pragma unroll
-                for (int t = 0; t < 5; ++t) {
-                    dw[t] = base + 4u * t < stop ? *reinterpret_cast<const uint32_t *>(base + 4u * t) : 0u;
-                    if (base + 4u * t < stop) cnt.touch(reinterpret_cast<const void *>(base + 4u * t), 4);
-                }
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int rem = m - b0 - 4 * jj;
-                    const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : (rem > 0 ? ((1u << (8 * rem)) - 1u) : 0u);
-                    uint32_t bad;
-                    const uint32_t b8 = pack4_fast(__builtin_amdgcn_alignbyte(dw[jj + 1], dw[jj], sh), keep, bad);
-                    if (bad && bad_at == 0x7FFFFFFF) bad_at = b0 + 4 * jj + (int)(__builtin_ctz(bad) >> 3);
-                    half = (half << 8) | b8;
-                }
-            }
-            // bases 32k .. 32k+15 (lane 2k) are the high half of word k
-            reinterpret_cast<uint32_t *>(&slot[src][lane >> 1])[(lane & 1) ? 0 : 1] = half;
+            const int bad_at = wave_pack_read(reads, offs[r], m, slot[src], lane, cnt);
             int first_bad = bad_at;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) first_bad = min_i(first_bad, __shfl_xor(first_bad, o, 64));
@@ -1039,6 +1050,109 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
     }
 }
 
+// ------------------------------------------------------------------ suffix tree
+
+// Search of the flattened suffix tree: from the root, take the child that
+// continues with the read's next base and compare the read with that
+// child's first suffix from the depth already matched; stop where the read
+// ends, where no child continues, or where the comparison stops inside the
+// edge.  The node or leaf reached holds the rows of the matched prefix: the
+// same (lo, hi, l, exact) as the suffix-array searches.
+template <class Q>
+__device__ __forceinline__ int4 st_match(const uint64_t *__restrict__ text, const int32_t *__restrict__ sa,
+                                         int32_t n, const StNode *__restrict__ nodes, int32_t root, const Q &q,
+                                         int m, int mv) {
+    NoCount cnt;
+    int lb = 0, rb = n, d = 0, l = 0;
+    int node = root;
+    const int plen = mv;
+    for (;;) {
+        if (d >= plen) {
+            l = plen;
+            break;
+        }
+        const int c = (int)((q[d >> 5] >> (62 - 2 * (d & 31))) & 3u);
+        const int ch = nodes[node].child[c];
+        if (ch == -1) {
+            l = d;
+            break;
+        }
+        int clb, crb, cdepth;
+        if (ch >= 0) {
+            const StNode cn = nodes[ch];
+            clb = cn.lb;
+            crb = cn.rb;
+            cdepth = cn.depth;
+        } else {
+            clb = -2 - ch;
+            crb = clb + 1;
+            cdepth = 0;
+        }
+        const int32_t p = sa[clb];
+        if (ch < 0) cdepth = n - p;
+        int lcp;
+        compare_from<kLongWords>(text, n, q, plen, p, d >> 5, lcp, cnt);
+        lb = clb;
+        rb = crb;
+        if (ch < 0 || lcp < cdepth || plen <= cdepth) {
+            l = min_i(lcp, plen);
+            break;
+        }
+        node = ch;
+        d = cdepth;
+    }
+    const int flags = l == m ? (int)kHitExact : 0;
+    if (l == 0) return make_int4(0, n, 0, flags);
+    return make_int4(lb, rb, l, flags);
+}
+
+// One wave per workgroup, 64 reads per chunk in input order: the wave packs
+// each read of the chunk into LDS, then every lane walks the tree for its own.
+__global__ __launch_bounds__(64) void search_st_kernel(const uint64_t *__restrict__ text,
+                                                       const int32_t *__restrict__ sa, int32_t n,
+                                                       const StNode *__restrict__ nodes, int32_t root,
+                                                       const uint8_t *__restrict__ reads,
+                                                       const int64_t *__restrict__ offs, int64_t nreads,
+                                                       int4 *__restrict__ out) {
+    __shared__ uint64_t slot[64][kLongWords];
+    const int lane = threadIdx.x;
+    NoCount cnt;
+    const int64_t nchunks = (nreads + 63) >> 6;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t i = (c << 6) + lane;
+        const bool act = i < nreads;
+        int64_t a = 0;
+        int m = -1;
+        if (act) {
+            a = offs[i];
+            const int64_t m64 = offs[i + 1] - a;
+            m = (m64 >= 0 && m64 <= SA_MAX_READ) ? (int)m64 : -1;
+        }
+        uint64_t todo = wave_ballot(act && m >= 0);
+        int mv = m;
+        while (todo) {
+            const int src = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t ra = __shfl(a, src, 64);
+            const int rm = __shfl(m, src, 64);
+            int first_bad = wave_pack_read(reads, ra, rm, slot[src], lane, cnt);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) first_bad = min_i(first_bad, __shfl_xor(first_bad, o, 64));
+            if (lane == src) mv = min_i(rm, first_bad);
+        }
+        __syncthreads();  // one wave: orders the LDS slots
+        if (act) {
+            if (m < 0) {
+                out[i] = make_int4(0, 0, 0, (int)kHitTooLong);
+            } else {
+                const LdsQuery q{slot[lane]};
+                out[i] = st_match(text, sa, n, nodes, root, q, m, mv);
+            }
+        }
+        __syncthreads();  // before the next chunk rewrites the slots
+    }
+}
+
 }  // namespace
 
 hipError_t prepare_kernels() {
@@ -1047,6 +1161,14 @@ hipError_t prepare_kernels() {
         (e = allow_tile_lds<1024, false>()) != hipSuccess || (e = allow_tile_lds<256, true>()) != hipSuccess)
         return e;
     return hipSuccess;
+}
+
+hipError_t launch_search_st(const uint64_t *text, const int32_t *sa, int32_t n, const StNode *nodes, int32_t root,
+                            const uint8_t *reads, const int64_t *offs, int64_t nreads, void *out, int grid,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(search_st_kernel, dim3((unsigned)(grid > 0 ? grid : 1)), dim3(64), 0, s, text, sa, n, nodes,
+                       root, reads, offs, nreads, static_cast<int4 *>(out));
+    return hipGetLastError();
 }
 
 hipError_t launch_build_rows(const uint64_t *text, const int32_t *sa, int32_t n, RowRec *rows, hipStream_t s) {

@@ -27,6 +27,8 @@ EXPORTS = [
     "sa_default_cfg", "match_batch", "match_batch_dev",
     "sa_stage_times", "sa_probe_counts", "sa_tune",
     "sa_locate_dev", "sa_locate",
+    "st_build", "st_free", "st_node_count", "st_root", "st_copy_nodes", "st_index_bytes", "st_upload", "st_dfree",
+    "st_match_batch_dev",
     "sa_server_create", "match_submit", "match_poll", "sa_server_destroy", "sa_strerror", "sa_last_error",
 ]
 
@@ -97,6 +99,15 @@ def lib():
             "sa_tune": ([p, p, p, i64, p, ctypes.c_char_p, ctypes.POINTER(MatchCfg), ctypes.POINTER(ctypes.c_double)], i32),
             "sa_locate_dev": ([p, p, i64, i32, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_int64)], i32),
             "sa_locate": ([p, p, i64, i32, i32, p, p, i64, ctypes.POINTER(ctypes.c_int64)], i32),
+            "st_build": ([p, pp], i32),
+            "st_free": ([p], None),
+            "st_node_count": ([p], i64),
+            "st_root": ([p], i32),
+            "st_copy_nodes": ([p, p], i32),
+            "st_index_bytes": ([p], i64),
+            "st_upload": ([p, p, pp], i32),
+            "st_dfree": ([p], None),
+            "st_match_batch_dev": ([p, p, p, i64, p, p], i32),
             "sa_server_create": ([ctypes.POINTER(ctypes.c_void_p), i32, ctypes.POINTER(ServerOpts), pp], i32),
             "match_submit": ([p, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_uint64)], i32),
             "match_poll": ([p, ctypes.c_uint64, i64, ctypes.POINTER(ReqStats)], i32),
@@ -304,6 +315,86 @@ def sa_probe_counts(d: DIndex, stream=None) -> dict:
     _check(lib().sa_probe_counts(d.ptr, _stream_handle(stream), c), "sa_probe_counts")
     return {"global_probes": c[0], "text_words": c[1], "tile_probes": c[2], "reads": c[3], "query_words": c[4],
             "key_words": c[5], "table_lookups": c[6], "touched_bytes": c[7]}
+
+
+class StIndex:
+    """Flattened suffix tree (st_index) built on the host from an Index."""
+
+    def __init__(self, ptr):
+        self._p = ptr
+
+    @property
+    def ptr(self):
+        return self._p
+
+    def node_count(self) -> int:
+        return int(lib().st_node_count(self._p))
+
+    def root(self) -> int:
+        return int(lib().st_root(self._p))
+
+    def nodes(self) -> np.ndarray:
+        """(count, 8) int32: lb, rb, depth, 0, child[a], child[c], child[g], child[t]."""
+        out = np.zeros((self.node_count(), 8), dtype=np.int32)
+        _check(lib().st_copy_nodes(self._p, out.ctypes.data), "st_copy_nodes")
+        return out
+
+    def device_bytes(self) -> int:
+        return int(lib().st_index_bytes(self._p))
+
+    def free(self):
+        if self._p:
+            lib().st_free(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class StDIndex:
+    """Suffix tree resident on the device, searching a resident index's text and SA."""
+
+    def __init__(self, ptr, d):
+        self._p = ptr
+        self._d = d  # the resident index must outlive the tree
+
+    @property
+    def ptr(self):
+        return self._p
+
+    def free(self):
+        if self._p:
+            lib().st_dfree(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def st_build(ix: Index) -> StIndex:
+    out = ctypes.c_void_p()
+    _check(lib().st_build(ix.ptr, ctypes.byref(out)), "st_build")
+    return StIndex(out)
+
+
+def st_upload(t: StIndex, d: DIndex) -> StDIndex:
+    out = ctypes.c_void_p()
+    _check(lib().st_upload(t.ptr, d.ptr, ctypes.byref(out)), "st_upload")
+    return StDIndex(out, d)
+
+
+def st_match_batch_dev(sd: StDIndex, d_reads, d_offs, d_out, nreads: int | None = None, stream=None) -> None:
+    """Suffix-tree search of a device batch (torch tensors, as match_batch_dev)."""
+    n = (d_offs.numel() - 1) if nreads is None else nreads
+    _check(lib().st_match_batch_dev(sd.ptr, ctypes.c_void_p(d_reads.data_ptr()), ctypes.c_void_p(d_offs.data_ptr()),
+                                    n, ctypes.c_void_p(d_out.data_ptr()), _stream_handle(stream)),
+           "st_match_batch_dev")
 
 
 def locate(d: DIndex, hits, cap: int, min_len: int = 0):
