@@ -579,45 +579,67 @@ __device__ __forceinline__ void pack_from_global(const uint8_t *__restrict__ rea
     w0 = dst[0];
 }
 
-// Packing: each workgroup copies the bytes of its 256 consecutive reads
-// into LDS with coalesced, aligned 16-byte loads, then each thread packs
-// its read from LDS four bases at a time into registers.  Reads whose
-// bytes are not in the staged span (offsets that are not contiguous, or a
-// span larger than the staging buffer) take the global path.  The packed
-// words then go back through LDS so that the workgroup's 256 slots of
-// kWMax words (one contiguous range of the output) are written with
-// coalesced 16-byte stores.  Read i is reads[offs[i] .. offs[i+1]), or
-// reads[offs[i] .. ends[i]) when an end array is given (reads scattered
-// over a larger buffer; always the global path).
+// Packing: each workgroup converts the bytes of its 256 consecutive reads
+// with coalesced, aligned 16-byte loads into a stream of 2-bit codes in
+// LDS (16 bases per word, 12 KB for 48 KB of ASCII) and a flag per byte
+// that is not a base; each thread then takes its read's words out of the
+// stream with funnel shifts and finds its first non-base from the flags.
+// Reads whose bytes are not in the converted span (offsets that are not
+// contiguous, or a span larger than 48 KB) take the global path.  The
+// packed words go back through LDS so that the workgroup's run of words is
+// written with coalesced 16-byte stores.  Read i is reads[offs[i] ..
+// offs[i+1]), or reads[offs[i] .. ends[i]) when an end array is given
+// (reads scattered over a larger buffer; always the global path).
 constexpr int kPackBlock = 256;
-constexpr int kPackStage = 48 * 1024;
-static_assert(kPackBlock * kWMax * 8 <= kPackStage, "packed slots must fit in the staging buffer");
+constexpr int kPackChunks = 3072;  // 16-byte chunks of ASCII a workgroup converts through LDS (48 KB)
+static_assert((kPackChunks + 4) * 6 <= (kPackBlock * kWMax + 8) * 8, "code stream and flags fit the buffer");
 
-// word k of a register array, written with a run-time k (select chain)
-__device__ __forceinline__ void put_word(uint64_t (&w)[kWMax], int k, uint64_t v) {
-#pragma unroll
-    for (int t = 0; t < kWMax; ++t) w[t] = (t == k) ? v : w[t];
+// The 0x80 flags of pack4_fast's four bytes as four bits, byte 0 lowest.
+__device__ __forceinline__ uint32_t bad_nibble(uint32_t bad) {
+    return ((bad >> 7) & 1u) | ((bad >> 14) & 2u) | ((bad >> 21) & 4u) | ((bad >> 28) & 8u);
 }
 
 __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restrict__ reads,
                                                           const int64_t *__restrict__ offs,
                                                           const int64_t *__restrict__ ends, int64_t nreads,
                                                           BatchBuffers b, BucketTable bt) {
-    __shared__ uint32_t stage[kPackStage / 4 + 8];
+    // the span's bases as a code stream (16 per word, first in the top bits)
+    // and a flag per byte that is not a base; later the packed words
+    __shared__ uint64_t lds_buf[kPackBlock * kWMax + 8];
+    uint32_t *codes = reinterpret_cast<uint32_t *>(lds_buf);
+    uint16_t *badm = reinterpret_cast<uint16_t *>(codes + kPackChunks + 4);
     const int64_t r0 = (int64_t)blockIdx.x * kPackBlock;
     const int64_t r1 = r0 + kPackBlock < nreads ? r0 + kPackBlock : nreads;
     const int64_t i = r0 + threadIdx.x;
     if (blockIdx.x == 0 && threadIdx.x < kStatWords) b.stats[threadIdx.x] = 0ull;
+    // with an end array, the workgroup's reads still form one span when each
+    // ends where the next starts (the usual case for a request's reads)
+    bool contiguous = true;
+    if (ends) contiguous = __syncthreads_and(i + 1 >= r1 || ends[i] == offs[i + 1]) != 0;
     const int64_t span0 = offs[r0];
-    const int64_t span1 = ends ? span0 : offs[r1];
+    const int64_t span1 = ends ? (contiguous ? ends[r1 - 1] : span0) : offs[r1];
     const uintptr_t A0 = (uintptr_t)(reads + span0) & ~(uintptr_t)15;
     const uintptr_t A1 = ((uintptr_t)(reads + span1) + 15) & ~(uintptr_t)15;
-    const bool staged = !ends && span1 > span0 && A1 - A0 <= (uintptr_t)kPackStage;
+    const bool staged = contiguous && span1 > span0 && A1 - A0 <= (uintptr_t)kPackChunks * 16u;
     if (staged) {
-        // every aligned 16-byte chunk here holds a byte of [span0, span1)
-        for (uintptr_t c = A0 + 16u * threadIdx.x; c < A1; c += 16u * kPackBlock)
-            *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(stage) + (c - A0)) =
-                *reinterpret_cast<const uint4 *>(c);
+        // every aligned 16-byte chunk here holds a byte of [span0, span1):
+        // coalesced loads, converted on the way into LDS
+        const int nvec = (int)((A1 - A0) >> 4);
+        const uint4 *src = reinterpret_cast<const uint4 *>(A0);
+        for (int c = threadIdx.x; c < nvec; c += kPackBlock) {
+            const uint4 v = src[c];
+            uint32_t bad, code, bits;
+            code = pack4_fast(v.x, 0xFFFFFFFFu, bad);
+            bits = bad_nibble(bad);
+            code = (code << 8) | pack4_fast(v.y, 0xFFFFFFFFu, bad);
+            bits |= bad_nibble(bad) << 4;
+            code = (code << 8) | pack4_fast(v.z, 0xFFFFFFFFu, bad);
+            bits |= bad_nibble(bad) << 8;
+            code = (code << 8) | pack4_fast(v.w, 0xFFFFFFFFu, bad);
+            bits |= bad_nibble(bad) << 12;
+            codes[c] = code;
+            badm[c] = (uint16_t)bits;
+        }
     }
     __syncthreads();
     uint64_t w[kWMax];
@@ -634,29 +656,29 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
             m = (int)m64;
             mv = m;
             if (staged && a >= span0 && e <= span1) {
-                // word k from dwords 8k .. 8k+8 of the staged span, read together
-                const uint32_t q = (uint32_t)((uintptr_t)(reads + a) - A0);
-                const uint32_t *src = stage + (q >> 2);
-                const uint32_t sh = q & 3u;
+                // word k: bases s + 32k .. s + 32k + 31 of the code stream
+                const uint32_t st0 = (uint32_t)((uintptr_t)(reads + a) - A0);
 #pragma unroll
                 for (int k = 0; k < kWMax; ++k) {
                     if (32 * k < m) {
-                        uint32_t dwv[9];
-#pragma unroll
-                        for (int t = 0; t < 9; ++t) dwv[t] = src[8 * k + t];
-                        uint32_t half[2] = {0u, 0u};
-#pragma unroll
-                        for (int jj = 0; jj < 8; ++jj) {
-                            const int rem = m - 32 * k - 4 * jj;
-                            const uint32_t dw = __builtin_amdgcn_alignbyte(dwv[jj + 1], dwv[jj], sh);
-                            const uint32_t keep =
-                                rem >= 4 ? 0xFFFFFFFFu : (rem > 0 ? ((1u << (8 * rem)) - 1u) : 0u);
-                            uint32_t bad;
-                            const uint32_t b8 = pack4_fast(dw, keep, bad);
-                            if (bad && mv == m) mv = 32 * k + 4 * jj + (__builtin_ctz(bad) >> 3);
-                            half[jj >> 2] = (half[jj >> 2] << 8) | b8;
+                        const uint32_t bpos = st0 + 32u * (uint32_t)k, q = bpos >> 4, r = bpos & 15u;
+                        const uint64_t hi = ((uint64_t)codes[q] << 32) | codes[q + 1];
+                        uint64_t x = r ? (hi << (2 * r)) | (codes[q + 2] >> (32 - 2 * r)) : hi;
+                        const int rem = m - 32 * k;
+                        if (rem < 32) x &= ~0ull << (64 - 2 * rem);
+                        w[k] = x;
+                    }
+                }
+                if (m > 0) {  // first byte that is not a base
+                    const uint32_t q0 = st0 >> 4, q1 = (st0 + (uint32_t)m - 1) >> 4;
+                    for (uint32_t q = q0; q <= q1; ++q) {
+                        uint32_t bits = badm[q];
+                        if (q == q0) bits &= 0xFFFFu << (st0 & 15u);
+                        if (q == q1) bits &= (2u << ((st0 + (uint32_t)m - 1) & 15u)) - 1u;
+                        if (bits) {
+                            mv = (int)(q * 16u + (uint32_t)__builtin_ctz(bits) - st0);
+                            break;
                         }
-                        w[k] = ((uint64_t)half[0] << 32) | half[1];
                     }
                 }
             } else {
@@ -674,8 +696,8 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
     const int nw = (i < nreads && m >= 0 && mv >= 0) ? (m > 0 ? (m + 31) >> 5 : 1) : 0;
     uint32_t wo;
     const uint32_t run_words = block_exclusive_scan((uint32_t)nw, wo, scan_tmp);
-    __syncthreads();  // the staged bytes are no longer needed
-    uint64_t *slots = reinterpret_cast<uint64_t *>(stage);
+    __syncthreads();  // the code stream is no longer needed
+    uint64_t *slots = lds_buf;
     if (i < nreads) {
 #pragma unroll
         for (int t = 0; t < kWMax; ++t)
