@@ -104,7 +104,7 @@ void sa_free(sa_index *ix);                           /* NULL is a no-op        
  * never touch the text), the table of the top levels of the
  * implicit binary-search tree that the tuned kernel stages in LDS (the tile
  * of Section IV), and, for n >= 4096, a prefix table: for every string v of
- * k = round(log4 n) bases (4 <= k <= 14), the first SA row whose suffix is
+ * k = round(log4 n) + 1 bases (4 <= k <= 14), the first SA row whose suffix is
  * not below v (4^k + 1 int32 entries).  The host index may be freed
  * afterwards.  Released with sa_dfree (NULL is a no-op). */
 int sa_upload(const sa_index *ix, int device, sa_dindex **out);
@@ -134,12 +134,14 @@ int sa_dindex_build_info(const sa_dindex *d, int *steps, int64_t *sorted_pairs);
 
 enum { SA_KERNEL_TUNED = 0, SA_KERNEL_PLAIN = 1 };
 
-/* Launch configuration.  Zero fields take the tuned defaults of the index
- * (sa_tune), else built-in defaults. */
+/* Launch configuration.  A NULL configuration means the index's defaults
+ * (sa_tune's choice once it has run, else built-in ones).  In a given one,
+ * a zero tile_levels, block, blocks_per_cu, group or nbuckets takes the
+ * index's default; every other field is used as given. */
 typedef struct {
     int kernel;          /* SA_KERNEL_TUNED or SA_KERNEL_PLAIN                     */
     int tile_levels;     /* tuned: levels of the search tree held in LDS (1..13)   */
-    int block;           /* tuned: threads per workgroup (64..1024, multiple of 64)*/
+    int block;           /* tuned: threads per workgroup: 256, 512 or 1024         */
     int blocks_per_cu;   /* tuned: persistent workgroups per compute unit          */
     int nbuckets;        /* tuned: length buckets (1..8)                           */
     int bucket_edge[8];  /* tuned: bucket b holds reads with m <= bucket_edge[b];

