@@ -958,31 +958,44 @@ struct LdsQuery {
 // The whole wave packs one read of m <= SA_MAX_READ bases at reads[a..a+m)
 // into dst[0 .. 32): lane l converts bases 16l .. 16l+15 from aligned dword
 // loads (an aligned dword that holds a byte of the read never crosses a
-// page) and writes its half word.  Returns this lane's first non-ACGT base
-// (0x7FFFFFFF if none); the caller takes the minimum over the wave.
+// page) and writes its half word.  Split in two so that a wave can have the
+// loads of several reads in flight before it converts them.
+struct PackLoad {
+    uint32_t dw[5];
+    uint32_t sh;
+};
+
 template <class Cnt>
-__device__ __forceinline__ int wave_pack_read(const uint8_t *__restrict__ reads, int64_t a, int m, uint64_t *dst,
-                                              int lane, Cnt &cnt) {
+__device__ __forceinline__ PackLoad wave_pack_load(const uint8_t *__restrict__ reads, int64_t a, int m, int lane,
+                                                   Cnt &cnt) {
+    PackLoad pl;
+    const int b0 = 16 * lane;
+    const uintptr_t x0 = (uintptr_t)(reads + a + b0);
+    const uintptr_t base = x0 & ~(uintptr_t)3;
+    const uintptr_t stop = (uintptr_t)(reads + a + m);
+    pl.sh = (uint32_t)(x0 & 3u);
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        const bool in = b0 < m && base + 4u * t < stop;
+        pl.dw[t] = in ? *reinterpret_cast<const uint32_t *>(base + 4u * t) : 0u;
+        if (in) cnt.touch(reinterpret_cast<const void *>(base + 4u * t), 4);
+    }
+    return pl;
+}
+
+// Returns this lane's first non-ACGT base (0x7FFFFFFF if none); the caller
+// takes the minimum over the wave.
+__device__ __forceinline__ int wave_pack_store(const PackLoad &pl, int m, uint64_t *dst, int lane) {
     const int b0 = 16 * lane;
     uint32_t half = 0;
     int bad_at = 0x7FFFFFFF;
     if (b0 < m) {
-        const uintptr_t x0 = (uintptr_t)(reads + a + b0);
-        const uintptr_t base = x0 & ~(uintptr_t)3;
-        const uint32_t sh = (uint32_t)(x0 & 3u);
-        const uintptr_t stop = (uintptr_t)(reads + a + m);
-        uint32_t dw[5];
-#pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            dw[t] = base + 4u * t < stop ? *reinterpret_cast<const uint32_t *>(base + 4u * t) : 0u;
-            if (base + 4u * t < stop) cnt.touch(reinterpret_cast<const void *>(base + 4u * t), 4);
-        }
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const int rem = m - b0 - 4 * jj;
             const uint32_t keep = rem >= 4 ? 0xFFFFFFFFu : (rem > 0 ? ((1u << (8 * rem)) - 1u) : 0u);
             uint32_t bad;
-            const uint32_t b8 = pack4_fast(__builtin_amdgcn_alignbyte(dw[jj + 1], dw[jj], sh), keep, bad);
+            const uint32_t b8 = pack4_fast(__builtin_amdgcn_alignbyte(pl.dw[jj + 1], pl.dw[jj], pl.sh), keep, bad);
             if (bad && bad_at == 0x7FFFFFFF) bad_at = b0 + 4 * jj + (int)(__builtin_ctz(bad) >> 3);
             half = (half << 8) | b8;
         }
@@ -990,6 +1003,44 @@ __device__ __forceinline__ int wave_pack_read(const uint8_t *__restrict__ reads,
     // bases 32k .. 32k+15 (lane 2k) are the high half of word k
     reinterpret_cast<uint32_t *>(dst + (lane >> 1))[(lane & 1) ? 0 : 1] = half;
     return bad_at;
+}
+
+// Packs the reads of the lanes in `todo` (a wave-uniform mask; rows `rid`,
+// starts `start`, lengths `len` per lane) into their lanes' LDS slots, eight
+// reads' loads in flight at a time; *mv of each such lane becomes its
+// length up to the first non-ACGT base.
+constexpr int kPackInFlight = 8;
+
+template <class Cnt>
+__device__ __forceinline__ void wave_pack_reads(const uint8_t *__restrict__ reads, uint64_t todo, int64_t start,
+                                                int len, uint64_t (*slot)[kLongWords], int lane, int &mv,
+                                                Cnt &cnt) {
+    while (todo) {
+        int src[kPackInFlight], m[kPackInFlight];
+        PackLoad pl[kPackInFlight];
+        int nb = 0;
+#pragma unroll
+        for (int u = 0; u < kPackInFlight; ++u) {
+            src[u] = 0;
+            m[u] = 0;
+            if (todo) {
+                src[u] = __ffsll((unsigned long long)todo) - 1;
+                todo &= todo - 1;
+                m[u] = __shfl(len, src[u], 64);
+                pl[u] = wave_pack_load(reads, __shfl(start, src[u], 64), m[u], lane, cnt);
+                nb = u + 1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPackInFlight; ++u) {
+            if (u < nb) {
+                int first_bad = wave_pack_store(pl[u], m[u], slot[src[u]], lane);
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) first_bad = min_i(first_bad, __shfl_xor(first_bad, o, 64));
+                if (lane == src[u]) mv = min_i(m[u], first_bad);
+            }
+        }
+    }
 }
 
 // One wave per workgroup.  In a sorted batch long reads sort last: each
@@ -1042,17 +1093,7 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         uint64_t todo = wave_ballot(is_long);
         if (!todo) continue;
         int mv_mine = lm.m;
-        while (todo) {
-            const int src = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1;
-            const int r = __shfl(rid, src, 64);
-            const int m = __shfl(lm.m, src, 64);
-            const int bad_at = wave_pack_read(reads, offs[r], m, slot[src], lane, cnt);
-            int first_bad = bad_at;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) first_bad = min_i(first_bad, __shfl_xor(first_bad, o, 64));
-            if (lane == src) mv_mine = min_i(m, first_bad);
-        }
+        wave_pack_reads(reads, todo, is_long ? offs[rid] : 0, lm.m, slot, lane, mv_mine, cnt);
         __syncthreads();  // the slots are written; one wave, so this orders LDS only
         if (is_long) {
             const LdsQuery q{slot[lane]};
@@ -1152,18 +1193,9 @@ __global__ __launch_bounds__(64) void search_st_kernel(const uint64_t *__restric
             const int64_t m64 = offs[i + 1] - a;
             m = (m64 >= 0 && m64 <= SA_MAX_READ) ? (int)m64 : -1;
         }
-        uint64_t todo = wave_ballot(act && m >= 0);
+        const uint64_t todo = wave_ballot(act && m >= 0);
         int mv = m;
-        while (todo) {
-            const int src = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1;
-            const int64_t ra = __shfl(a, src, 64);
-            const int rm = __shfl(m, src, 64);
-            int first_bad = wave_pack_read(reads, ra, rm, slot[src], lane, cnt);
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) first_bad = min_i(first_bad, __shfl_xor(first_bad, o, 64));
-            if (lane == src) mv = min_i(rm, first_bad);
-        }
+        wave_pack_reads(reads, todo, a, m, slot, lane, mv, cnt);
         __syncthreads();  // one wave: orders the LDS slots
         if (act) {
             if (m < 0) {
