@@ -196,15 +196,22 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         e = launch_search_plain(d->view, ws->b, nreads, d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "plain search launch");
     } else {
-        const int grid = std::max(1, d->cu_count * c.blocks_per_cu);
-        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, c.group, ws->b, order, nreads,
+        // persistent workgroups; a batch too small to give each of them
+        // `group` chunks of 64 reads takes smaller blocks, and no more
+        // workgroups than there are blocks (each one stages the tile)
+        const int64_t chunks = (nreads + 63) / 64, gmax = std::max<int64_t>(1, (int64_t)d->cu_count * c.blocks_per_cu);
+        const int group = (int)std::max<int64_t>(1, std::min<int64_t>(c.group, chunks / gmax));
+        const int grid = (int)std::min<int64_t>(gmax, (chunks + group - 1) / group);
+        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, group, ws->b, order, nreads,
                                 d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
     // reads longer than kShortMax: their own kernel, over the tail of the sorted order
     const uint32_t long_field = (long_read_key(c.nbuckets) >> key_shift) & key_mask;
     e = launch_search_long(d->view, d_reads, d_offs, ws->b, order, sorted_key, key_shift, key_mask, long_field,
-                           c.prefix_table, std::max(1, d->cu_count * 8), nreads, d_out, c.count != 0, s);
+                           c.prefix_table,
+                           (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)d->cu_count * 8, (nreads + 63) / 64)),
+                           nreads, d_out, c.count != 0, s);
     if (e != hipSuccess) return hip_fail(e, "long-read search launch");
     if (prof && (e = hipEventRecord(ws->ev[3], s)) != hipSuccess) return hip_fail(e, "event record");
     ws->profiled = prof;

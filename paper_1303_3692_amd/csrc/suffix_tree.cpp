@@ -224,7 +224,9 @@ extern "C" int st_match_batch_dev(const st_dindex *s, const uint8_t *d_reads, co
     DeviceGuard g(s->d->device);
     if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
     hipError_t e = launch_search_st(s->d->d_text, s->d->d_sa, (int32_t)s->d->n, s->d_nodes, s->root, d_reads, d_offs,
-                                    nreads, d_out, std::max(1, s->d->cu_count * 8),
+                                    nreads, d_out,
+                                    (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)s->d->cu_count * 8,
+                                                                                (nreads + 63) / 64)),
                                     static_cast<hipStream_t>(hip_stream));
     return e == hipSuccess ? SA_OK : hip_fail(e, "suffix tree search launch");
 }
