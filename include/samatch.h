@@ -162,6 +162,11 @@ typedef struct {
                             (1..64): workgroup rank r takes blocks r, r+G, ... */
     int prefix_table;    /* tuned: 1 = start each search from the prefix table
                             (when the index has one), 0 = from the LDS tile     */
+    int inline_pack;     /* tuned, reads in input order (sort 0) given by CSR
+                            offsets: 1 = the search kernel converts its reads
+                            from ASCII itself (no separate pack pass), when its
+                            tile and packing areas fit in LDS (160 KB);
+                            0 = a pack pass first                               */
 } sa_match_cfg;
 
 /* Fill cfg with the index's current defaults. */

@@ -132,6 +132,7 @@ int check_cfg(const sa_dindex *d, const sa_match_cfg &c) {
     if (c.group < 1 || c.group > 64) return fail(SA_EINVAL, "group must be in 1..64");
     if (c.sort != 0 && c.sort != 1 && c.sort != 8 && c.sort != 16 && c.sort != 24)
         return fail(SA_EINVAL, "sort must be 0, 1, 8, 16 or 24");
+    if (c.inline_pack != 0 && c.inline_pack != 1) return fail(SA_EINVAL, "inline_pack must be 0 or 1");
     for (int i = 0; i + 1 < c.nbuckets; i++)
         if (c.bucket_edge[i] < 1 || (i > 0 && c.bucket_edge[i] <= c.bucket_edge[i - 1]))
             return fail(SA_EINVAL, "bucket edges must ascend");
@@ -164,15 +165,24 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
     const bool prof = c.profile != 0;
     hipError_t e = hipSuccess;
     if (prof && (e = hipEventRecord(ws->ev[0], s)) != hipSuccess) return hip_fail(e, "event record");
-    BucketTable bt = bucket_table(c);
-    bt.keys = (c.kernel == SA_KERNEL_TUNED && c.sort) ? 1 : 0;
-    e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bt, s);
-    if (e != hipSuccess) return hip_fail(e, "pack launch");
+    // reads in input order from CSR offsets: the tuned kernel can pack them
+    // itself when its tile and the waves' packing areas fit in LDS
+    const bool inl = c.kernel == SA_KERNEL_TUNED && c.inline_pack && c.sort == 0 && d_ends == nullptr &&
+                     tuned_lds_bytes(c.tile_levels, c.count ? 256 : c.block, true) <= inline_lds_limit();
+    if (inl) {
+        e = launch_clear_stats(ws->b, s);
+        if (e != hipSuccess) return hip_fail(e, "stats clear launch");
+    } else {
+        BucketTable bt = bucket_table(c);
+        bt.keys = (c.kernel == SA_KERNEL_TUNED && c.sort) ? 1 : 0;
+        e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bt, s);
+        if (e != hipSuccess) return hip_fail(e, "pack launch");
+    }
     if (prof && (e = hipEventRecord(ws->ev[1], s)) != hipSuccess) return hip_fail(e, "event record");
     const uint32_t *order = nullptr, *sorted_key = nullptr;
     int key_shift = 0;
     uint32_t key_mask = 0;
-    if (c.kernel == SA_KERNEL_TUNED && c.sort) {
+    if (c.kernel == SA_KERNEL_TUNED && c.sort && !inl) {
         // The key is (length bucket << 24 | first 12 bases).  Prefix bits
         // beyond about one group per 64-read chunk put no more lanes on
         // shared pivots, so the sort covers the top 8, 16 or 24 prefix bits
@@ -202,14 +212,14 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         const int64_t chunks = (nreads + 63) / 64, gmax = std::max<int64_t>(1, (int64_t)d->cu_count * c.blocks_per_cu);
         const int group = (int)std::max<int64_t>(1, std::min<int64_t>(c.group, chunks / gmax));
         const int grid = (int)std::min<int64_t>(gmax, (chunks + group - 1) / group);
-        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, group, ws->b, order, nreads,
-                                d_out, c.count != 0, s);
+        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, group, ws->b, order,
+                                inl ? d_reads : nullptr, inl ? d_offs : nullptr, nreads, d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
     // reads longer than kShortMax: their own kernel, over the tail of the sorted order
     const uint32_t long_field = (long_read_key(c.nbuckets) >> key_shift) & key_mask;
     e = launch_search_long(d->view, d_reads, d_offs, ws->b, order, sorted_key, key_shift, key_mask, long_field,
-                           c.prefix_table,
+                           c.prefix_table, inl,
                            (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)d->cu_count * 8, (nreads + 63) / 64)),
                            nreads, d_out, c.count != 0, s);
     if (e != hipSuccess) return hip_fail(e, "long-read search launch");
@@ -378,6 +388,7 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
     c.use_graph = 0;
     c.group = 4;
     c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
+    c.inline_pack = 1;
     *out = d.release();
     return SA_OK;
 }

@@ -14,6 +14,9 @@ constexpr int kLongWords = SA_MAX_READ / 32;  // words of a read on the long-rea
 constexpr int kStatWords = 9;
 constexpr int kLongFlag = 8;
 constexpr int kMaxTileLevels = 13;        // 8191 nodes x 12 B = 96 KiB of LDS
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of a gfx950 compute unit
+constexpr int kInlineVec = 768;           // 16-byte pieces of ASCII a wave packs in the search kernel (12 KB)
+constexpr int kInlineWaveBytes = (kInlineVec + 4) * 6 + 8;  // its codes (4 B) and flags (2 B) per piece
 constexpr int kSortBlock = 256;           // radix sort: threads per workgroup
 constexpr int kSortItems = 16;            // keys per thread per pass
 constexpr int kSortTile = kSortBlock * kSortItems;
@@ -108,9 +111,21 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi
 // count = true runs the instrumented variant that fills b.stats.
 // group: 64-read chunks per block of the work split (see the kernel).
 // use_table: start LB searches from the prefix table (when the index has one).
+// offs not NULL: the kernel packs the reads itself from reads/offs (CSR,
+// input order: order must be NULL; no pack kernel runs, and b.stats must be
+// cleared before, see launch_clear_stats); the dynamic LDS is then
+// tuned_lds_bytes(tile_levels, block, true), which must not exceed
+// inline_lds_limit().
 hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int use_table, int block, int grid,
-                               int group, const BatchBuffers &b, const uint32_t *order, int64_t nreads,
-                               void *out, bool count, hipStream_t s);
+                               int group, const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
+                               const int64_t *offs, int64_t nreads, void *out, bool count, hipStream_t s);
+
+// Most dynamic LDS an inline-packing tuned kernel may take on the device
+// that prepare_kernels last ran on (0 before).
+size_t inline_lds_limit();
+
+// Zero b.stats (the pack kernel does it otherwise).
+hipError_t launch_clear_stats(const BatchBuffers &b, hipStream_t s);
 
 hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_t nreads,
                                void *out, bool count, hipStream_t s);
@@ -121,9 +136,12 @@ hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_
 // long reads sort last, from the first row whose key bits
 // [key_shift, key_shift + bits(key_mask)) reach long_field.
 // Read i starts at reads[offs[i]] (offs holds the start array in gather mode).
-hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b, const uint32_t *order, const uint32_t *sorted_key,
-                              int key_shift, uint32_t key_mask, uint32_t long_field, int use_table, int grid,
-                              int64_t nreads, void *out, bool count, hipStream_t s);
+// lengths_from_offs: take each read's length from the CSR offsets instead of
+// the pack kernel's record (when the search kernel packed its reads).
+hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b,
+                              const uint32_t *order, const uint32_t *sorted_key, int key_shift, uint32_t key_mask,
+                              uint32_t long_field, int use_table, bool lengths_from_offs, int grid, int64_t nreads,
+                              void *out, bool count, hipStream_t s);
 
 // Suffix-tree search, one read per lane, reads in input order, each packed
 // into LDS by its wave (reads of up to SA_MAX_READ bases).
@@ -136,9 +154,18 @@ hipError_t launch_search_st(const uint64_t *text, const int32_t *sa, int32_t n, 
 __host__ __device__ inline uint32_t long_read_key(int nbuckets) { return ((uint32_t)(nbuckets - 1) << 24) | 0xFFFFFFu; }
 
 // Dynamic LDS bytes of the tuned kernel for a tile depth.
-inline size_t tile_lds_bytes(int levels) {
+__host__ __device__ inline size_t tile_lds_bytes(int levels) {
     const size_t nodes = ((size_t)1 << levels) - 1;
     return nodes * (sizeof(uint64_t) + sizeof(int32_t));
+}
+
+// Start of the per-wave packing areas after the tile (16-byte aligned).
+__host__ __device__ inline size_t inline_area_offset(int levels) { return (tile_lds_bytes(levels) + 15) & ~(size_t)15; }
+
+// Dynamic LDS of the tuned kernel: the tile, plus one packing area per wave
+// when it packs its reads itself.
+inline size_t tuned_lds_bytes(int levels, int block, bool inline_pack) {
+    return inline_pack ? inline_area_offset(levels) + (size_t)(block / 64) * kInlineWaveBytes : tile_lds_bytes(levels);
 }
 
 }  // namespace samatch

@@ -13,6 +13,7 @@
 // is smaller than the query.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <type_traits>
 
@@ -752,6 +753,91 @@ __device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_
     cnt.touch(out + rid, 16);
 }
 
+// tuned_one for a read whose packed words are already in registers.
+template <int W, class Cnt>
+__device__ __forceinline__ void tuned_regs(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa,
+                                           int levels, bool use_table, const uint64_t (&w)[kWMax], int rid, int m,
+                                           int mv, int4 *out, Cnt &cnt) {
+    if (m < 0) {
+        out[rid] = make_int4(0, 0, 0, (int)kHitTooLong);
+        return;
+    }
+    uint64_t q[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) q[k] = w[k];
+    out[rid] = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, cnt);
+    cnt.touch(out + rid, 16);
+}
+
+// Packing inside the search kernel, for reads in input order with CSR
+// offsets: a wave's 64 consecutive reads are one span of the ASCII buffer.
+// The wave converts the span with coalesced, aligned 16-byte loads into a
+// 2-bit code stream and non-base flags in its own LDS area (as the pack
+// kernel does for a workgroup), then each lane takes its read's words out
+// of the stream into registers.  A span longer than the area, and a read
+// outside its wave's span (offsets that go backwards), take the global
+// path.  Saves the pack kernel's writes of the packed words and lengths
+// and the search kernel's reads of them.
+__device__ __forceinline__ void inline_stage(const uint8_t *__restrict__ reads, uintptr_t A0, int nvec,
+                                             uint32_t *codes, uint16_t *badm, int lane) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(A0);
+    for (int c0 = 0; c0 < nvec; c0 += 4 * 64) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + 64 * u + lane;
+            if (c < nvec) v[u] = src[c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + 64 * u + lane;
+            if (c < nvec) {
+                uint32_t bad, code, bits;
+                code = pack4_fast(v[u].x, 0xFFFFFFFFu, bad);
+                bits = bad_nibble(bad);
+                code = (code << 8) | pack4_fast(v[u].y, 0xFFFFFFFFu, bad);
+                bits |= bad_nibble(bad) << 4;
+                code = (code << 8) | pack4_fast(v[u].z, 0xFFFFFFFFu, bad);
+                bits |= bad_nibble(bad) << 8;
+                code = (code << 8) | pack4_fast(v[u].w, 0xFFFFFFFFu, bad);
+                bits |= bad_nibble(bad) << 12;
+                codes[c] = code;
+                badm[c] = (uint16_t)bits;
+            }
+        }
+    }
+}
+
+// Words and first non-base of a read of m bases starting st0 bytes into a
+// staged code stream.
+__device__ __forceinline__ void inline_extract(const uint32_t *codes, const uint16_t *badm, uint32_t st0, int m,
+                                               uint64_t (&w)[kWMax], int &mv) {
+#pragma unroll
+    for (int k = 0; k < kWMax; ++k) {
+        if (32 * k < m) {
+            const uint32_t bpos = st0 + 32u * (uint32_t)k, q = bpos >> 4, r = bpos & 15u;
+            const uint64_t hi = ((uint64_t)codes[q] << 32) | codes[q + 1];
+            uint64_t x = r ? (hi << (2 * r)) | (codes[q + 2] >> (32 - 2 * r)) : hi;
+            const int rem = m - 32 * k;
+            if (rem < 32) x &= ~0ull << (64 - 2 * rem);
+            w[k] = x;
+        }
+    }
+    mv = m;
+    if (m > 0) {
+        const uint32_t q0 = st0 >> 4, q1 = (st0 + (uint32_t)m - 1) >> 4;
+        for (uint32_t q = q0; q <= q1; ++q) {
+            uint32_t bits = badm[q];
+            if (q == q0) bits &= 0xFFFFu << (st0 & 15u);
+            if (q == q1) bits &= (2u << ((st0 + (uint32_t)m - 1) & 15u)) - 1u;
+            if (bits) {
+                mv = (int)(q * 16u + (uint32_t)__builtin_ctz(bits) - st0);
+                break;
+            }
+        }
+    }
+}
+
 // Sum a per-lane 64-bit count over the wave and add it to a global counter.
 __device__ __forceinline__ void wave_add64(unsigned long long *dst, unsigned long long v) {
 #pragma unroll
@@ -785,15 +871,29 @@ __device__ __forceinline__ int64_t workgroup_rank() {
 // LDS once, then its waves take 64-read chunks until the workgroup's blocks
 // are done.  Each chunk runs the instantiation for the longest read it
 // holds.
-template <int BLOCK, bool COUNT>
+//
+// INLINE: the kernel packs its reads itself from the ASCII buffer and CSR
+// offsets (reads in input order; no pack kernel ran), each wave in its own
+// LDS area after the tile.
+template <int BLOCK, bool COUNT, bool INLINE>
 __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group,
                                                              BatchBuffers b, const uint32_t *__restrict__ order,
-                                                             int64_t nreads, int4 *__restrict__ out) {
+                                                             const uint8_t *__restrict__ reads,
+                                                             const int64_t *__restrict__ offs, int64_t nreads,
+                                                             int4 *__restrict__ out) {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned s_next;
     const int nodes = (1 << levels) - 1;
     uint64_t *s_key = smem;
     int32_t *s_sa = reinterpret_cast<int32_t *>(smem + nodes);
+    uint32_t *w_codes = nullptr;
+    uint16_t *w_badm = nullptr;
+    if constexpr (INLINE) {
+        uint8_t *area = reinterpret_cast<uint8_t *>(smem) + inline_area_offset(levels) +
+                        (size_t)(threadIdx.x >> 6) * kInlineWaveBytes;
+        w_codes = reinterpret_cast<uint32_t *>(area);
+        w_badm = reinterpret_cast<uint16_t *>(w_codes + kInlineVec + 4);
+    }
     if (threadIdx.x == 0) s_next = 0u;
     for (int i = threadIdx.x; i < nodes; i += BLOCK) {
         s_key[i] = ix.tile_key[i];
@@ -815,6 +915,69 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         if (chunk >= nchunks) break;  // every later chunk of this workgroup lies further on
         const int64_t j = (chunk << 6) + lane;
         const bool active = j < nreads;
+        if constexpr (INLINE) {
+            const int64_t a = active ? offs[j] : 0, e = active ? offs[j + 1] : 0;
+            if (COUNT && active) cnt.touch(offs + j, 16);
+            const int64_t m64 = e - a;
+            // m = -1: length out of range (the too-long result); long reads are the long kernel's
+            const bool long_read = active && m64 > kShortMax && m64 <= SA_MAX_READ;
+            const int m = (m64 >= 0 && m64 <= kShortMax) ? (int)m64 : -1;
+            if (long_read) b.stats[kLongFlag] = 1ull;
+            const bool short_read = active && !long_read;
+            const int last = (int)min_i(63, (int)(nreads - 1 - (chunk << 6)));
+            const int64_t span0 = __shfl(a, 0, 64), span1 = __shfl(e, last, 64);
+            const uintptr_t A0 = (uintptr_t)(reads + span0) & ~(uintptr_t)15;
+            const uintptr_t A1 = ((uintptr_t)(reads + span1) + 15) & ~(uintptr_t)15;
+            const bool staged = span1 > span0 && A1 - A0 <= (uintptr_t)kInlineVec * 16u;
+            if (staged) {
+                const int nvec = (int)((A1 - A0) >> 4);
+                inline_stage(reads, A0, nvec, w_codes, w_badm, lane);
+                if (COUNT)
+                    for (int c = lane; c < nvec; c += 64) cnt.touch(reinterpret_cast<const uint4 *>(A0) + c, 16);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            uint64_t w[kWMax];
+#pragma unroll
+            for (int t = 0; t < kWMax; ++t) w[t] = 0;
+            int mv = m;
+            if (short_read && m > 0) {
+                if (staged && a >= span0 && e <= span1) {
+                    inline_extract(w_codes, w_badm, (uint32_t)((uintptr_t)(reads + a) - A0), m, w, mv);
+                } else {
+                    uint64_t g[kWMax + 1];
+                    pack_from_global(reads, a, m, g, mv, g[kWMax]);
+#pragma unroll
+                    for (int t = 0; t < kWMax; ++t) w[t] = (32 * t < m) ? g[t] : 0;
+                }
+            }
+            const int wn = max_i(1, (m + 31) >> 5);
+            int wc = 1;
+#pragma unroll
+            for (int t = 2; t <= kWMax; ++t)
+                if (wave_ballot(short_read && wn >= t)) wc = t;
+            if (staged) {  // every lane has its words before the next chunk restages
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (!short_read) continue;
+            if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
+            const int rid = (int)j;
+            switch (wc) {
+                case 1: tuned_regs<1>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                case 2: tuned_regs<2>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                case 3: tuned_regs<3>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                case 4: tuned_regs<4>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                case 5: tuned_regs<5>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                case 6: tuned_regs<6>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                case 7: tuned_regs<7>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                case 8: tuned_regs<8>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                case 9: tuned_regs<9>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                default: tuned_regs<10>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+            }
+            continue;
+        }
         const int rid = active ? (order ? (int)order[j] : (int)j) : 0;
         const ReadLen lm = decode_len(active ? b.qlm[rid] : encode_len(0, 0, 0));
         if (COUNT && active) {
@@ -932,18 +1095,31 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
     }
 }
 
-template <int BLOCK, bool COUNT>
-hipError_t allow_tile_lds() {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&search_tuned_kernel<BLOCK, COUNT>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile_lds_bytes(kMaxTileLevels));
+// Dynamic LDS the inline-packing kernels may take (set by prepare_kernels
+// from the device's limit per workgroup).
+std::atomic<size_t> g_inline_lds{0};
+
+template <int BLOCK, bool COUNT, bool INLINE>
+hipError_t allow_tile_lds(size_t inline_lds) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&search_tuned_kernel<BLOCK, COUNT, INLINE>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               INLINE ? (int)inline_lds : (int)tile_lds_bytes(kMaxTileLevels));
 }
 
 template <int BLOCK, bool COUNT>
 hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int group, int grid, const BatchBuffers &b,
-                              const uint32_t *order, int64_t nreads, int4 *out, hipStream_t s) {
-    const size_t lds = tile_lds_bytes(levels);
-    hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT>), dim3(grid), dim3(BLOCK), lds, s, ix, levels, use_table,
-                       group, b, order, nreads, out);
+                              const uint32_t *order, const uint8_t *reads, const int64_t *offs, int64_t nreads,
+                              int4 *out, hipStream_t s) {
+    if (offs) {
+        const size_t lds = tuned_lds_bytes(levels, BLOCK, true);
+        if (lds > g_inline_lds.load()) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, true>), dim3(grid), dim3(BLOCK), lds, s, ix, levels,
+                           use_table, group, b, order, reads, offs, nreads, out);
+    } else {
+        hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, false>), dim3(grid), dim3(BLOCK),
+                           tile_lds_bytes(levels), s, ix, levels, use_table, group, b, order, reads, offs, nreads,
+                           out);
+    }
     return hipGetLastError();
 }
 
@@ -1056,7 +1232,8 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
                                                          const uint32_t *__restrict__ order,
                                                          const uint32_t *__restrict__ sorted_key, int key_shift,
                                                          uint32_t key_mask, uint32_t long_field, int use_table_i,
-                                                         int64_t nreads, int4 *__restrict__ out) {
+                                                         int lengths_from_offs, int64_t nreads,
+                                                         int4 *__restrict__ out) {
     __shared__ uint64_t slot[64][kLongWords];
     __shared__ int64_t s_first;
     const int lane = threadIdx.x;
@@ -1084,10 +1261,18 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         const int64_t j = first + (c << 6) + lane;
         const bool act = j < nreads;
         const int rid = act ? (order ? (int)order[j] : (int)j) : 0;
-        const ReadLen lm = decode_len(act ? b.qlm[rid] : encode_len(-1, 0, 0));
-        if (COUNT && act) {
-            if (order) cnt.touch(order + j, 4);
-            cnt.touch(b.qlm + rid, 8);
+        ReadLen lm;
+        if (lengths_from_offs) {  // input order, CSR offsets: a read of kShortMax+1 .. SA_MAX_READ bases is long
+            const int64_t m64 = act ? offs[rid + 1] - offs[rid] : -1;
+            const bool lng = m64 > kShortMax && m64 <= SA_MAX_READ;
+            lm = decode_len(encode_len(lng ? (int)m64 : -1, lng ? -1 : 0, 0));
+            if (COUNT && act) cnt.touch(offs + rid, 16);
+        } else {
+            lm = decode_len(act ? b.qlm[rid] : encode_len(-1, 0, 0));
+            if (COUNT && act) {
+                if (order) cnt.touch(order + j, 4);
+                cnt.touch(b.qlm + rid, 8);
+            }
         }
         const bool is_long = act && lm.m >= 0 && lm.mv < 0;
         uint64_t todo = wave_ballot(is_long);
@@ -1209,15 +1394,34 @@ __global__ __launch_bounds__(64) void search_st_kernel(const uint64_t *__restric
     }
 }
 
+__global__ void clear_stats_kernel(BatchBuffers b) {
+    if (threadIdx.x < kStatWords) b.stats[threadIdx.x] = 0ull;
+}
+
 }  // namespace
 
 hipError_t prepare_kernels() {
     hipError_t e;
-    if ((e = allow_tile_lds<256, false>()) != hipSuccess || (e = allow_tile_lds<512, false>()) != hipSuccess ||
-        (e = allow_tile_lds<1024, false>()) != hipSuccess || (e = allow_tile_lds<256, true>()) != hipSuccess)
+    int dev = 0, per_block = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
         return e;
+    // room for the kernels' static LDS
+    const size_t inline_lds = std::min(kLdsBytes, per_block > 256 ? (size_t)per_block - 256 : (size_t)0);
+    if ((e = allow_tile_lds<256, false, false>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<512, false, false>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<1024, false, false>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<256, true, false>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<256, false, true>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<512, false, true>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<1024, false, true>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<256, true, true>(inline_lds)) != hipSuccess)
+        return e;
+    g_inline_lds.store(inline_lds);
     return hipSuccess;
 }
+
+size_t inline_lds_limit() { return g_inline_lds.load(); }
 
 hipError_t launch_search_st(const uint64_t *text, const int32_t *sa, int32_t n, const StNode *nodes, int32_t root,
                             const uint8_t *reads, const int64_t *offs, int64_t nreads, void *out, int grid,
@@ -1255,16 +1459,21 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi
 }
 
 hipError_t launch_search_tuned(const DevIndex &ix, int levels, int use_table, int block, int grid, int group,
-                               const BatchBuffers &b, const uint32_t *order, int64_t nreads, void *out, bool count,
-                               hipStream_t s) {
+                               const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
+                               const int64_t *offs, int64_t nreads, void *out, bool count, hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
-    if (group < 1) return hipErrorInvalidValue;
+    if (group < 1 || (offs && order)) return hipErrorInvalidValue;
     if (count)  // counts do not depend on the workgroup shape or the work split
-        return launch_tuned_block<256, true>(ix, levels, use_table, group, grid * (block / 256), b, order, nreads, o, s);
+        return launch_tuned_block<256, true>(ix, levels, use_table, group, grid * (block / 256), b, order, reads, offs,
+                                             nreads, o, s);
     switch (block) {
-        case 256: return launch_tuned_block<256, false>(ix, levels, use_table, group, grid, b, order, nreads, o, s);
-        case 512: return launch_tuned_block<512, false>(ix, levels, use_table, group, grid, b, order, nreads, o, s);
-        case 1024: return launch_tuned_block<1024, false>(ix, levels, use_table, group, grid, b, order, nreads, o, s);
+        case 256:
+            return launch_tuned_block<256, false>(ix, levels, use_table, group, grid, b, order, reads, offs, nreads, o, s);
+        case 512:
+            return launch_tuned_block<512, false>(ix, levels, use_table, group, grid, b, order, reads, offs, nreads, o, s);
+        case 1024:
+            return launch_tuned_block<1024, false>(ix, levels, use_table, group, grid, b, order, reads, offs, nreads, o,
+                                                   s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1276,17 +1485,25 @@ hipError_t launch_build_prefix_table(const DevIndex &ix, int k, uint32_t *tab, h
     return hipGetLastError();
 }
 
-hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b, const uint32_t *order, const uint32_t *sorted_key,
-                              int key_shift, uint32_t key_mask, uint32_t long_field, int use_table, int grid,
-                              int64_t nreads, void *out, bool count, hipStream_t s) {
+hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b,
+                              const uint32_t *order, const uint32_t *sorted_key, int key_shift, uint32_t key_mask,
+                              uint32_t long_field, int use_table, bool lengths_from_offs, int grid, int64_t nreads,
+                              void *out, bool count, hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
     const dim3 g((unsigned)(grid > 0 ? grid : 1));
+    if (lengths_from_offs && order) return hipErrorInvalidValue;
+    const int lfo = lengths_from_offs ? 1 : 0;
     if (count)
         hipLaunchKernelGGL(search_long_kernel<true>, g, dim3(64), 0, s, ix, reads, offs, b, order, sorted_key,
-                           key_shift, key_mask, long_field, use_table, nreads, o);
+                           key_shift, key_mask, long_field, use_table, lfo, nreads, o);
     else
         hipLaunchKernelGGL(search_long_kernel<false>, g, dim3(64), 0, s, ix, reads, offs, b, order, sorted_key,
-                           key_shift, key_mask, long_field, use_table, nreads, o);
+                           key_shift, key_mask, long_field, use_table, lfo, nreads, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_stats(const BatchBuffers &b, hipStream_t s) {
+    hipLaunchKernelGGL(clear_stats_kernel, dim3(1), dim3(64), 0, s, b);
     return hipGetLastError();
 }
 

@@ -52,6 +52,7 @@ std::string cfg_json(const sa_match_cfg &c) {
     std::ostringstream o;
     o << "\"tile_levels\":" << c.tile_levels << ",\"block\":" << c.block << ",\"blocks_per_cu\":" << c.blocks_per_cu
       << ",\"group\":" << c.group << ",\"prefix_table\":" << c.prefix_table << ",\"sort\":" << c.sort
+      << ",\"inline_pack\":" << c.inline_pack
       << ",\"nbuckets\":" << c.nbuckets << ",\"bucket_edge\":[";
     for (int i = 0; i < c.nbuckets; i++) o << (i ? "," : "") << c.bucket_edge[i];
     o << "]";
@@ -81,6 +82,7 @@ bool parse_cached(const std::string &path, const std::string &key, sa_match_cfg 
         c.group = json_int(line, "group", 4);
         c.prefix_table = json_int(line, "prefix_table", 0);
         c.sort = json_int(line, "sort", 1);
+        c.inline_pack = json_int(line, "inline_pack", 1);
         c.nbuckets = std::max(1, std::min(8, json_int(line, "nbuckets", 1)));
         const size_t p = line.find("\"bucket_edge\":[");
         if (p != std::string::npos) {
@@ -177,11 +179,15 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
         }
         ms = best_rep;
         if (std::getenv("SAMATCH_TUNE_LOG"))
-            std::fprintf(stderr, "tune: levels=%d block=%d per_cu=%d group=%d table=%d sort=%d buckets=%d -> %.4f ms\n",
-                         c.tile_levels, c.block, c.blocks_per_cu, c.group, c.prefix_table, c.sort, c.nbuckets, ms);
+            std::fprintf(stderr,
+                         "tune: levels=%d block=%d per_cu=%d group=%d table=%d sort=%d inline=%d buckets=%d -> %.4f ms\n",
+                         c.tile_levels, c.block, c.blocks_per_cu, c.group, c.prefix_table, c.sort, c.inline_pack,
+                         c.nbuckets, ms);
         return SA_OK;
     };
-    // stage 1: tile depth x workgroup shape with one bucket
+    // stage 1: tile depth x workgroup shape with one bucket, the search
+    // start, sort and packing of the built-in defaults
+    const int base_sort = d->view.ptab_k > 0 ? 0 : 1;
     std::vector<int> levels;
     for (int t = std::min(13, d->tile_levels); t >= std::max(1, std::min(9, d->tile_levels)); t--) levels.push_back(t);
     for (int lv : levels) {
@@ -195,9 +201,10 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
                 c.blocks_per_cu = per_cu;
                 c.nbuckets = 1;
                 c.bucket_edge[0] = SA_MAX_READ;
-                c.sort = 1;
+                c.sort = base_sort;
+                c.inline_pack = 1;
                 c.group = 4;
-                c.prefix_table = d->defaults.prefix_table;
+                c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
                 double ms = 0;
                 rc = time_cfg(c, ms);
                 if (rc == SA_EINVAL) continue;
@@ -207,14 +214,16 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
         }
     }
     // stage 1b: block size of the work split with the best shape, the
-    // search start (prefix table or LDS tile only), and the sort width
+    // search start (prefix table or LDS tile only), the sort width, and
+    // packing in the search kernel or in a pass of its own
     static const int kGroups[4] = {1, 2, 8, 16};
     static const int kSortBits[4] = {0, 8, 16, 24};
-    for (int variant = 0; variant < 9; variant++) {
+    for (int variant = 0; variant < 10; variant++) {
         sa_match_cfg c = top;
         if (variant < 4) c.group = kGroups[variant];
         else if (variant == 4 && d->view.ptab_k > 0) c.prefix_table = !top.prefix_table;
-        else if (variant >= 5) c.sort = kSortBits[variant - 5];
+        else if (variant >= 5 && variant < 9) c.sort = kSortBits[variant - 5];
+        else if (variant == 9 && top.sort == 0) c.inline_pack = !top.inline_pack;
         else continue;
         double ms = 0;
         rc = time_cfg(c, ms);

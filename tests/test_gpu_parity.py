@@ -57,6 +57,9 @@ CONFIGS = [
     ("tuned-sort-adaptive", dict(sort=1)),
     ("tuned-sort8", dict(sort=8, group=1)),
     ("tuned-sort24-buckets", dict(sort=24, nbuckets=2, bucket_edge=[96, 1024])),
+    ("tuned-pack-pass", dict(sort=0, inline_pack=0)),
+    ("tuned-inline-t12-b1024", dict(tile_levels=12, block=1024, blocks_per_cu=1, sort=0, inline_pack=1)),
+    ("tuned-inline-no-table", dict(prefix_table=0, sort=0, inline_pack=1, group=1)),
 ]
 
 
@@ -248,3 +251,54 @@ def test_prefix_table_edges(device, kind):
             reads.append(r)
         reads += ["".join(rng.choice("ACGT") for _ in range(rng.randint(5, 40))) for _ in range(100)]
         check_text(text, reads, device, f"{kind}/{n}")
+
+
+def test_inline_pack_spans(device):
+    """The search kernel's own packing against the pack pass and the oracle:
+    waves whose 64 reads span more than its 12 KB packing area (300-base
+    reads, long reads among short ones), offsets that go backwards (a
+    negative length is too long; the reads after it lie before the wave's
+    span), and the whole batch moved 5 bytes into its buffer."""
+    say("case: inline pack spans")
+    ref = gen.make_reference("c2", n=400_000)
+    text = ref.ascii().tobytes().decode()
+    rng = np.random.default_rng(17)
+
+    def sample(m):
+        p = int(rng.integers(0, ref.n - m))
+        r = text[p:p + m]
+        u = rng.random()
+        if u < 0.3:
+            j = int(rng.integers(0, m))
+            r = r[:j] + "ACGT"[(ref.codes[p + j] + 1) % 4] + r[j + 1:]
+        elif u < 0.4:
+            j = int(rng.integers(0, m))
+            r = r[:j] + "n" + r[j + 1:]
+        return r
+
+    reads = [sample(300) for _ in range(200)]                                  # 19 KB per wave
+    reads += [sample(900) if k % 10 == 3 else sample(100) for k in range(300)]  # long reads among short ones
+    reads += [sample(int(rng.integers(1, 200))) for _ in range(300)]
+    d = S.sa_upload(S.sa_build(text), 0)
+    sa = oracle.sa_build(text)
+    data, offs = oracle.pack_reads(reads)
+    want = oracle.match(text, sa, data, offs)
+    variants = [S.cfg(d, sort=0, inline_pack=v) for v in (1, 0)]
+    for c in variants:
+        assert_same(run_dev(d, data[:-1], offs, device, c), want, f"inline={c.inline_pack}")
+        # the same reads 5 bytes into the buffer
+        shifted = np.concatenate([np.frombuffer(b"NNNNN", np.uint8), data[:-1]])
+        assert_same(run_dev(d, shifted, offs + 5, device, c), want, f"shifted inline={c.inline_pack}")
+    # offsets that go backwards: read 70 runs from offs[70] back to an
+    # earlier byte (too long); reads 71.. start before the wave's first read
+    o2 = offs.copy()
+    o2[71:] -= int(offs[71] - offs[10])
+    starts, ends = o2[:-1], o2[1:]
+    ok = ends >= starts
+    assert not ok[70] and ok[:70].all() and ok[71:].all()
+    buf = data[:-1]
+    w_ok = oracle.match(text, sa, *oracle.pack_reads([bytes(buf[a:b]).decode() for a, b in zip(starts[ok], ends[ok])]))
+    for c in variants:
+        got = run_dev(d, buf, o2, device, c)
+        assert tuple(got[70]) == (0, 0, 0, S.SA_HIT_TOOLONG), f"inline={c.inline_pack}"
+        assert_same(got[ok], w_ok, f"backwards inline={c.inline_pack}")
