@@ -777,35 +777,112 @@ __device__ __forceinline__ void tuned_regs(const DevIndex &ix, const uint64_t *s
 // of the stream into registers.  A span longer than the area, and a read
 // outside its wave's span (offsets that go backwards), take the global
 // path.  Saves the pack kernel's writes of the packed words and lengths
-// and the search kernel's reads of them.
-__device__ __forceinline__ void inline_stage(const uint8_t *__restrict__ reads, uintptr_t A0, int nvec,
-                                             uint32_t *codes, uint16_t *badm, int lane) {
-    const uint4 *src = reinterpret_cast<const uint4 *>(A0);
-    for (int c0 = 0; c0 < nvec; c0 += 4 * 64) {
-        uint4 v[4];
+// and the search kernel's reads of them.  The loads are pipelined: a wave
+// loads the offsets of the chunk after next and the ASCII of the next
+// chunk (into registers) before it searches the current one.
+// The wave-uniform span of a chunk's reads: the aligned 16-byte pieces
+// [A0, A0 + 16 nvec) that hold bytes [s0, s1) of the read buffer; staged
+// when it fits the wave's packing area.
+struct Span {
+    uintptr_t A0;
+    int64_t s0, s1;
+    int nvec;
+    bool staged;
+};
+
+// Offsets of the reads of chunk (none when chunk < 0): loads issued here,
+// used later.
+__device__ __forceinline__ void chunk_offsets(const int64_t *__restrict__ offs, int64_t chunk, int64_t nreads,
+                                              int lane, int64_t &a, int64_t &e) {
+    const int64_t j = (chunk << 6) + lane;
+    const bool act = chunk >= 0 && j < nreads;
+    a = act ? offs[j] : 0;
+    e = act ? offs[j + 1] : 0;
+}
+
+__device__ __forceinline__ Span chunk_span(const uint8_t *__restrict__ reads, int64_t chunk, int64_t nreads,
+                                           int64_t a, int64_t e) {
+    Span sp{0, 0, 0, 0, false};
+    if (chunk < 0) return sp;
+    const int last = (int)min_i(63, (int)(nreads - 1 - (chunk << 6)));
+    sp.s0 = __shfl(a, 0, 64);
+    sp.s1 = __shfl(e, last, 64);
+    sp.A0 = (uintptr_t)(reads + sp.s0) & ~(uintptr_t)15;
+    const uintptr_t A1 = ((uintptr_t)(reads + sp.s1) + 15) & ~(uintptr_t)15;
+    sp.staged = sp.s1 > sp.s0 && A1 - sp.A0 <= (uintptr_t)kInlineVec * 16u;
+    sp.nvec = sp.staged ? (int)((A1 - sp.A0) >> 4) : 0;
+    return sp;
+}
+
+// Pieces of a staged span a wave holds in registers between chunks (lane l
+// holds pieces l, l + 64, ...); the rest of a longer span is loaded when it
+// is converted.
+#ifndef SAMATCH_INLINE_AHEAD
+#define SAMATCH_INLINE_AHEAD 6
+#endif
+constexpr int kInlineAhead = SAMATCH_INLINE_AHEAD;
+
+template <class Cnt>
+__device__ __forceinline__ void span_prefetch(const Span &sp, int lane, uint4 (&v)[kInlineAhead], Cnt &cnt) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(sp.A0);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = c0 + 64 * u + lane;
-            if (c < nvec) v[u] = src[c];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = c0 + 64 * u + lane;
-            if (c < nvec) {
-                uint32_t bad, code, bits;
-                code = pack4_fast(v[u].x, 0xFFFFFFFFu, bad);
-                bits = bad_nibble(bad);
-                code = (code << 8) | pack4_fast(v[u].y, 0xFFFFFFFFu, bad);
-                bits |= bad_nibble(bad) << 4;
-                code = (code << 8) | pack4_fast(v[u].z, 0xFFFFFFFFu, bad);
-                bits |= bad_nibble(bad) << 8;
-                code = (code << 8) | pack4_fast(v[u].w, 0xFFFFFFFFu, bad);
-                bits |= bad_nibble(bad) << 12;
-                codes[c] = code;
-                badm[c] = (uint16_t)bits;
-            }
+    for (int u = 0; u < kInlineAhead; ++u) {
+        const int c = 64 * u + lane;
+        if (c < sp.nvec) {
+            v[u] = src[c];
+            cnt.touch(src + c, 16);
         }
     }
+}
+
+__device__ __forceinline__ void convert_piece(const uint4 &v, uint32_t *codes, uint16_t *badm, int c) {
+    uint32_t bad, code, bits;
+    code = pack4_fast(v.x, 0xFFFFFFFFu, bad);
+    bits = bad_nibble(bad);
+    code = (code << 8) | pack4_fast(v.y, 0xFFFFFFFFu, bad);
+    bits |= bad_nibble(bad) << 4;
+    code = (code << 8) | pack4_fast(v.z, 0xFFFFFFFFu, bad);
+    bits |= bad_nibble(bad) << 8;
+    code = (code << 8) | pack4_fast(v.w, 0xFFFFFFFFu, bad);
+    bits |= bad_nibble(bad) << 12;
+    codes[c] = code;
+    badm[c] = (uint16_t)bits;
+}
+
+// The staged span as codes and flags in the wave's area: the prefetched
+// pieces, then the rest (four loads in flight per lane).
+template <class Cnt>
+__device__ __forceinline__ void span_convert(const Span &sp, const uint4 (&v)[kInlineAhead], uint32_t *codes,
+                                             uint16_t *badm, int lane, Cnt &cnt) {
+#pragma unroll
+    for (int u = 0; u < kInlineAhead; ++u) {
+        const int c = 64 * u + lane;
+        if (c < sp.nvec) convert_piece(v[u], codes, badm, c);
+    }
+    const uint4 *src = reinterpret_cast<const uint4 *>(sp.A0);
+    for (int c0 = 64 * kInlineAhead; c0 < sp.nvec; c0 += 4 * 64) {
+        uint4 r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + 64 * u + lane;
+            if (c < sp.nvec) {
+                r[u] = src[c];
+                cnt.touch(src + c, 16);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + 64 * u + lane;
+            if (c < sp.nvec) convert_piece(r[u], codes, badm, c);
+        }
+    }
+}
+
+// LDS written by this wave's lanes is visible to its other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Words and first non-base of a read of m bases starting st0 bytes into a
@@ -907,77 +984,93 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
     const int lane = threadIdx.x & 63;
     const int64_t nchunks = (nreads + 63) >> 6;
     const int64_t G = gridDim.x, rank = workgroup_rank();
-    for (;;) {
+    // the next chunk of this wave (-1 when the workgroup's blocks are done;
+    // every later one lies further on)
+    auto take = [&]() -> int64_t {
         unsigned c = 0;
         if (lane == 0) c = atomicAdd(&s_next, 1u);
         c = __shfl(c, 0, 64);
         const int64_t chunk = ((int64_t)(c / group) * G + rank) * group + (c % group);
-        if (chunk >= nchunks) break;  // every later chunk of this workgroup lies further on
-        const int64_t j = (chunk << 6) + lane;
-        const bool active = j < nreads;
-        if constexpr (INLINE) {
-            const int64_t a = active ? offs[j] : 0, e = active ? offs[j + 1] : 0;
+        return chunk < nchunks ? chunk : -1;
+    };
+    if constexpr (INLINE) {
+        int64_t c0 = take(), a0, e0;
+        chunk_offsets(offs, c0, nreads, lane, a0, e0);
+        Span sp0 = chunk_span(reads, c0, nreads, a0, e0);
+        uint4 v[kInlineAhead];
+        span_prefetch(sp0, lane, v, cnt);
+        int64_t c1 = c0 >= 0 ? take() : -1, a1, e1;
+        chunk_offsets(offs, c1, nreads, lane, a1, e1);
+        while (c0 >= 0) {
+            const int64_t j = (c0 << 6) + lane;
+            const bool active = j < nreads;
             if (COUNT && active) cnt.touch(offs + j, 16);
-            const int64_t m64 = e - a;
+            const int64_t m64 = e0 - a0;
             // m = -1: length out of range (the too-long result); long reads are the long kernel's
             const bool long_read = active && m64 > kShortMax && m64 <= SA_MAX_READ;
             const int m = (m64 >= 0 && m64 <= kShortMax) ? (int)m64 : -1;
             if (long_read) b.stats[kLongFlag] = 1ull;
             const bool short_read = active && !long_read;
-            const int last = (int)min_i(63, (int)(nreads - 1 - (chunk << 6)));
-            const int64_t span0 = __shfl(a, 0, 64), span1 = __shfl(e, last, 64);
-            const uintptr_t A0 = (uintptr_t)(reads + span0) & ~(uintptr_t)15;
-            const uintptr_t A1 = ((uintptr_t)(reads + span1) + 15) & ~(uintptr_t)15;
-            const bool staged = span1 > span0 && A1 - A0 <= (uintptr_t)kInlineVec * 16u;
-            if (staged) {
-                const int nvec = (int)((A1 - A0) >> 4);
-                inline_stage(reads, A0, nvec, w_codes, w_badm, lane);
-                if (COUNT)
-                    for (int c = lane; c < nvec; c += 64) cnt.touch(reinterpret_cast<const uint4 *>(A0) + c, 16);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (sp0.staged) {
+                span_convert(sp0, v, w_codes, w_badm, lane, cnt);
+                wave_lds_sync();
             }
             uint64_t w[kWMax];
 #pragma unroll
             for (int t = 0; t < kWMax; ++t) w[t] = 0;
             int mv = m;
             if (short_read && m > 0) {
-                if (staged && a >= span0 && e <= span1) {
-                    inline_extract(w_codes, w_badm, (uint32_t)((uintptr_t)(reads + a) - A0), m, w, mv);
+                if (sp0.staged && a0 >= sp0.s0 && e0 <= sp0.s1) {
+                    inline_extract(w_codes, w_badm, (uint32_t)((uintptr_t)(reads + a0) - sp0.A0), m, w, mv);
                 } else {
                     uint64_t g[kWMax + 1];
-                    pack_from_global(reads, a, m, g, mv, g[kWMax]);
+                    pack_from_global(reads, a0, m, g, mv, g[kWMax]);
 #pragma unroll
                     for (int t = 0; t < kWMax; ++t) w[t] = (32 * t < m) ? g[t] : 0;
                 }
             }
+            if (sp0.staged) wave_lds_sync();  // every lane has its words before the area is reused
+            // loads for the chunks ahead, in flight during this chunk's searches
+            const Span sp1 = chunk_span(reads, c1, nreads, a1, e1);
+            span_prefetch(sp1, lane, v, cnt);
+            const int64_t c2 = c1 >= 0 ? take() : -1;
+            int64_t a2, e2;
+            chunk_offsets(offs, c2, nreads, lane, a2, e2);
             const int wn = max_i(1, (m + 31) >> 5);
             int wc = 1;
 #pragma unroll
             for (int t = 2; t <= kWMax; ++t)
                 if (wave_ballot(short_read && wn >= t)) wc = t;
-            if (staged) {  // every lane has its words before the next chunk restages
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
+            if (short_read) {
+                if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
+                const int rid = (int)j;
+                switch (wc) {
+                    case 1: tuned_regs<1>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    case 2: tuned_regs<2>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    case 3: tuned_regs<3>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    case 4: tuned_regs<4>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    case 5: tuned_regs<5>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    case 6: tuned_regs<6>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    case 7: tuned_regs<7>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    case 8: tuned_regs<8>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    case 9: tuned_regs<9>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    default: tuned_regs<10>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                }
             }
-            if (!short_read) continue;
-            if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
-            const int rid = (int)j;
-            switch (wc) {
-                case 1: tuned_regs<1>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                case 2: tuned_regs<2>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                case 3: tuned_regs<3>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                case 4: tuned_regs<4>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                case 5: tuned_regs<5>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                case 6: tuned_regs<6>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                case 7: tuned_regs<7>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                case 8: tuned_regs<8>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                case 9: tuned_regs<9>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                default: tuned_regs<10>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-            }
-            continue;
+            c0 = c1;
+            a0 = a1;
+            e0 = e1;
+            sp0 = sp1;
+            c1 = c2;
+            a1 = a2;
+            e1 = e2;
         }
+    }
+    while (!INLINE) {  // reads packed by the pack kernel
+        const int64_t chunk = take();
+        if (chunk < 0) break;
+        const int64_t j = (chunk << 6) + lane;
+        const bool active = j < nreads;
         const int rid = active ? (order ? (int)order[j] : (int)j) : 0;
         const ReadLen lm = decode_len(active ? b.qlm[rid] : encode_len(0, 0, 0));
         if (COUNT && active) {
