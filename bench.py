@@ -182,11 +182,21 @@ def main():
         return S.sa_probe_counts(d, stream)
 
     lens = reads.lengths()
-    read_bytes = int(((lens + 3) // 4).sum())  # packed query, 2 bits per base
 
-    def alg_bytes(cnt):
-        # per read: packed query + 16-byte result; per global probe: a 4-byte
-        # SA entry plus the 8-byte words it compares (row keys and text words)
+    def packs_inline(c):
+        # the search kernel packs the reads itself (no pack pass) when the
+        # batch is in input order and its tile plus one 4640-byte packing
+        # area per wave fit in LDS (160 KB less room for static variables)
+        tile = ((1 << c.tile_levels) - 1) * 12
+        return (c.kernel == S.SA_KERNEL_TUNED and c.inline_pack == 1 and c.sort == 0 and
+                ((tile + 15) // 16 * 16 + (c.block // 64) * 4640) <= 160 * 1024 - 256)
+
+    def alg_bytes(cnt, c):
+        # per read: its input (the ASCII bytes and an 8-byte offset when the
+        # search kernel packs it, else the 2-bit packed words) + the 16-byte
+        # result; per global probe: a 4-byte SA entry plus the 8-byte words
+        # it compares (row keys and text words)
+        read_bytes = int(lens.sum()) + 8 * N if packs_inline(c) else int(((lens + 3) // 4).sum())
         return read_bytes + 16 * N + 4 * cnt["global_probes"] + 8 * (cnt["text_words"] + cnt["key_words"])
 
     # ---- tuned path
@@ -216,8 +226,8 @@ def main():
             "plain and tuned kernels disagree"
         plain = {"reads_per_s": N * pk / pel, "ms_per_step": 1000.0 * pel / pk, "search_ms": pst["search"],
                  "global_probes_per_read": pcnt["global_probes"] / N,
-                 "alg_bytes_per_read": alg_bytes(pcnt) / N,
-                 "search_GBps_alg": alg_bytes(pcnt) / (pst["search"] * 1e-3) / 1e9}
+                 "alg_bytes_per_read": alg_bytes(pcnt, pc) / N,
+                 "search_GBps_alg": alg_bytes(pcnt, pc) / (pst["search"] * 1e-3) / 1e9}
         log(f"plain: {plain}")
 
     # ---- one call per distinct read length (the unbatched form)
@@ -274,7 +284,7 @@ def main():
     log(f"locate: {locate}")
     del loc_offs, loc_pos
 
-    B = alg_bytes(cnt)
+    B = alg_bytes(cnt, cfg)
     achieved = B / (stages["search"] * 1e-3) / 1e9
     # HBM traffic per launch from the committed rocprofv3 counters, only when
     # they were taken on these kernel sources and this workload
@@ -287,7 +297,8 @@ def main():
     touched = cnt["touched_bytes"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "search_tuned_kernel", "alg_bytes_per_launch": B, "alg_bytes_per_read": round(B / N, 2),
+                "kernel": "search_tuned_kernel", "packs_reads": packs_inline(cfg),
+                "alg_bytes_per_launch": B, "alg_bytes_per_read": round(B / N, 2),
                 "launch_ms": round(stages["search"], 4), "kernel_src": kernel_source_hash(),
                 # bytes touched: 64-byte segments addressed per wave access, counted by the instrumented kernel
                 "touched_bytes_per_launch": touched, "touched_GBps": round(touched / (stages["search"] * 1e-3) / 1e9, 2),
