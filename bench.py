@@ -295,6 +295,14 @@ def main():
         if prof.get("kernel_src") == kernel_source_hash() and prof.get("workload") == args.config:
             traffic = round(prof["traffic_bytes"])
     touched = cnt["touched_bytes"]
+    # the search's scattered accesses (64-byte segments touched, less the
+    # coalesced input and results) against the rate this device serves
+    # random 16-byte loads from a table the size of the row records
+    coalesced = B - (4 * cnt["global_probes"] + 8 * (cnt["text_words"] + cnt["key_words"]))
+    scattered = max(0, touched - coalesced) / 64
+    ceiling = S.sa_random_read_rate(0, max(8, min(28, int(np.ceil(np.log2(max(2, len(d))))))))
+    scattered_rate = scattered / (stages["search"] * 1e-3)
+    log(f"random 16-byte loads: {ceiling / 1e9:.1f} G/s; search scattered segments {scattered_rate / 1e9:.1f} G/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "search_tuned_kernel", "packs_reads": packs_inline(cfg),
@@ -302,7 +310,12 @@ def main():
                 "launch_ms": round(stages["search"], 4), "kernel_src": kernel_source_hash(),
                 # bytes touched: 64-byte segments addressed per wave access, counted by the instrumented kernel
                 "touched_bytes_per_launch": touched, "touched_GBps": round(touched / (stages["search"] * 1e-3) / 1e9, 2),
-                "touched_frac": round(touched / (stages["search"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
+                "touched_frac": round(touched / (stages["search"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                # measured random-access ceiling (G 16-byte loads/s) and the
+                # search's scattered 64-byte segments per second against it
+                "random_ceiling_G_per_s": round(ceiling / 1e9, 2),
+                "scattered_G_per_s": round(scattered_rate / 1e9, 2),
+                "random_frac": round(scattered_rate / ceiling, 4)}
 
     # ---- CPU baseline: the oracle's search phase on the host cores, on a
     # bounded sample of the batch (its first reads)

@@ -205,6 +205,16 @@ int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]);
  * Waits for that batch. */
 int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[8]);
 
+/* Measurement helper, not part of the matching path: the rate (loads per
+ * second, into *loads_per_s) at which the device serves random 16-byte
+ * loads from a table of 2^log2_entries 16-byte entries (8 <= log2_entries
+ * <= 28), the access pattern of the search kernels' probes.  Every lane
+ * follows two independent chains of 16 dependent loads at hashed positions,
+ * 16 waves per compute unit; the best of five timed launches.  Allocates and
+ * frees the table; runs on the null stream and waits for it.  SA_EINVAL for a
+ * size out of range, SA_EDEVICE / SA_ENOMEM on device failures. */
+int sa_random_read_rate(int device, int log2_entries, double *loads_per_s);
+
 /* Autotuner: time candidate configurations (tile depth, workgroups per CU,
  * block size, bucket edges) on the given device batch, keep the fastest as
  * the index's default, and return it in best (nullable).  best_ms receives

@@ -24,6 +24,7 @@ SOURCES = [
     "locate.hip",
     "tune.hip",
     "server.hip",
+    "probe.hip",
 ]
 
 ARCH = os.environ.get("SAMATCH_ARCH", "gfx950")

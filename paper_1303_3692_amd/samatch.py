@@ -25,7 +25,7 @@ EXPORTS = [
     "sa_build", "sa_build_from_sa", "sa_index_length", "sa_index_copy_sa", "sa_save", "sa_load", "sa_free",
     "sa_upload", "sa_dfree", "sa_dindex_length", "sa_build_device", "sa_download", "sa_dindex_build_info",
     "sa_default_cfg", "match_batch", "match_batch_dev",
-    "sa_stage_times", "sa_probe_counts", "sa_tune",
+    "sa_stage_times", "sa_probe_counts", "sa_tune", "sa_random_read_rate",
     "sa_locate_dev", "sa_locate",
     "st_build", "st_free", "st_node_count", "st_root", "st_copy_nodes", "st_index_bytes", "st_upload", "st_dfree",
     "st_match_batch_dev",
@@ -98,6 +98,7 @@ def lib():
             "match_batch_dev": ([p, p, p, i64, p, p, ctypes.POINTER(MatchCfg)], i32),
             "sa_stage_times": ([p, p, ctypes.POINTER(ctypes.c_double)], i32),
             "sa_probe_counts": ([p, p, ctypes.POINTER(ctypes.c_int64)], i32),
+            "sa_random_read_rate": ([i32, i32, ctypes.POINTER(ctypes.c_double)], i32),
             "sa_tune": ([p, p, p, i64, p, ctypes.c_char_p, ctypes.POINTER(MatchCfg), ctypes.POINTER(ctypes.c_double)], i32),
             "sa_locate_dev": ([p, p, i64, i32, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_int64)], i32),
             "sa_locate": ([p, p, i64, i32, i32, p, p, i64, ctypes.POINTER(ctypes.c_int64)], i32),
@@ -317,6 +318,15 @@ def sa_probe_counts(d: DIndex, stream=None) -> dict:
     _check(lib().sa_probe_counts(d.ptr, _stream_handle(stream), c), "sa_probe_counts")
     return {"global_probes": c[0], "text_words": c[1], "tile_probes": c[2], "reads": c[3], "query_words": c[4],
             "key_words": c[5], "table_lookups": c[6], "touched_bytes": c[7]}
+
+
+def sa_random_read_rate(device: int = 0, log2_entries: int = 24) -> float:
+    """Random 16-byte loads per second the device serves from a table of
+    2^log2_entries 16-byte entries (a measurement helper, not part of the
+    matching path)."""
+    r = ctypes.c_double()
+    _check(lib().sa_random_read_rate(device, log2_entries, ctypes.byref(r)), "sa_random_read_rate")
+    return r.value
 
 
 class StIndex:
