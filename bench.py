@@ -59,6 +59,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the built-in launch defaults")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end timing from host memory")
     ap.add_argument("--no-graph", action="store_true", help="launch the kernels directly instead of replaying a graph")
     ap.add_argument("--per-length", action="store_true",
                     help="also time one batch call per distinct read length (default for c3)")
@@ -317,6 +318,19 @@ def main():
                 "scattered_G_per_s": round(scattered_rate / 1e9, 2),
                 "random_frac": round(scattered_rate / ceiling, 4)}
 
+    # ---- end to end from host memory (match_batch: reads copied in, results
+    # copied out, over PCIe; not the headline, which starts from HBM)
+    e2e = None
+    if not args.no_e2e:
+        S.match_batch(d, reads.data, reads.offs)
+        t = time.perf_counter()
+        for _ in range(3):
+            S.match_batch(d, reads.data, reads.offs)
+        t_e2e = (time.perf_counter() - t) / 3
+        e2e = {"ms_per_batch": round(1000 * t_e2e, 3), "reads_per_s": round(N / t_e2e, 1),
+               "input_bytes": int(len(reads.data) + 8 * (N + 1)), "output_bytes": 16 * N}
+        log(f"end to end from host memory: {e2e}")
+
     # ---- CPU baseline: the oracle's search phase on the host cores, on a
     # bounded sample of the batch (its first reads)
     cpu = None
@@ -334,10 +348,17 @@ def main():
         t_match = time.perf_counter() - t
         got = out[:ns]
         same = bool((want[:, :3] == got[:, :3]).all() and (want[:, 3] == (got[:, 3] & 1)).all())
+        # and on one core, over a smaller sample
+        n1 = min(ns, CPU_SAMPLE_READS // 16)
+        t = time.perf_counter()
+        want1 = oracle.match(text, osa, reads.data[:reads.offs[n1]], reads.offs[:n1 + 1], nthreads=1)
+        t_one = time.perf_counter() - t
+        same = same and bool((want1 == want[:n1]).all())
         cpu = {"value": round(ns / t_match, 1), "unit": "reads/s", "cores": threads, "kind": "oracle",
                "sample": f"the first {ns:,} of {N:,} reads; oracle search phase only, over the device-built suffix "
                          f"array after the oracle checked it sorted ({t_chk:.1f}s, untimed)",
-               "matches_gpu": same}
+               "matches_gpu": same,
+               "one_core": {"value": round(n1 / t_one, 1), "unit": "reads/s", "sample": f"the first {n1:,} reads"}}
         log(f"cpu oracle: {cpu}")
 
     value = N * args.steps / elapsed
@@ -362,6 +383,7 @@ def main():
         "per_length": per_length,
         "speedup_vs_per_length": round(value / per_length["reads_per_s"], 3) if per_length else None,
         "locate": locate,
+        "end_to_end_from_host": e2e,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

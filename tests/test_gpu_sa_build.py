@@ -124,3 +124,13 @@ def test_full_c4_reference_is_sorted():
     d, sa = device_sa(t)
     print("  built:", d.build_info(), flush=True)
     assert oracle.sa_check(t, sa) == 0
+
+
+def test_random_read_rate_probe():
+    """The measurement helper bench.py reports beside the search: a plausible
+    rate for a small and a large table, the small one not slower."""
+    print("case: random read rate", flush=True)
+    small = S.sa_random_read_rate(0, 16)
+    large = S.sa_random_read_rate(0, 24)
+    assert 1e9 < large < 1e12 and 1e9 < small < 1e12
+    assert small > 0.8 * large

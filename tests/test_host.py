@@ -128,3 +128,13 @@ def test_null_handles_are_rejected():
     L.sa_free(None)
     L.sa_dfree(None)
     assert L.sa_server_destroy(None) == S.SA_OK
+
+
+def test_random_read_rate_rejects_bad_arguments():
+    """Checked before any device call: a table size out of range, no output."""
+    L = S.lib()
+    r = ctypes.c_double(-1.0)
+    assert L.sa_random_read_rate(0, 7, ctypes.byref(r)) == S.SA_EINVAL
+    assert L.sa_random_read_rate(0, 29, ctypes.byref(r)) == S.SA_EINVAL
+    assert L.sa_random_read_rate(0, 20, None) == S.SA_EINVAL
+    assert r.value == -1.0
