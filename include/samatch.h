@@ -177,6 +177,10 @@ int sa_default_cfg(const sa_dindex *d, sa_match_cfg *cfg);
  * may be nonzero, offsets must not decrease); out[nreads]: results in input
  * order.  Reads longer than SA_MAX_READ -> SA_ETOOBIG before any work.
  * hip_stream: a hipStream_t or NULL for the null stream.  cfg may be NULL.
+ * The batch streams through pinned staging in chunks of whole reads (at most
+ * 32 MiB of bytes or 2^19 reads each): the host copies one chunk in while the
+ * device searches the one before, so the device sees each chunk as a batch
+ * of its own (stage times and counts report the last chunk).
  * Thread-safe for distinct streams. */
 int match_batch(const sa_dindex *d, const char *reads, const int64_t *offs, int64_t nreads,
                 sa_hit *out, void *hip_stream, const sa_match_cfg *cfg);

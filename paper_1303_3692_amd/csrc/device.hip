@@ -1,5 +1,7 @@
 // Device-resident index, per-stream scratch, and the batch entry points.
 #include <hip/hip_runtime.h>
+#include <system_error>
+#include <thread>
 
 #include <algorithm>
 #include <atomic>
@@ -37,12 +39,18 @@ Workspace::~Workspace() {
     drop_graphs();
     for (void *p : {(void *)b.qw, (void *)b.qlm, (void *)b.key[0], (void *)b.key[1],
                     (void *)b.val[0], (void *)b.val[1], (void *)b.hist, (void *)b.digit_total,
-                    (void *)b.stats, (void *)d_reads, (void *)d_offs, (void *)d_out})
+                    (void *)b.stats})
         if (p) (void)hipFree(p);
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
+}
+
+HostSlot::~HostSlot() {
+    for (void *p : {(void *)d_reads, (void *)d_offs, (void *)d_out})
+        if (p) (void)hipFree(p);
     for (void *p : {(void *)h_reads, (void *)h_offs, (void *)h_out})
         if (p) (void)hipHostFree(p);
+    if (done) (void)hipEventDestroy(done);
 }
 
 static hipError_t grow(void **p, size_t bytes) {
@@ -78,30 +86,34 @@ int Workspace::reserve(int64_t nreads) {
     return SA_OK;
 }
 
-int Workspace::reserve_staging(int64_t nreads, int64_t nbytes) {
+int HostSlot::reserve(int64_t nreads, int64_t nbytes) {
     hipError_t e;
+    if (!done && (e = hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "event creation");
     if (nbytes > bytes_cap) {
         const int64_t c = std::max<int64_t>(nbytes, 1 << 20);
         if (h_reads) (void)hipHostFree(h_reads);
         h_reads = nullptr;
+        bytes_cap = 0;
         if ((e = hipHostMalloc((void **)&h_reads, (size_t)c, hipHostMallocDefault)) != hipSuccess)
             return hip_fail(e, "pinned staging");
         if ((e = grow((void **)&d_reads, (size_t)c)) != hipSuccess) return hip_fail(e, "staging");
         bytes_cap = c;
     }
-    if (nreads > stage_cap) {
+    if (nreads > reads_cap) {
         const int64_t c = std::max<int64_t>(nreads, 1024);
         if (h_offs) (void)hipHostFree(h_offs);
         if (h_out) (void)hipHostFree(h_out);
         h_offs = nullptr;
         h_out = nullptr;
+        reads_cap = 0;
         if ((e = hipHostMalloc((void **)&h_offs, sizeof(int64_t) * (size_t)(c + 1), hipHostMallocDefault)) != hipSuccess ||
             (e = hipHostMalloc((void **)&h_out, sizeof(sa_hit) * (size_t)c, hipHostMallocDefault)) != hipSuccess)
             return hip_fail(e, "pinned staging");
         if ((e = grow((void **)&d_offs, sizeof(int64_t) * (size_t)(c + 1))) != hipSuccess ||
             (e = grow((void **)&d_out, sizeof(sa_hit) * (size_t)c)) != hipSuccess)
             return hip_fail(e, "staging");
-        stage_cap = c;
+        reads_cap = c;
     }
     return SA_OK;
 }
@@ -485,6 +497,37 @@ extern "C" int match_batch_dev(const sa_dindex *dc, const uint8_t *d_reads, cons
     return run_batch(d, ws, d_reads, d_offs, nullptr, nreads, d_out, s, c);
 }
 
+// Host batches stream through pinned staging in chunks of whole reads.
+constexpr int64_t kHostChunkBytes = (int64_t)32 << 20;
+constexpr int64_t kHostChunkReads = (int64_t)1 << 19;
+
+// memcpy split over a few threads (one copy thread moves ~10 GB/s; the
+// staging copies would otherwise bound a host batch below the bus rate).
+static void host_copy(void *dst, const void *src, size_t bytes) {
+    const size_t kPart = (size_t)4 << 20;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({(size_t)8, (size_t)hw, bytes / kPart});
+    if (nt <= 1) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t part = (bytes / nt + 63) & ~(size_t)63;
+    std::vector<std::thread> th;
+    try {
+        for (size_t t = 1; t < nt; t++) {
+            const size_t a = t * part, b = std::min(bytes, a + part);
+            if (a >= b) break;
+            th.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, b - a); });
+        }
+    } catch (const std::system_error &) {
+        // no more threads: this thread copies what was not handed out
+    }
+    std::memcpy(dst, src, std::min(bytes, part));
+    const size_t done = (th.size() + 1) * part;  // parts 1 .. th.size() went to the threads
+    if (done < bytes) std::memcpy((char *)dst + done, (const char *)src + done, bytes - done);
+    for (std::thread &x : th) x.join();
+}
+
 extern "C" int match_batch(const sa_dindex *dc, const char *reads, const int64_t *offs, int64_t nreads,
                            sa_hit *out, void *hip_stream, const sa_match_cfg *cfg) {
     clear_error();
@@ -506,21 +549,53 @@ extern "C" int match_batch(const sa_dindex *dc, const char *reads, const int64_t
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     Workspace *ws = workspace_for(d, s);
     std::lock_guard<std::mutex> lk(ws->mu);
-    const int64_t base = offs[0], nbytes = offs[nreads] - offs[0];
-    if ((rc = ws->reserve_staging(nreads, nbytes))) return rc;
-    std::memcpy(ws->h_reads, reads + base, (size_t)nbytes);
-    for (int64_t i = 0; i <= nreads; i++) ws->h_offs[i] = offs[i] - base;
-    hipError_t e;
-    if ((e = hipMemcpyAsync(ws->d_reads, ws->h_reads, (size_t)nbytes, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(ws->d_offs, ws->h_offs, sizeof(int64_t) * (size_t)(nreads + 1), hipMemcpyHostToDevice,
-                            s)) != hipSuccess)
-        return hip_fail(e, "batch upload");
-    if ((rc = enqueue_batch(d, ws, ws->d_reads, ws->d_offs, nullptr, nreads, ws->d_out, s, c))) return rc;
-    if ((e = hipMemcpyAsync(ws->h_out, ws->d_out, sizeof(sa_hit) * (size_t)nreads, hipMemcpyDeviceToHost, s)) !=
-            hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(e, "batch download");
-    std::memcpy(out, ws->h_out, sizeof(sa_hit) * (size_t)nreads);
+    // chunks of whole reads, at most kHostChunkBytes of ASCII (or one read)
+    // and kHostChunkReads reads each; chunk k uses slot k % 2, so the host
+    // copies chunk k in (and chunk k - 2 out) while the device works on k - 1
+    std::vector<int64_t> cuts{0};
+    int64_t most = 0;
+    while (cuts.back() < nreads) {
+        const int64_t r0 = cuts.back();
+        const int64_t by_bytes =
+            (int64_t)(std::upper_bound(offs + r0 + 1, offs + nreads + 1, offs[r0] + kHostChunkBytes) - offs) - 1;
+        const int64_t r1 = std::max(r0 + 1, std::min(r0 + kHostChunkReads, by_bytes));
+        most = std::max(most, r1 - r0);
+        cuts.push_back(r1);
+    }
+    if ((rc = ws->reserve(most))) return rc;  // no scratch growth between chunks
+    const size_t nchunks = cuts.size() - 1;
+    auto finish = [&](size_t k) -> int {
+        HostSlot &hs = ws->host[k & 1];
+        hipError_t e = hipEventSynchronize(hs.done);
+        if (e != hipSuccess) return hip_fail(e, "batch download");
+        host_copy(out + cuts[k], hs.h_out, sizeof(sa_hit) * (size_t)(cuts[k + 1] - cuts[k]));
+        return SA_OK;
+    };
+    // on an error, nothing may still be in flight on the staging buffers
+    auto bail = [&](int code) {
+        (void)hipStreamSynchronize(s);
+        return code;
+    };
+    for (size_t k = 0; k < nchunks; k++) {
+        HostSlot &hs = ws->host[k & 1];
+        if (k >= 2 && (rc = finish(k - 2))) return bail(rc);  // also frees the slot
+        const int64_t r0 = cuts[k], n = cuts[k + 1] - r0, b0 = offs[r0], nb = offs[cuts[k + 1]] - b0;
+        if ((rc = hs.reserve(n, nb))) return bail(rc);
+        host_copy(hs.h_reads, reads + b0, (size_t)nb);
+        for (int64_t i = 0; i <= n; i++) hs.h_offs[i] = offs[r0 + i] - b0;
+        hipError_t e;
+        if ((e = hipMemcpyAsync(hs.d_reads, hs.h_reads, (size_t)nb, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(hs.d_offs, hs.h_offs, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, s)) !=
+                hipSuccess)
+            return bail(hip_fail(e, "batch upload"));
+        if ((rc = enqueue_batch(d, ws, hs.d_reads, hs.d_offs, nullptr, n, hs.d_out, s, c))) return bail(rc);
+        if ((e = hipMemcpyAsync(hs.h_out, hs.d_out, sizeof(sa_hit) * (size_t)n, hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipEventRecord(hs.done, s)) != hipSuccess)
+            return bail(hip_fail(e, "batch download"));
+    }
+    for (size_t k = nchunks >= 2 ? nchunks - 2 : 0; k < nchunks; k++)
+        if ((rc = finish(k))) return bail(rc);
     return SA_OK;
 }
 

@@ -34,10 +34,24 @@ struct GraphEntry {
 
 // Scratch of one (index, stream): device buffers of the pipeline plus pinned
 // and device staging for host batches.  Grows on demand, never shrinks.
+// One of the two pinned-host / device buffer sets through which match_batch
+// streams a batch from host memory, chunk by chunk.
+struct HostSlot {
+    ~HostSlot();
+    int reserve(int64_t nreads, int64_t nbytes);
+    int64_t reads_cap = 0, bytes_cap = 0;
+    char *h_reads = nullptr;
+    int64_t *h_offs = nullptr;
+    sa_hit *h_out = nullptr;
+    uint8_t *d_reads = nullptr;
+    int64_t *d_offs = nullptr;
+    sa_hit *d_out = nullptr;
+    hipEvent_t done = nullptr;  // recorded after the slot's last chunk came back to h_out
+};
+
 struct Workspace {
     ~Workspace();
     int reserve(int64_t nreads);
-    int reserve_staging(int64_t nreads, int64_t nbytes);
     void drop_graphs();
 
     // replayable launch sequences (at most kMaxGraphs, least recently used dropped)
@@ -51,14 +65,8 @@ struct Workspace {
     // stage events of the last profiled batch, and whether counts are held
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool profiled = false, counted = false;
-    // host batches
-    int64_t stage_cap = 0, bytes_cap = 0;
-    char *h_reads = nullptr;
-    int64_t *h_offs = nullptr;
-    sa_hit *h_out = nullptr;
-    uint8_t *d_reads = nullptr;
-    int64_t *d_offs = nullptr;
-    sa_hit *d_out = nullptr;
+    // host batches: chunks alternate between the two slots
+    HostSlot host[2];
 };
 
 Workspace *workspace_for(sa_dindex *d, hipStream_t s);
