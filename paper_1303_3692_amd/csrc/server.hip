@@ -23,6 +23,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -101,7 +102,6 @@ struct Request {
     int fail_code = SA_OK;
     bool admitted = false, failed = false;
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
-    hipEvent_t uploaded = nullptr;
 };
 
 struct Piece {
@@ -135,6 +135,9 @@ struct sa_server {
     char *h_pool = nullptr;
     std::mutex pool_mu;
     hipStream_t upload_stream = nullptr;
+    hipEvent_t uploaded = nullptr;  // recorded on upload_stream after each round of admissions
+    bool any_upload = false;
+    std::vector<Request *> to_upload;  // admitted this round, reads not yet copied to the arena
     std::vector<Slot> slots;
 
     std::mutex mu;
@@ -151,8 +154,9 @@ struct sa_server {
 
     void run();
     bool admit_locked();
-    bool launch_locked(Slot &sl);
-    bool reap_locked(Slot &sl, bool wait);
+    int upload_locked();
+    bool launch(Slot &sl, std::unique_lock<std::mutex> &lk);
+    bool reap(Slot &sl, bool wait, std::unique_lock<std::mutex> &lk);
     void finish_locked(Request *r, int status);
     void echo_execute(Slot &sl);
 };
@@ -164,10 +168,6 @@ void sa_server::finish_locked(Request *r, int status) {
     if (r->arena_off >= 0) {
         arena.release(r->arena_off, r->arena_bytes);
         r->arena_off = -1;
-    }
-    if (r->uploaded) {
-        (void)hipEventDestroy(r->uploaded);
-        r->uploaded = nullptr;
     }
     if (r->admitted) inflight_reads -= r->nreads;
     if (r->pool_off >= 0) {
@@ -202,26 +202,50 @@ bool sa_server::admit_locked() {
         r->admitted = true;
         r->t_admit = now_ns();
         inflight_reads += r->nreads;
-        if (!o.test_echo && r->nreads > 0) {
-            hipError_t e = hipMemcpyAsync(d_arena + off, r->h_reads, (size_t)r->offs[(size_t)r->nreads],
-                                          hipMemcpyHostToDevice, upload_stream);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventRecord(r->uploaded, upload_stream);
-            if (e != hipSuccess) {
-                finish_locked(r, SA_EDEVICE);
-                any = true;
-                continue;
-            }
+        if (r->nreads == 0) {
+            finish_locked(r, SA_OK);
+        } else {
+            if (!o.test_echo) to_upload.push_back(r);
+            active[(size_t)r->ref].push_back(r);
         }
-        if (r->nreads == 0) finish_locked(r, SA_OK);
-        else active[(size_t)r->ref].push_back(r);
         any = true;
     }
     return any;
 }
 
+// Copy this round's admitted reads to the arena, then mark the upload
+// stream; every batch launched afterwards waits for that mark (one event
+// for the round instead of one per request).
+int sa_server::upload_locked() {
+    if (to_upload.empty()) return SA_OK;
+    std::vector<Request *> rs;
+    rs.swap(to_upload);
+    hipError_t e = hipSuccess;
+    for (Request *r : rs)
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_arena + r->arena_off, r->h_reads, (size_t)r->offs[(size_t)r->nreads],
+                               hipMemcpyHostToDevice, upload_stream);
+    if (e == hipSuccess) e = hipEventRecord(uploaded, upload_stream);
+    if (e == hipSuccess) {
+        any_upload = true;
+        return SA_OK;
+    }
+    const int rc = hip_fail(e, "request upload");
+    // none of them is in a batch yet: drop them from scheduling
+    for (Request *r : rs) {
+        auto &q = active[(size_t)r->ref];
+        q.erase(std::remove(q.begin(), q.end(), r), q.end());
+        finish_locked(r, SA_EDEVICE);
+    }
+    return rc;
+}
+
 // Form a batch for a free slot from one reference's admitted requests.
-bool sa_server::launch_locked(Slot &sl) {
+// The pieces are taken with the lock held; the per-read work (start and end
+// arrays) and the launches run with it released, so that submitters and
+// pollers are not held up (only this thread touches the slots, and a
+// request with batches in flight keeps its buffers).
+bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
     const int nref = (int)refs.size();
     int ref = -1;
     for (int k = 0; k < nref; k++) {
@@ -256,18 +280,23 @@ bool sa_server::launch_locked(Slot &sl) {
         sl.error = SA_EDEVICE;
         return true;
     }
+    lk.unlock();
+    struct Relock {
+        std::unique_lock<std::mutex> &l;
+        ~Relock() { l.lock(); }
+    } relock{lk};
     // starts and ends of every read, relative to the arena
     int64_t *st = sl.h_se, *en = sl.h_se + o.max_batch_reads;
     for (const Piece &p : sl.pieces) {
         const int64_t base = p.req->arena_off;
+        const int64_t *of = p.req->offs.data() + p.first;
         for (int64_t k = 0; k < p.count; k++) {
-            st[p.pos + k] = base + p.req->offs[(size_t)(p.first + k)];
-            en[p.pos + k] = base + p.req->offs[(size_t)(p.first + k + 1)];
+            st[p.pos + k] = base + of[k];
+            en[p.pos + k] = base + of[k + 1];
         }
     }
     hipError_t e = hipSuccess;
-    for (const Piece &p : sl.pieces)
-        if (e == hipSuccess && p.req->uploaded) e = hipStreamWaitEvent(sl.stream, p.req->uploaded, 0);
+    if (any_upload) e = hipStreamWaitEvent(sl.stream, uploaded, 0);
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl.d_se, st, sizeof(int64_t) * (size_t)rows, hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess)
@@ -282,7 +311,7 @@ bool sa_server::launch_locked(Slot &sl) {
     Workspace *ws = workspace_for(d, sl.stream);
     int rc;
     {
-        std::lock_guard<std::mutex> lk(ws->mu);
+        std::lock_guard<std::mutex> wl(ws->mu);
         rc = enqueue_batch(d, ws, d_arena, sl.d_se, sl.d_se + o.max_batch_reads, rows, sl.d_out, sl.stream,
                            resolve_cfg(d, nullptr));
     }
@@ -319,8 +348,10 @@ void sa_server::echo_execute(Slot &sl) {
         }
 }
 
-// Collect a finished batch: scatter results, finish complete requests.
-bool sa_server::reap_locked(Slot &sl, bool wait) {
+// Collect a finished batch: scatter results (with the lock released: the
+// owners' output arrays stay valid while their requests are pending),
+// then finish complete requests.
+bool sa_server::reap(Slot &sl, bool wait, std::unique_lock<std::mutex> &lk) {
     if (!sl.busy) return false;
     if (!o.test_echo && sl.error == SA_OK) {
         hipError_t e = wait ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
@@ -329,13 +360,18 @@ bool sa_server::reap_locked(Slot &sl, bool wait) {
     } else if (o.test_echo && sl.error == SA_OK) {
         echo_execute(sl);
     }
+    if (sl.error == SA_OK) {
+        lk.unlock();
+        for (const Piece &p : sl.pieces)
+            std::memcpy(p.req->out + p.first, sl.h_out + p.pos, sizeof(sa_hit) * (size_t)p.count);
+        lk.lock();
+    }
     for (const Piece &p : sl.pieces) {
         Request *r = p.req;
         r->inflight_batches--;
         if (sl.error != SA_OK) {
             if (!r->failed) { r->failed = true; r->fail_code = sl.error; }
         } else if (!r->failed) {
-            std::memcpy(r->out + p.first, sl.h_out + p.pos, sizeof(sa_hit) * (size_t)p.count);
             r->done += p.count;
         }
         if (r->inflight_batches == 0) {
@@ -359,11 +395,12 @@ void sa_server::run() {
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         bool progress = false;
-        for (Slot &sl : slots) progress |= reap_locked(sl, false);
+        for (Slot &sl : slots) progress |= reap(sl, false, lk);
         if (!stop) {
             progress |= admit_locked();
+            (void)upload_locked();
             for (Slot &sl : slots)
-                if (!sl.busy) progress |= launch_locked(sl);
+                if (!sl.busy && !stop) progress |= launch(sl, lk);
         }
         bool busy = false;
         for (Slot &sl : slots) busy |= sl.busy;
@@ -410,6 +447,8 @@ static void free_resources(sa_server *s) {
         (void)hipStreamDestroy(s->upload_stream);
         s->upload_stream = nullptr;
     }
+    if (s->uploaded) (void)hipEventDestroy(s->uploaded);
+    s->uploaded = nullptr;
     if (s->d_arena) (void)hipFree(s->d_arena);
     s->d_arena = nullptr;
     if (s->h_pool) (void)hipHostFree(s->h_pool);
@@ -481,7 +520,8 @@ extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const s
                     return hip_fail(e, "pinned host pool");
                 s->pool.init(o.host_pool_bytes);
             }
-            if ((e = hipStreamCreateWithFlags(&s->upload_stream, hipStreamNonBlocking)) != hipSuccess)
+            if ((e = hipStreamCreateWithFlags(&s->upload_stream, hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&s->uploaded, hipEventDisableTiming)) != hipSuccess)
                 return hip_fail(e, "stream creation");
             for (Slot &sl : s->slots) {
                 if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
