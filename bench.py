@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end timing from host memory")
+    ap.add_argument("--serve-streams", type=int, default=2, help="--serve: pipelines the server runs at once")
+    ap.add_argument("--serve-levels", default="0.5,0.8,0.95", help="--serve: loads relative to the offline rate")
     ap.add_argument("--no-graph", action="store_true", help="launch the kernels directly instead of replaying a graph")
     ap.add_argument("--per-length", action="store_true",
                     help="also time one batch call per distinct read length (default for c3)")
@@ -540,8 +542,6 @@ def serve_bench(args, np, torch, gen, S):
     loads relative to the offline rate of the same request mix through the
     host entry point; latency runs from each request's scheduled arrival to
     its completion (steady clock on both sides)."""
-    import threading
-
     names = args.serve_refs.split(",")
     refs, dix = [], []
     for name in names:
@@ -575,50 +575,24 @@ def serve_bench(args, np, torch, gen, S):
     log(f"{len(pool)} distinct requests ({sum(r.count for _, r in pool)} reads) generated in "
         f"{time.perf_counter() - t:.1f}s")
     levels = []
-    for k, rho in enumerate((0.5, 0.8, 0.95)):
+    for k, rho in enumerate(float(x) for x in args.serve_levels.split(",")):
         lam = rho * x_off / mean_size
         nreq = args.serve_warmup + args.serve_requests
         stream = gen.request_stream(refs, nreq, lam, seed_sub=k, pool=pool)
-        srv = S.Server(dix, max_batch_reads=1 << 20, nstreams=2)
-        tickets = [None] * nreq
-        sched = [0] * nreq
-        t0 = time.monotonic_ns() + 50_000_000
-
-        # several submitting threads (the library call releases the GIL while it copies
-        # the reads), each taking every nth request at its scheduled time
-        nthreads = 8
-
-        def submitter(part):
-            for i in range(part, nreq, nthreads):
-                due = t0 + int(stream[i].t_arrival * 1e9)
-                while True:
-                    now = time.monotonic_ns()
-                    if now >= due:
-                        break
-                    time.sleep(min(0.002, (due - now) / 1e9))
-                sched[i] = due
-                tickets[i] = srv.submit(stream[i].ref, stream[i].reads.data, stream[i].reads.offs)[0]
-
-        ths = [threading.Thread(target=submitter, args=(p,)) for p in range(nthreads)]
-        for th in ths:
-            th.start()
-        done = {}
-        for i in range(nreq):
-            while tickets[i] is None:
-                time.sleep(0.0005)
-            while True:
-                rc, st = srv.poll(tickets[i], timeout_us=100_000)
-                if rc != S.SA_PENDING:
-                    done[i] = (rc, st)
-                    break
-        for th in ths:
-            th.join()
+        srv = S.Server(dix, max_batch_reads=1 << 20, nstreams=args.serve_streams)
+        # the client: native threads of the library submit each request at
+        # its scheduled time (open loop), so no interpreter lock sits in
+        # the measured loop
+        outs, sched, stats = srv.replay([r.ref for r in stream], [r.reads.data for r in stream],
+                                        [r.reads.offs for r in stream],
+                                        [int(r.t_arrival * 1e9) for r in stream], nthreads=8)
         srv.destroy()
+        done = {i: (stats[i]["status"], stats[i]) for i in range(nreq)}
         meas = range(args.serve_warmup, nreq)
-        lat = [(done[i][1]["t_done_ns"] - sched[i]) / 1e6 for i in meas if done[i][0] == S.SA_OK]
+        lat = [(done[i][1]["t_done_ns"] - int(sched[i])) / 1e6 for i in meas if done[i][0] == S.SA_OK]
         reads_meas = sum(stream[i].reads.count for i in meas)
-        span = (max(done[i][1]["t_done_ns"] for i in meas) - min(sched[i] for i in meas)) / 1e9
-        late = sum(1 for i in range(nreq) if done[i][1]["t_submit_ns"] - sched[i] > 5_000_000)
+        span = (max(done[i][1]["t_done_ns"] for i in meas) - min(int(sched[i]) for i in meas)) / 1e9
+        late = sum(1 for i in range(nreq) if done[i][1]["t_submit_ns"] - int(sched[i]) > 5_000_000)
         lv = {"rho": rho, "requests_per_s": round(lam, 1), "p50_ms": round(percentile(lat, 0.50), 3),
               "p99_ms": round(percentile(lat, 0.99), 3), "served_reads_per_s": round(reads_meas / span, 1),
               "offered_reads_per_s": round(rho * x_off, 1), "failed": sum(1 for v in done.values() if v[0] != 0),

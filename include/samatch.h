@@ -317,6 +317,20 @@ int sa_server_create(const sa_dindex *const *refs, int nrefs, const sa_server_op
 int match_submit(sa_server *s, int ref, const char *reads, const int64_t *offs, int64_t nreads,
                  sa_hit *out, uint64_t *ticket);
 
+/* Measurement helper (an open-loop client in native threads, so that a
+ * load test measures the server and not its caller): submits request i
+ * (reference ref[i], reads[i] with offsets offs[i][0..nreads[i]], results
+ * into out[i]) at arrival_ns[i] nanoseconds after a start about 20 ms after
+ * the call, from nthreads threads (1..64; thread t submits requests t,
+ * t + nthreads, ...), then waits for every request.  sched_ns[i] receives
+ * the scheduled submit time and stats[i] the request's timestamps and
+ * status, on the steady clock of sa_req_stats.  arrival_ns must not
+ * decrease within each thread's share.  Returns SA_OK, or the first error
+ * of a submit (that request's status holds it; the others still run). */
+int sa_server_replay(sa_server *s, int64_t nreq, const int32_t *ref, const char *const *reads,
+                     const int64_t *const *offs, const int64_t *nreads, const int64_t *arrival_ns,
+                     sa_hit *const *out, int nthreads, int64_t *sched_ns, sa_req_stats *stats);
+
 /* Wait up to timeout_us (0: just look, < 0: forever) for a request.
  * Returns SA_PENDING while it runs, SA_OK once out[] is filled, or the
  * request's error code; st (nullable) receives its timestamps.  A finished

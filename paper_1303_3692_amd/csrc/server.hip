@@ -11,7 +11,8 @@
 // stream slot then takes up to max_batch_reads unscheduled reads of one
 // reference, from the admitted requests of that reference in admission
 // order, and runs one pipeline over them (the reads stay where they are in
-// the arena; the batch passes each read's start and end).  When a slot's
+// the arena; a small kernel expands the batch's pieces into each read's
+// start and end from the offsets uploaded with the reads).  When a slot's
 // batch finishes, its results are copied into the owners' output arrays;
 // a request whose reads are all done is finished and its arena space
 // returned.
@@ -85,6 +86,40 @@ class Arena {
     std::map<int64_t, int64_t> free_;
 };
 
+// A request's host copy and arena image: its bytes, zero padding to a
+// multiple of 8, then its nreads + 1 offsets (rebased to 0).
+int64_t offs_at(int64_t nbytes) { return (nbytes + 7) & ~int64_t(7); }
+int64_t image_bytes(int64_t nbytes, int64_t nreads) { return offs_at(nbytes) + 8 * (nreads + 1); }
+
+// One piece of a batch as the expansion kernel reads it: rows [pos, pos +
+// count) are reads first .. first + count - 1 of a request whose bytes start
+// at arena byte `reads_at` and whose offsets of those reads start at arena
+// byte `offs_at` (8-byte aligned).
+struct PieceDev {
+    int64_t pos, count, reads_at, offs_at;
+};
+constexpr int kMaxPieces = 4096;  // pieces per batch
+
+// Row r of the batch: its piece (the last one starting at or before r, by
+// binary search over the ascending positions), then its start and end.
+__global__ void expand_pieces_kernel(const PieceDev *__restrict__ pieces, int npieces,
+                                     const uint8_t *__restrict__ arena, int64_t rows, int64_t *__restrict__ st,
+                                     int64_t *__restrict__ en) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    int lo = 0, hi = npieces - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pieces[mid].pos <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    const PieceDev p = pieces[lo];
+    const int64_t *of = reinterpret_cast<const int64_t *>(arena + p.offs_at);
+    const int64_t k = r - p.pos;
+    st[r] = p.reads_at + of[k];
+    en[r] = p.reads_at + of[k + 1];
+}
+
 struct Request {
     uint64_t ticket = 0;
     int ref = 0;
@@ -116,7 +151,8 @@ struct Slot {
     int ref = 0;
     int64_t nreads = 0;
     std::vector<Piece> pieces;
-    int64_t *h_se = nullptr;  // starts then ends (pinned)
+    PieceDev *h_pieces = nullptr;  // pinned, kMaxPieces
+    PieceDev *d_pieces = nullptr;
     sa_hit *h_out = nullptr;  // pinned
     int64_t *d_se = nullptr;
     sa_hit *d_out = nullptr;
@@ -186,7 +222,7 @@ bool sa_server::admit_locked() {
     bool any = false;
     while (!queued.empty()) {
         Request *r = queued.front();
-        const int64_t bytes = std::max<int64_t>(1, r->offs[(size_t)r->nreads]);
+        const int64_t bytes = image_bytes(r->offs[(size_t)r->nreads], r->nreads);
         if (bytes > arena.capacity() || r->nreads > o.max_inflight_reads) {
             queued.pop_front();
             finish_locked(r, SA_ENOSPC);
@@ -223,8 +259,9 @@ int sa_server::upload_locked() {
     hipError_t e = hipSuccess;
     for (Request *r : rs)
         if (e == hipSuccess)
-            e = hipMemcpyAsync(d_arena + r->arena_off, r->h_reads, (size_t)r->offs[(size_t)r->nreads],
-                               hipMemcpyHostToDevice, upload_stream);
+            e = hipMemcpyAsync(d_arena + r->arena_off, r->h_reads,
+                               (size_t)image_bytes(r->offs[(size_t)r->nreads], r->nreads), hipMemcpyHostToDevice,
+                               upload_stream);
     if (e == hipSuccess) e = hipEventRecord(uploaded, upload_stream);
     if (e == hipSuccess) {
         any_upload = true;
@@ -259,7 +296,7 @@ bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
     sl.ref = ref;
     sl.error = SA_OK;
     int64_t rows = 0;
-    while (!q.empty() && rows < o.max_batch_reads) {
+    while (!q.empty() && rows < o.max_batch_reads && (int)sl.pieces.size() < kMaxPieces) {
         Request *r = q.front();
         const int64_t take = std::min(r->nreads - r->next, o.max_batch_reads - rows);
         sl.pieces.push_back(Piece{r, r->next, take, rows});
@@ -285,23 +322,25 @@ bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
         std::unique_lock<std::mutex> &l;
         ~Relock() { l.lock(); }
     } relock{lk};
-    // starts and ends of every read, relative to the arena
-    int64_t *st = sl.h_se, *en = sl.h_se + o.max_batch_reads;
-    for (const Piece &p : sl.pieces) {
-        const int64_t base = p.req->arena_off;
-        const int64_t *of = p.req->offs.data() + p.first;
-        for (int64_t k = 0; k < p.count; k++) {
-            st[p.pos + k] = base + of[k];
-            en[p.pos + k] = base + of[k + 1];
-        }
+    // the pieces, expanded on the device into each read's start and end
+    // (relative to the arena) once the reads' upload is done
+    const int npieces = (int)sl.pieces.size();
+    for (int i = 0; i < npieces; i++) {
+        const Piece &p = sl.pieces[(size_t)i];
+        const int64_t nbytes = p.req->offs[(size_t)p.req->nreads];
+        sl.h_pieces[i] = PieceDev{p.pos, p.count, p.req->arena_off, p.req->arena_off + offs_at(nbytes) + 8 * p.first};
     }
+    int64_t *d_st = sl.d_se, *d_en = sl.d_se + o.max_batch_reads;
     hipError_t e = hipSuccess;
     if (any_upload) e = hipStreamWaitEvent(sl.stream, uploaded, 0);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(sl.d_se, st, sizeof(int64_t) * (size_t)rows, hipMemcpyHostToDevice, sl.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sl.d_se + o.max_batch_reads, en, sizeof(int64_t) * (size_t)rows, hipMemcpyHostToDevice,
+        e = hipMemcpyAsync(sl.d_pieces, sl.h_pieces, sizeof(PieceDev) * (size_t)npieces, hipMemcpyHostToDevice,
                            sl.stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(expand_pieces_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, sl.stream,
+                           sl.d_pieces, npieces, d_arena, rows, d_st, d_en);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) {
         sl.error = hip_fail(e, "batch upload");
         (void)hipStreamSynchronize(sl.stream);  // the staging buffers are reused by the next batch
@@ -429,7 +468,8 @@ static void free_resources(sa_server *s) {
     for (Slot &sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
-        if (sl.h_se) (void)hipHostFree(sl.h_se);
+        if (sl.h_pieces) (void)hipHostFree(sl.h_pieces);
+        if (sl.d_pieces) (void)hipFree(sl.d_pieces);
         if (sl.h_out) (void)hipHostFree(sl.h_out);
         if (sl.d_se) (void)hipFree(sl.d_se);
         if (sl.d_out) (void)hipFree(sl.d_out);
@@ -526,8 +566,9 @@ extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const s
             for (Slot &sl : s->slots) {
                 if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
                     (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
-                    (e = hipHostMalloc((void **)&sl.h_se, sizeof(int64_t) * 2 * (size_t)o.max_batch_reads,
-                                       hipHostMallocDefault)) != hipSuccess ||
+                    (e = hipHostMalloc((void **)&sl.h_pieces, sizeof(PieceDev) * kMaxPieces, hipHostMallocDefault)) !=
+                        hipSuccess ||
+                    (e = hipMalloc((void **)&sl.d_pieces, sizeof(PieceDev) * kMaxPieces)) != hipSuccess ||
                     (e = hipHostMalloc((void **)&sl.h_out, sizeof(sa_hit) * (size_t)o.max_batch_reads,
                                        hipHostMallocDefault)) != hipSuccess ||
                     (e = hipMalloc((void **)&sl.d_se, sizeof(int64_t) * 2 * (size_t)o.max_batch_reads)) != hipSuccess ||
@@ -578,20 +619,25 @@ extern "C" int match_submit(sa_server *s, int ref, const char *reads, const int6
     r->t_submit = now_ns();
     try {
         const int64_t base = offs[0], nbytes = offs[nreads] - offs[0];
-        if (s->h_pool && nbytes > 0) {
+        const int64_t image = image_bytes(nbytes, nreads);
+        if (s->h_pool && nreads > 0) {
             std::lock_guard<std::mutex> pl(s->pool_mu);
-            r->pool_off = s->pool.alloc(nbytes);
-            if (r->pool_off >= 0) r->pool_bytes = nbytes;
+            r->pool_off = s->pool.alloc(image);
+            if (r->pool_off >= 0) r->pool_bytes = image;
         }
+        char *img;
         if (r->pool_off >= 0) {
-            std::memcpy(s->h_pool + r->pool_off, reads + base, (size_t)nbytes);
-            r->h_reads = s->h_pool + r->pool_off;
+            img = s->h_pool + r->pool_off;
         } else {
-            r->reads.assign(reads + base, reads + base + nbytes);
-            r->h_reads = r->reads.data();
+            r->reads.resize((size_t)image);
+            img = r->reads.data();
         }
+        if (nbytes > 0) std::memcpy(img, reads + base, (size_t)nbytes);
+        std::memset(img + nbytes, 0, (size_t)(offs_at(nbytes) - nbytes));
+        int64_t *io = reinterpret_cast<int64_t *>(img + offs_at(nbytes));
         r->offs.resize((size_t)nreads + 1);
-        for (int64_t i = 0; i <= nreads; i++) r->offs[(size_t)i] = offs[i] - base;
+        for (int64_t i = 0; i <= nreads; i++) io[i] = r->offs[(size_t)i] = offs[i] - base;
+        r->h_reads = img;
     } catch (const std::bad_alloc &) {
         release_pool(s, r.get());
         return fail(SA_ENOMEM, "request copy");
@@ -664,5 +710,50 @@ extern "C" int sa_server_destroy(sa_server *s) {
     }
     free_resources(s);
     delete s;
+    return SA_OK;
+}
+
+extern "C" int sa_server_replay(sa_server *s, int64_t nreq, const int32_t *ref, const char *const *reads,
+                                const int64_t *const *offs, const int64_t *nreads, const int64_t *arrival_ns,
+                                sa_hit *const *out, int nthreads, int64_t *sched_ns, sa_req_stats *stats) {
+    clear_error();
+    if (!s || nreq < 0 || (nreq > 0 && (!ref || !reads || !offs || !nreads || !arrival_ns || !out || !sched_ns ||
+                                        !stats)))
+        return fail(SA_EINVAL, "bad argument");
+    if (nthreads < 1 || nthreads > 64) return fail(SA_EINVAL, "nthreads must be in 1..64");
+    std::vector<uint64_t> tickets((size_t)nreq, 0);
+    std::vector<int> submit_rc((size_t)nreq, SA_OK);
+    const int64_t t0 = now_ns() + 20000000;
+    auto client = [&](int t) {
+        for (int64_t i = t; i < nreq; i += nthreads) {
+            const int64_t due = t0 + arrival_ns[i];
+            for (;;) {  // sleep to about 100 us before the due time, then spin
+                const int64_t left = due - now_ns();
+                if (left <= 0) break;
+                if (left > 150000) std::this_thread::sleep_for(std::chrono::nanoseconds(left - 100000));
+            }
+            sched_ns[i] = due;
+            submit_rc[(size_t)i] = match_submit(s, ref[i], reads[i], offs[i], nreads[i], out[i], &tickets[(size_t)i]);
+        }
+    };
+    std::vector<std::thread> th;
+    try {
+        for (int t = 0; t < nthreads; t++) th.emplace_back(client, t);
+    } catch (const std::system_error &) {
+        for (std::thread &x : th) x.join();
+        return fail(SA_ENOMEM, "client threads");
+    }
+    for (std::thread &x : th) x.join();
+    int first = SA_OK;
+    for (int64_t i = 0; i < nreq; i++) {
+        std::memset(&stats[i], 0, sizeof(sa_req_stats));
+        if (submit_rc[(size_t)i] != SA_OK) {
+            stats[i].status = submit_rc[(size_t)i];
+            if (first == SA_OK) first = submit_rc[(size_t)i];
+            continue;
+        }
+        (void)match_poll(s, tickets[(size_t)i], -1, &stats[i]);
+    }
+    if (first != SA_OK) return fail(first, "a replayed request could not be submitted");
     return SA_OK;
 }

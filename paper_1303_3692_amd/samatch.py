@@ -29,7 +29,8 @@ EXPORTS = [
     "sa_locate_dev", "sa_locate",
     "st_build", "st_free", "st_node_count", "st_root", "st_copy_nodes", "st_index_bytes", "st_upload", "st_dfree",
     "st_match_batch_dev",
-    "sa_server_create", "match_submit", "match_poll", "sa_server_destroy", "sa_strerror", "sa_last_error",
+    "sa_server_create", "match_submit", "match_poll", "sa_server_replay", "sa_server_destroy", "sa_strerror",
+    "sa_last_error",
 ]
 
 
@@ -114,6 +115,7 @@ def lib():
             "sa_server_create": ([ctypes.POINTER(ctypes.c_void_p), i32, ctypes.POINTER(ServerOpts), pp], i32),
             "match_submit": ([p, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_uint64)], i32),
             "match_poll": ([p, ctypes.c_uint64, i64, ctypes.POINTER(ReqStats)], i32),
+            "sa_server_replay": ([p, i64, p, p, p, p, p, p, i32, p, ctypes.POINTER(ReqStats)], i32),
             "sa_server_destroy": ([p], i32),
             "sa_strerror": ([i32], ctypes.c_char_p),
             "sa_last_error": ([], ctypes.c_char_p),
@@ -489,6 +491,30 @@ class Server:
             _check(rc, "match_poll")
         return rc, {"t_submit_ns": st.t_submit_ns, "t_admit_ns": st.t_admit_ns, "t_done_ns": st.t_done_ns,
                     "status": st.status, "nreads": st.nreads}
+
+    def replay(self, refs, datas, offss, arrival_ns, nthreads: int = 8):
+        """Open-loop load from native client threads (sa_server_replay):
+        request i (reference refs[i], reads datas[i] / offss[i]) is submitted
+        arrival_ns[i] ns after the start.  Returns (outs, sched_ns, stats)
+        with one (n, 4) int32 result array and one stats dict per request."""
+        n = len(refs)
+        datas = [_bytes(x) if len(x) else np.zeros(1, dtype=np.uint8) for x in datas]
+        offss = [np.ascontiguousarray(o, dtype=np.int64) for o in offss]
+        outs = [np.zeros((max(len(o) - 1, 1), 4), dtype=np.int32) for o in offss]
+        ref_a = np.ascontiguousarray(refs, dtype=np.int32)
+        nr = np.array([len(o) - 1 for o in offss], dtype=np.int64)
+        arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+        rp = np.array([x.ctypes.data for x in datas], dtype=np.uint64)
+        op = np.array([o.ctypes.data for o in offss], dtype=np.uint64)
+        outp = np.array([o.ctypes.data for o in outs], dtype=np.uint64)
+        sched = np.zeros(n, dtype=np.int64)
+        st = (ReqStats * max(n, 1))()
+        rc = lib().sa_server_replay(self._p, n, ref_a.ctypes.data, rp.ctypes.data, op.ctypes.data, nr.ctypes.data,
+                                    arr.ctypes.data, outp.ctypes.data, nthreads, sched.ctypes.data, st)
+        stats = [{"t_submit_ns": st[i].t_submit_ns, "t_admit_ns": st[i].t_admit_ns, "t_done_ns": st[i].t_done_ns,
+                  "status": st[i].status, "nreads": st[i].nreads} for i in range(n)]
+        _check(rc, "sa_server_replay")
+        return [o[:len(f) - 1] for o, f in zip(outs, offss)], sched, stats
 
     def destroy(self):
         if self._p:

@@ -92,3 +92,25 @@ def test_open_loop_stream_and_budget(refs):
         alone = S.match_batch(refs[which][3], r.data, r.offs)
         assert (out == alone).all()
     srv.destroy()
+
+
+def test_replayed_stream(refs):
+    """The native load-test client on the device: an open-loop stream over
+    both references, every result identical to the same reads matched alone."""
+    print("case: serving replay", flush=True)
+    rng = np.random.default_rng(14)
+    stream = []
+    for i in range(80):
+        which = int(rng.integers(0, 2))
+        spec = gen.ReadSpec(2900 + i, int(rng.integers(0, 5000)), 30, 300, 0.3, 0.0, 0.02)
+        stream.append((which, gen.make_reads(refs[which][0], spec)))
+    arrival = np.cumsum(rng.exponential(200_000, size=len(stream))).astype(np.int64)  # ~5,000 requests/s
+    srv = S.Server([r[3] for r in refs], max_batch_reads=1 << 16, nstreams=2)
+    outs, sched, stats = srv.replay([w for w, _ in stream], [r.data for _, r in stream], [r.offs for _, r in stream],
+                                    arrival, nthreads=4)
+    srv.destroy()
+    for (which, r), out, t, st in zip(stream, outs, sched, stats):
+        assert st["status"] == S.SA_OK
+        assert t <= st["t_submit_ns"] <= st["t_admit_ns"] <= st["t_done_ns"]
+        if r.count:
+            assert (out == S.match_batch(refs[which][3], r.data, r.offs)).all()

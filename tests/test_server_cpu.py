@@ -161,3 +161,37 @@ def test_destroy_with_pending_requests():
     outs = [srv.submit(i % 2, *make_request(rng, 20))[1] for i in range(50)]
     srv.destroy()  # must not hang or crash; unfinished outputs stay untouched
     assert all(o.shape[1] == 4 for o in outs)
+
+
+def test_replay_submits_open_loop_from_native_threads():
+    """sa_server_replay (the load-test client): every request submitted at
+    or after its scheduled time, in time order per client thread, each
+    getting its own ticket and its results, the timestamps ordered."""
+    rng = np.random.default_rng(5)
+    srv = S.Server([None, None, None], test_echo=1, max_batch_reads=300, nstreams=2)
+    n = 120
+    reqs = [make_request(rng, int(rng.integers(0, 80))) for _ in range(n)]
+    refs = [i % 3 for i in range(n)]
+    arrival = np.sort(rng.integers(0, 30_000_000, size=n))  # within 30 ms
+    outs, sched, stats = srv.replay(refs, [r[0] for r in reqs], [r[1] for r in reqs], arrival, nthreads=4)
+    tickets = set()
+    for i, ((data, offs), out, st) in enumerate(zip(reqs, outs, stats)):
+        assert st["status"] == S.SA_OK
+        assert sched[i] <= st["t_submit_ns"] <= st["t_admit_ns"] <= st["t_done_ns"]
+        assert st["nreads"] == len(offs) - 1
+        if len(offs) > 1:
+            ticket = int(out[0, 1] - out[0, 0])
+            tickets.add(ticket)
+            assert (out == echo_expect(offs, ticket, refs[i], data)).all()
+    assert len(tickets) == sum(1 for d, o in reqs if len(o) > 1) and min(tickets) >= 1 and max(tickets) <= n
+    assert (np.diff(sched) == np.diff(arrival)).all()
+    srv.destroy()
+
+
+def test_replay_rejects_bad_arguments():
+    srv = S.Server([None], test_echo=1)
+    L = S.lib()
+    assert L.sa_server_replay(None, 0, None, None, None, None, None, None, 1, None, None) == S.SA_EINVAL
+    assert L.sa_server_replay(srv._p, 0, None, None, None, None, None, None, 0, None, None) == S.SA_EINVAL
+    assert L.sa_server_replay(srv._p, 1, None, None, None, None, None, None, 1, None, None) == S.SA_EINVAL
+    srv.destroy()
