@@ -296,8 +296,9 @@ typedef struct {
     int test_echo;               /* 1: no device work, results are a deterministic echo  */
     int test_fail_batch;         /* > 0: the n-th executed batch fails (error injection) */
     int64_t host_pool_bytes;     /* pinned host memory that submit copies reads into, so
-                                    uploads are direct DMA (0: default 1 GiB, < 0: none); a
-                                    request that does not fit is copied to pageable memory */
+                                    uploads are direct DMA (0: default 1 GiB, < 0: none); when
+                                    it is full, submit waits for room; a request larger than
+                                    the whole pool is copied to pageable memory */
 } sa_server_opts;
 
 typedef struct {
@@ -311,9 +312,11 @@ typedef struct {
 int sa_server_create(const sa_dindex *const *refs, int nrefs, const sa_server_opts *opts,
                      sa_server **out);
 
-/* Queue nreads host reads against refs[ref].  The reads are copied (into
- * the server's pinned pool when it has room) before the call returns; out[nreads] must stay valid until match_poll reports
- * the request finished.  *ticket identifies the request. Thread-safe. */
+/* Queue nreads host reads against refs[ref].  The reads are copied into the
+ * server's pinned pool before the call returns (waiting for room while the
+ * pool is full: backpressure on the caller); out[nreads] must stay valid
+ * until match_poll reports the request finished.  *ticket identifies the
+ * request.  SA_ECANCELED when the server is being destroyed.  Thread-safe. */
 int match_submit(sa_server *s, int ref, const char *reads, const int64_t *offs, int64_t nreads,
                  sa_hit *out, uint64_t *ticket);
 

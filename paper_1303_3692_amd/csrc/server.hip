@@ -2,20 +2,23 @@
 // many requests, admission by a device-memory budget, several streams in
 // flight, per-request scatter of results and timestamps.
 //
-// Life of a request: submit copies its reads into pinned host memory (a
-// pool allocated once, so the upload is a direct DMA; pageable memory when
-// the pool is full) and queues it.
-// The loop admits queued requests in arrival order while the device budget
-// (free HBM minus the reserve, fixed when the server starts) has room for
-// its reads; admission copies the reads into a device arena.  Each free
-// stream slot then takes up to max_batch_reads unscheduled reads of one
-// reference, from the admitted requests of that reference in admission
-// order, and runs one pipeline over them (the reads stay where they are in
-// the arena; a small kernel expands the batch's pieces into each read's
-// start and end from the offsets uploaded with the reads).  When a slot's
-// batch finishes, its results are copied into the owners' output arrays;
-// a request whose reads are all done is finished and its arena space
-// returned.
+// Life of a request: submit copies its reads and offsets into pinned host
+// memory (a pool allocated once and mapped into the device's address space,
+// so the kernels read the request there, over the bus, with no upload;
+// submit waits for room when the pool is full, and only a request larger
+// than the whole pool goes to pageable memory and through the device arena)
+// and queues it.
+// The loop admits queued requests in arrival order while the in-flight
+// read budget allows (and, for a request outside the pool, the device
+// arena, sized from free HBM minus the reserve when the server starts, has
+// room; admission copies it there).  Each free stream slot then takes up to
+// max_batch_reads unscheduled reads of one reference, from the admitted
+// requests of that reference in admission order, and runs one pipeline over
+// them (the reads stay where they are; a small kernel expands the batch's
+// pieces into each read's start and end from the offsets stored with the
+// reads).  A scatter thread copies a finished batch's results into the
+// owners' output arrays while the loop keeps scheduling; a request whose
+// reads are all done is finished and its pool and arena space returned.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -93,8 +96,10 @@ int64_t image_bytes(int64_t nbytes, int64_t nreads) { return offs_at(nbytes) + 8
 
 // One piece of a batch as the expansion kernel reads it: rows [pos, pos +
 // count) are reads first .. first + count - 1 of a request whose bytes start
-// at arena byte `reads_at` and whose offsets of those reads start at arena
-// byte `offs_at` (8-byte aligned).
+// at byte `reads_at` and whose offsets of those reads start at byte
+// `offs_at` (8-byte aligned), both relative to the arena base (a request
+// read from the mapped host pool lies outside the arena: the difference of
+// the two addresses).
 struct PieceDev {
     int64_t pos, count, reads_at, offs_at;
 };
@@ -114,7 +119,7 @@ __global__ void expand_pieces_kernel(const PieceDev *__restrict__ pieces, int np
         else hi = mid - 1;
     }
     const PieceDev p = pieces[lo];
-    const int64_t *of = reinterpret_cast<const int64_t *>(arena + p.offs_at);
+    const int64_t *of = reinterpret_cast<const int64_t *>((uintptr_t)arena + (uintptr_t)p.offs_at);
     const int64_t k = r - p.pos;
     st[r] = p.reads_at + of[k];
     en[r] = p.reads_at + of[k + 1];
@@ -130,6 +135,7 @@ struct Request {
     std::vector<int64_t> offs;    // nreads + 1, rebased to 0
     sa_hit *out = nullptr;        // caller's
     int64_t arena_off = -1, arena_bytes = 0;
+    int64_t dev_at = 0;           // where the kernels find the image, relative to the arena base
     int64_t next = 0;             // next unscheduled read
     int64_t done = 0;             // reads with results
     int inflight_batches = 0;
@@ -148,6 +154,7 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
+    bool scattering = false;  // done on the device, results being copied out
     int ref = 0;
     int64_t nreads = 0;
     std::vector<Piece> pieces;
@@ -169,7 +176,10 @@ struct sa_server {
     uint8_t *d_arena = nullptr;
     Arena pool;                // pinned host pool for submitted reads (own lock)
     char *h_pool = nullptr;
+    uint8_t *pool_dev = nullptr;  // the pool as the device addresses it (reads are taken from it directly)
     std::mutex pool_mu;
+    std::condition_variable pool_cv;  // room was returned to the pool, or the server stops
+    bool pool_closed = false;         // under pool_mu
     hipStream_t upload_stream = nullptr;
     hipEvent_t uploaded = nullptr;  // recorded on upload_stream after each round of admissions
     bool any_upload = false;
@@ -187,12 +197,20 @@ struct sa_server {
     int next_ref = 0;
     bool stop = false;
     std::thread loop;
+    // finished batches whose results the scatter thread copies into the
+    // owners' arrays (the loop thread meanwhile keeps scheduling)
+    std::deque<Slot *> to_scatter;
+    std::condition_variable cv_scatter;
+    bool scatter_stop = false;
+    std::thread scatter;
 
     void run();
     bool admit_locked();
     int upload_locked();
     bool launch(Slot &sl, std::unique_lock<std::mutex> &lk);
     bool reap(Slot &sl, bool wait, std::unique_lock<std::mutex> &lk);
+    void settle_locked(Slot &sl);
+    void scatter_run();
     void finish_locked(Request *r, int status);
     void echo_execute(Slot &sl);
 };
@@ -209,6 +227,7 @@ void sa_server::finish_locked(Request *r, int status) {
     if (r->pool_off >= 0) {
         std::lock_guard<std::mutex> pl(pool_mu);
         pool.release(r->pool_off, r->pool_bytes);
+        pool_cv.notify_all();
         r->pool_off = -1;
     }
     r->h_reads = nullptr;
@@ -217,31 +236,40 @@ void sa_server::finish_locked(Request *r, int status) {
     cv_done.notify_all();
 }
 
-// Admit queued requests in arrival order while the budget allows.
+// Admit queued requests in arrival order while the budget allows.  A
+// request in the pinned pool is read by the kernels where it is (the device
+// maps the pool), so it needs no arena space and no upload; any other one is
+// copied to the arena.
 bool sa_server::admit_locked() {
     bool any = false;
     while (!queued.empty()) {
         Request *r = queued.front();
         const int64_t bytes = image_bytes(r->offs[(size_t)r->nreads], r->nreads);
-        if (bytes > arena.capacity() || r->nreads > o.max_inflight_reads) {
+        const bool mapped = pool_dev != nullptr && r->pool_off >= 0;
+        if ((!mapped && bytes > arena.capacity()) || r->nreads > o.max_inflight_reads) {
             queued.pop_front();
             finish_locked(r, SA_ENOSPC);
             any = true;
             continue;
         }
         if (inflight_reads > 0 && inflight_reads + r->nreads > o.max_inflight_reads) break;
-        const int64_t off = arena.alloc(bytes);
-        if (off < 0) break;
+        if (!mapped) {
+            const int64_t off = arena.alloc(bytes);
+            if (off < 0) break;
+            r->arena_off = off;
+            r->arena_bytes = bytes;
+            r->dev_at = off;
+        } else {
+            r->dev_at = (int64_t)((uintptr_t)(pool_dev + r->pool_off) - (uintptr_t)d_arena);
+        }
         queued.pop_front();
-        r->arena_off = off;
-        r->arena_bytes = bytes;
         r->admitted = true;
         r->t_admit = now_ns();
         inflight_reads += r->nreads;
         if (r->nreads == 0) {
             finish_locked(r, SA_OK);
         } else {
-            if (!o.test_echo) to_upload.push_back(r);
+            if (!o.test_echo && !mapped) to_upload.push_back(r);
             active[(size_t)r->ref].push_back(r);
         }
         any = true;
@@ -328,7 +356,7 @@ bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
     for (int i = 0; i < npieces; i++) {
         const Piece &p = sl.pieces[(size_t)i];
         const int64_t nbytes = p.req->offs[(size_t)p.req->nreads];
-        sl.h_pieces[i] = PieceDev{p.pos, p.count, p.req->arena_off, p.req->arena_off + offs_at(nbytes) + 8 * p.first};
+        sl.h_pieces[i] = PieceDev{p.pos, p.count, p.req->dev_at, p.req->dev_at + offs_at(nbytes) + 8 * p.first};
     }
     int64_t *d_st = sl.d_se, *d_en = sl.d_se + o.max_batch_reads;
     hipError_t e = hipSuccess;
@@ -391,7 +419,8 @@ void sa_server::echo_execute(Slot &sl) {
 // owners' output arrays stay valid while their requests are pending),
 // then finish complete requests.
 bool sa_server::reap(Slot &sl, bool wait, std::unique_lock<std::mutex> &lk) {
-    if (!sl.busy) return false;
+    (void)lk;
+    if (!sl.busy || sl.scattering) return false;
     if (!o.test_echo && sl.error == SA_OK) {
         hipError_t e = wait ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
         if (e == hipErrorNotReady) return false;
@@ -399,12 +428,19 @@ bool sa_server::reap(Slot &sl, bool wait, std::unique_lock<std::mutex> &lk) {
     } else if (o.test_echo && sl.error == SA_OK) {
         echo_execute(sl);
     }
-    if (sl.error == SA_OK) {
-        lk.unlock();
-        for (const Piece &p : sl.pieces)
-            std::memcpy(p.req->out + p.first, sl.h_out + p.pos, sizeof(sa_hit) * (size_t)p.count);
-        lk.lock();
+    if (sl.error == SA_OK) {  // the scatter thread copies the results out, then settles the slot
+        sl.scattering = true;
+        to_scatter.push_back(&sl);
+        cv_scatter.notify_one();
+        return true;
     }
+    settle_locked(sl);
+    return true;
+}
+
+// Account a finished batch whose results (if any) are in the owners'
+// arrays: finish complete requests, free the slot.
+void sa_server::settle_locked(Slot &sl) {
     for (const Piece &p : sl.pieces) {
         Request *r = p.req;
         r->inflight_batches--;
@@ -425,8 +461,27 @@ bool sa_server::reap(Slot &sl, bool wait, std::unique_lock<std::mutex> &lk) {
         }
     }
     sl.busy = false;
+    sl.scattering = false;
     sl.pieces.clear();
-    return true;
+}
+
+// Copy finished batches' results into the owners' output arrays with the
+// lock released (a request with a batch in flight is pending, so its array
+// stays valid), then settle them.
+void sa_server::scatter_run() {
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        cv_scatter.wait(lk, [&] { return scatter_stop || !to_scatter.empty(); });
+        if (to_scatter.empty()) break;  // stopping, nothing left
+        Slot *sl = to_scatter.front();
+        to_scatter.pop_front();
+        lk.unlock();
+        for (const Piece &p : sl->pieces)
+            std::memcpy(p.req->out + p.first, sl->h_out + p.pos, sizeof(sa_hit) * (size_t)p.count);
+        lk.lock();
+        settle_locked(*sl);
+        cv_work.notify_one();
+    }
 }
 
 void sa_server::run() {
@@ -556,9 +611,14 @@ extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const s
                 return hip_fail(e, "arena allocation");
             s->arena.init(arena_bytes);
             if (o.host_pool_bytes > 0) {
-                if ((e = hipHostMalloc((void **)&s->h_pool, (size_t)o.host_pool_bytes, hipHostMallocDefault)) != hipSuccess)
+                // coherent and mapped: the kernels read requests from it directly
+                if ((e = hipHostMalloc((void **)&s->h_pool, (size_t)o.host_pool_bytes,
+                                       hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
                     return hip_fail(e, "pinned host pool");
                 s->pool.init(o.host_pool_bytes);
+                void *dp = nullptr;
+                if (hipHostGetDevicePointer(&dp, s->h_pool, 0) == hipSuccess && dp) s->pool_dev = (uint8_t *)dp;
+                (void)hipGetLastError();  // without a mapping, requests go through the arena
             }
             if ((e = hipStreamCreateWithFlags(&s->upload_stream, hipStreamNonBlocking)) != hipSuccess ||
                 (e = hipEventCreateWithFlags(&s->uploaded, hipEventDisableTiming)) != hipSuccess)
@@ -588,7 +648,21 @@ extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const s
         return rc;
     }
     sa_server *raw = s.get();
-    s->loop = std::thread([raw] { raw->run(); });
+    try {
+        s->scatter = std::thread([raw] { raw->scatter_run(); });
+        s->loop = std::thread([raw] { raw->run(); });
+    } catch (const std::system_error &) {
+        if (s->scatter.joinable()) {
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->scatter_stop = true;
+                s->cv_scatter.notify_all();
+            }
+            s->scatter.join();
+        }
+        free_resources(s.get());
+        return fail(SA_ENOMEM, "server threads");
+    }
     *out = s.release();
     return SA_OK;
 }
@@ -597,6 +671,7 @@ static void release_pool(sa_server *s, Request *r) {
     if (r->pool_off < 0) return;
     std::lock_guard<std::mutex> pl(s->pool_mu);
     s->pool.release(r->pool_off, r->pool_bytes);
+    s->pool_cv.notify_all();
     r->pool_off = -1;
 }
 
@@ -620,9 +695,15 @@ extern "C" int match_submit(sa_server *s, int ref, const char *reads, const int6
     try {
         const int64_t base = offs[0], nbytes = offs[nreads] - offs[0];
         const int64_t image = image_bytes(nbytes, nreads);
-        if (s->h_pool && nreads > 0) {
-            std::lock_guard<std::mutex> pl(s->pool_mu);
-            r->pool_off = s->pool.alloc(image);
+        if (s->h_pool && nreads > 0 && image <= s->pool.capacity()) {
+            // wait for room rather than take the pageable path: a pageable
+            // request's upload is a synchronous copy on the request loop
+            std::unique_lock<std::mutex> pl(s->pool_mu);
+            for (;;) {
+                r->pool_off = s->pool.alloc(image);
+                if (r->pool_off >= 0 || s->pool_closed) break;
+                s->pool_cv.wait(pl);
+            }
             if (r->pool_off >= 0) r->pool_bytes = image;
         }
         char *img;
@@ -681,6 +762,11 @@ extern "C" int sa_server_destroy(sa_server *s) {
     clear_error();
     if (!s) return SA_OK;
     {
+        std::lock_guard<std::mutex> pl(s->pool_mu);
+        s->pool_closed = true;  // submitters waiting for room give up
+        s->pool_cv.notify_all();
+    }
+    {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
         // queued and admitted-but-unscheduled work is cancelled now; batches
@@ -703,6 +789,12 @@ extern "C" int sa_server_destroy(sa_server *s) {
         s->cv_work.notify_all();
     }
     if (s->loop.joinable()) s->loop.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->scatter_stop = true;
+        s->cv_scatter.notify_all();
+    }
+    if (s->scatter.joinable()) s->scatter.join();
     {
         std::lock_guard<std::mutex> lk(s->mu);
         for (auto &kv : s->all)

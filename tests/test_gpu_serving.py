@@ -66,8 +66,13 @@ def test_requests_alone_and_in_the_mix(refs):
     srv.destroy()
 
 
-def test_open_loop_stream_and_budget(refs):
-    print("case: serving stream", flush=True)
+@pytest.mark.parametrize("pool", [-1, 0])
+def test_open_loop_stream_and_budget(refs, pool):
+    """pool -1: no pinned pool, every request goes through the device arena
+    under a 4 MB budget (requests wait for admission; one that can never fit
+    is refused).  pool 0: the default mapped pool, read by the kernels in
+    place; the arena budget does not apply and the big request runs."""
+    print("case: serving stream, pool", pool, flush=True)
     rng = np.random.default_rng(13)
     reqs = []
     for i in range(40):
@@ -75,18 +80,22 @@ def test_open_loop_stream_and_budget(refs):
         spec = gen.ReadSpec(1900 + i, int(rng.integers(1, 3000)), 30, 300, 0.2, 0.01, 0.01)
         reqs.append((which, gen.make_reads(refs[which][0], spec)))
     # a device budget of about 3.7 MB for read data (4 MB less the per-stream
-    # buffers): requests wait for admission, and a 6 MB request never fits
+    # buffers)
     free_now = torch.cuda.mem_get_info()[0]
     srv = S.Server([r[3] for r in refs], test_fake_free_hbm=free_now, hbm_reserve_bytes=free_now - (4 << 20),
-                   max_batch_reads=1024, nstreams=2)
+                   max_batch_reads=1024, nstreams=2, host_pool_bytes=pool)
     big = gen.make_reads(refs[0][0], gen.ReadSpec(2999, 30_000, 200, 200, 0.0, 0.0, 0.0))
     tickets = []
     for which, r in reqs:
         tickets.append(srv.submit(which, r.data, r.offs))
         time.sleep(0.001)
-    t_big, _ = srv.submit(0, big.data, big.offs)
+    t_big, out_big = srv.submit(0, big.data, big.offs)
     res = wait_all(srv, [t for t, _ in tickets] + [t_big])
-    assert res[t_big][0] == S.SA_ENOSPC
+    if pool < 0:
+        assert res[t_big][0] == S.SA_ENOSPC
+    else:
+        assert res[t_big][0] == S.SA_OK
+        assert (out_big == S.match_batch(refs[0][3], big.data, big.offs)).all()
     for (t, out), (which, r) in zip(tickets, reqs):
         assert res[t][0] == S.SA_OK
         alone = S.match_batch(refs[which][3], r.data, r.offs)
