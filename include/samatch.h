@@ -295,10 +295,14 @@ typedef struct {
     int64_t test_fake_free_hbm;  /* < 0: ask the device; >= 0: pretend this much is free */
     int test_echo;               /* 1: no device work, results are a deterministic echo  */
     int test_fail_batch;         /* > 0: the n-th executed batch fails (error injection) */
-    int64_t host_pool_bytes;     /* pinned host memory that submit copies reads into, so
-                                    uploads are direct DMA (0: default 1 GiB, < 0: none); when
-                                    it is full, submit waits for room; a request larger than
-                                    the whole pool is copied to pageable memory */
+    int64_t host_pool_bytes;     /* pinned host memory, mapped for the device, that submit
+                                    copies reads into; the kernels read them there with no
+                                    upload (0: default 1 GiB, < 0: none); when it is full,
+                                    submit waits for room; a request larger than the whole
+                                    pool (or any request without a pool) is copied to pageable
+                                    memory and uploaded into a device arena, sized from free
+                                    HBM less hbm_reserve_bytes, where it needs room to be
+                                    admitted (SA_ENOSPC when it could never fit) */
 } sa_server_opts;
 
 typedef struct {
@@ -307,7 +311,10 @@ typedef struct {
     int64_t nreads;
 } sa_req_stats;
 
-/* Start a request loop over nrefs resident indexes (all on one device). The
+/* Start a request loop over nrefs resident indexes (all on one device):
+ * requests are admitted in arrival order while max_inflight_reads allows,
+ * batched per reference across requests (continuous batching) on nstreams
+ * streams, and their results scattered back by a thread of their own.  The
  * indexes must outlive the server.  opts may be NULL (defaults). */
 int sa_server_create(const sa_dindex *const *refs, int nrefs, const sa_server_opts *opts,
                      sa_server **out);
