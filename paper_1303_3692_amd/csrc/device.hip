@@ -177,9 +177,9 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
     const bool prof = c.profile != 0;
     hipError_t e = hipSuccess;
     if (prof && (e = hipEventRecord(ws->ev[0], s)) != hipSuccess) return hip_fail(e, "event record");
-    // reads in input order from CSR offsets: the tuned kernel can pack them
-    // itself when its tile and the waves' packing areas fit in LDS
-    const bool inl = c.kernel == SA_KERNEL_TUNED && c.inline_pack && c.sort == 0 && d_ends == nullptr &&
+    // reads in input order: the tuned kernel can pack them itself when its
+    // tile and the waves' packing areas fit in LDS
+    const bool inl = c.kernel == SA_KERNEL_TUNED && c.inline_pack && c.sort == 0 &&
                      tuned_lds_bytes(c.tile_levels, c.count ? 256 : c.block, true) <= inline_lds_limit();
     if (inl) {
         e = launch_clear_stats(ws->b, s);
@@ -225,13 +225,14 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         const int group = (int)std::max<int64_t>(1, std::min<int64_t>(c.group, chunks / gmax));
         const int grid = (int)std::min<int64_t>(gmax, (chunks + group - 1) / group);
         e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, group, ws->b, order,
-                                inl ? d_reads : nullptr, inl ? d_offs : nullptr, nreads, d_out, c.count != 0, s);
+                                inl ? d_reads : nullptr, inl ? d_offs : nullptr, inl ? d_ends : nullptr, nreads, d_out,
+                                c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
     // reads longer than kShortMax: their own kernel, over the tail of the sorted order
     const uint32_t long_field = (long_read_key(c.nbuckets) >> key_shift) & key_mask;
     e = launch_search_long(d->view, d_reads, d_offs, ws->b, order, sorted_key, key_shift, key_mask, long_field,
-                           c.prefix_table, inl,
+                           c.prefix_table, inl, inl ? d_ends : nullptr,
                            (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)d->cu_count * 8, (nreads + 63) / 64)),
                            nreads, d_out, c.count != 0, s);
     if (e != hipSuccess) return hip_fail(e, "long-read search launch");

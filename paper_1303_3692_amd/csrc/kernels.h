@@ -111,14 +111,16 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi
 // count = true runs the instrumented variant that fills b.stats.
 // group: 64-read chunks per block of the work split (see the kernel).
 // use_table: start LB searches from the prefix table (when the index has one).
-// offs not NULL: the kernel packs the reads itself from reads/offs (CSR,
-// input order: order must be NULL; no pack kernel runs, and b.stats must be
+// offs not NULL: the kernel packs the reads itself from reads/offs (and
+// ends, when not NULL: read i is reads[offs[i] .. ends[i]), else CSR) in
+// input order (order must be NULL; no pack kernel runs, and b.stats must be
 // cleared before, see launch_clear_stats); the dynamic LDS is then
 // tuned_lds_bytes(tile_levels, block, true), which must not exceed
 // inline_lds_limit().
 hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int use_table, int block, int grid,
                                int group, const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
-                               const int64_t *offs, int64_t nreads, void *out, bool count, hipStream_t s);
+                               const int64_t *offs, const int64_t *ends, int64_t nreads, void *out, bool count,
+                               hipStream_t s);
 
 // Most dynamic LDS an inline-packing tuned kernel may take on the device
 // that prepare_kernels last ran on (0 before).
@@ -136,12 +138,13 @@ hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_
 // long reads sort last, from the first row whose key bits
 // [key_shift, key_shift + bits(key_mask)) reach long_field.
 // Read i starts at reads[offs[i]] (offs holds the start array in gather mode).
-// lengths_from_offs: take each read's length from the CSR offsets instead of
-// the pack kernel's record (when the search kernel packed its reads).
+// lengths_from_offs: take each read's length from offs (and ends, when not
+// NULL) instead of the pack kernel's record (when the search kernel packed
+// its reads).
 hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b,
                               const uint32_t *order, const uint32_t *sorted_key, int key_shift, uint32_t key_mask,
-                              uint32_t long_field, int use_table, bool lengths_from_offs, int grid, int64_t nreads,
-                              void *out, bool count, hipStream_t s);
+                              uint32_t long_field, int use_table, bool lengths_from_offs, const int64_t *ends,
+                              int grid, int64_t nreads, void *out, bool count, hipStream_t s);
 
 // Suffix-tree search, one read per lane, reads in input order, each packed
 // into LDS by its wave (reads of up to SA_MAX_READ bases).

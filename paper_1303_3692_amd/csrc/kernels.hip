@@ -790,26 +790,36 @@ struct Span {
     bool staged;
 };
 
-// Offsets of the reads of chunk (none when chunk < 0): loads issued here,
-// used later.
-__device__ __forceinline__ void chunk_offsets(const int64_t *__restrict__ offs, int64_t chunk, int64_t nreads,
-                                              int lane, int64_t &a, int64_t &e) {
+// Start and end of each read of chunk (none when chunk < 0): loads issued
+// here, used later.  Read j ends at offs[j + 1], or at ends[j] when an end
+// array is given (reads gathered from anywhere in the buffer).
+__device__ __forceinline__ void chunk_offsets(const int64_t *__restrict__ offs, const int64_t *__restrict__ ends,
+                                              int64_t chunk, int64_t nreads, int lane, int64_t &a, int64_t &e) {
     const int64_t j = (chunk << 6) + lane;
     const bool act = chunk >= 0 && j < nreads;
     a = act ? offs[j] : 0;
-    e = act ? offs[j + 1] : 0;
+    e = act ? (ends ? ends[j] : offs[j + 1]) : 0;
 }
 
-__device__ __forceinline__ Span chunk_span(const uint8_t *__restrict__ reads, int64_t chunk, int64_t nreads,
-                                           int64_t a, int64_t e) {
+// With an end array the span is staged only when the chunk's reads follow
+// each other (every read ends where the next starts), so that every staged
+// byte belongs to one of them; with CSR offsets the span lies between two
+// offsets of the one buffer.
+__device__ __forceinline__ Span chunk_span(const uint8_t *__restrict__ reads, bool gathered, int64_t chunk,
+                                           int64_t nreads, int lane, int64_t a, int64_t e) {
     Span sp{0, 0, 0, 0, false};
     if (chunk < 0) return sp;
     const int last = (int)min_i(63, (int)(nreads - 1 - (chunk << 6)));
     sp.s0 = __shfl(a, 0, 64);
     sp.s1 = __shfl(e, last, 64);
+    bool joined = true;
+    if (gathered) {
+        const int64_t next_a = __shfl_down(a, 1, 64);
+        joined = __ballot(lane < last && e != next_a) == 0;
+    }
     sp.A0 = (uintptr_t)(reads + sp.s0) & ~(uintptr_t)15;
     const uintptr_t A1 = ((uintptr_t)(reads + sp.s1) + 15) & ~(uintptr_t)15;
-    sp.staged = sp.s1 > sp.s0 && A1 - sp.A0 <= (uintptr_t)kInlineVec * 16u;
+    sp.staged = joined && sp.s1 > sp.s0 && A1 - sp.A0 <= (uintptr_t)kInlineVec * 16u;
     sp.nvec = sp.staged ? (int)((A1 - sp.A0) >> 4) : 0;
     return sp;
 }
@@ -956,7 +966,8 @@ template <int BLOCK, bool COUNT, bool INLINE>
 __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group,
                                                              BatchBuffers b, const uint32_t *__restrict__ order,
                                                              const uint8_t *__restrict__ reads,
-                                                             const int64_t *__restrict__ offs, int64_t nreads,
+                                                             const int64_t *__restrict__ offs,
+                                                             const int64_t *__restrict__ ends, int64_t nreads,
                                                              int4 *__restrict__ out) {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned s_next;
@@ -995,16 +1006,19 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
     };
     if constexpr (INLINE) {
         int64_t c0 = take(), a0, e0;
-        chunk_offsets(offs, c0, nreads, lane, a0, e0);
-        Span sp0 = chunk_span(reads, c0, nreads, a0, e0);
+        chunk_offsets(offs, ends, c0, nreads, lane, a0, e0);
+        Span sp0 = chunk_span(reads, ends != nullptr, c0, nreads, lane, a0, e0);
         uint4 v[kInlineAhead];
         span_prefetch(sp0, lane, v, cnt);
         int64_t c1 = c0 >= 0 ? take() : -1, a1, e1;
-        chunk_offsets(offs, c1, nreads, lane, a1, e1);
+        chunk_offsets(offs, ends, c1, nreads, lane, a1, e1);
         while (c0 >= 0) {
             const int64_t j = (c0 << 6) + lane;
             const bool active = j < nreads;
-            if (COUNT && active) cnt.touch(offs + j, 16);
+            if (COUNT && active) {
+                cnt.touch(offs + j, ends ? 8 : 16);
+                if (ends) cnt.touch(ends + j, 8);
+            }
             const int64_t m64 = e0 - a0;
             // m = -1: length out of range (the too-long result); long reads are the long kernel's
             const bool long_read = active && m64 > kShortMax && m64 <= SA_MAX_READ;
@@ -1031,11 +1045,11 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
             }
             if (sp0.staged) wave_lds_sync();  // every lane has its words before the area is reused
             // loads for the chunks ahead, in flight during this chunk's searches
-            const Span sp1 = chunk_span(reads, c1, nreads, a1, e1);
+            const Span sp1 = chunk_span(reads, ends != nullptr, c1, nreads, lane, a1, e1);
             span_prefetch(sp1, lane, v, cnt);
             const int64_t c2 = c1 >= 0 ? take() : -1;
             int64_t a2, e2;
-            chunk_offsets(offs, c2, nreads, lane, a2, e2);
+            chunk_offsets(offs, ends, c2, nreads, lane, a2, e2);
             const int wn = max_i(1, (m + 31) >> 5);
             int wc = 1;
 #pragma unroll
@@ -1201,17 +1215,17 @@ hipError_t allow_tile_lds(size_t inline_lds) {
 
 template <int BLOCK, bool COUNT>
 hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int group, int grid, const BatchBuffers &b,
-                              const uint32_t *order, const uint8_t *reads, const int64_t *offs, int64_t nreads,
-                              int4 *out, hipStream_t s) {
+                              const uint32_t *order, const uint8_t *reads, const int64_t *offs, const int64_t *ends,
+                              int64_t nreads, int4 *out, hipStream_t s) {
     if (offs) {
         const size_t lds = tuned_lds_bytes(levels, BLOCK, true);
         if (lds > g_inline_lds.load()) return hipErrorInvalidValue;
         hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, true>), dim3(grid), dim3(BLOCK), lds, s, ix, levels,
-                           use_table, group, b, order, reads, offs, nreads, out);
+                           use_table, group, b, order, reads, offs, ends, nreads, out);
     } else {
         hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, false>), dim3(grid), dim3(BLOCK),
-                           tile_lds_bytes(levels), s, ix, levels, use_table, group, b, order, reads, offs, nreads,
-                           out);
+                           tile_lds_bytes(levels), s, ix, levels, use_table, group, b, order, reads, offs, ends,
+                           nreads, out);
     }
     return hipGetLastError();
 }
@@ -1325,8 +1339,8 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
                                                          const uint32_t *__restrict__ order,
                                                          const uint32_t *__restrict__ sorted_key, int key_shift,
                                                          uint32_t key_mask, uint32_t long_field, int use_table_i,
-                                                         int lengths_from_offs, int64_t nreads,
-                                                         int4 *__restrict__ out) {
+                                                         int lengths_from_offs, const int64_t *__restrict__ ends,
+                                                         int64_t nreads, int4 *__restrict__ out) {
     __shared__ uint64_t slot[64][kLongWords];
     __shared__ int64_t s_first;
     const int lane = threadIdx.x;
@@ -1356,7 +1370,7 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         const int rid = act ? (order ? (int)order[j] : (int)j) : 0;
         ReadLen lm;
         if (lengths_from_offs) {  // input order, CSR offsets: a read of kShortMax+1 .. SA_MAX_READ bases is long
-            const int64_t m64 = act ? offs[rid + 1] - offs[rid] : -1;
+            const int64_t m64 = act ? (ends ? ends[rid] : offs[rid + 1]) - offs[rid] : -1;
             const bool lng = m64 > kShortMax && m64 <= SA_MAX_READ;
             lm = decode_len(encode_len(lng ? (int)m64 : -1, lng ? -1 : 0, 0));
             if (COUNT && act) cnt.touch(offs + rid, 16);
@@ -1553,20 +1567,23 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi
 
 hipError_t launch_search_tuned(const DevIndex &ix, int levels, int use_table, int block, int grid, int group,
                                const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
-                               const int64_t *offs, int64_t nreads, void *out, bool count, hipStream_t s) {
+                               const int64_t *offs, const int64_t *ends, int64_t nreads, void *out, bool count,
+                               hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
     if (group < 1 || (offs && order)) return hipErrorInvalidValue;
     if (count)  // counts do not depend on the workgroup shape or the work split
         return launch_tuned_block<256, true>(ix, levels, use_table, group, grid * (block / 256), b, order, reads, offs,
-                                             nreads, o, s);
+                                             ends, nreads, o, s);
     switch (block) {
         case 256:
-            return launch_tuned_block<256, false>(ix, levels, use_table, group, grid, b, order, reads, offs, nreads, o, s);
+            return launch_tuned_block<256, false>(ix, levels, use_table, group, grid, b, order, reads, offs, ends, nreads,
+                                                   o, s);
         case 512:
-            return launch_tuned_block<512, false>(ix, levels, use_table, group, grid, b, order, reads, offs, nreads, o, s);
+            return launch_tuned_block<512, false>(ix, levels, use_table, group, grid, b, order, reads, offs, ends, nreads,
+                                                   o, s);
         case 1024:
-            return launch_tuned_block<1024, false>(ix, levels, use_table, group, grid, b, order, reads, offs, nreads, o,
-                                                   s);
+            return launch_tuned_block<1024, false>(ix, levels, use_table, group, grid, b, order, reads, offs, ends, nreads,
+                                                   o, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1580,18 +1597,18 @@ hipError_t launch_build_prefix_table(const DevIndex &ix, int k, uint32_t *tab, h
 
 hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b,
                               const uint32_t *order, const uint32_t *sorted_key, int key_shift, uint32_t key_mask,
-                              uint32_t long_field, int use_table, bool lengths_from_offs, int grid, int64_t nreads,
-                              void *out, bool count, hipStream_t s) {
+                              uint32_t long_field, int use_table, bool lengths_from_offs, const int64_t *ends,
+                              int grid, int64_t nreads, void *out, bool count, hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
     const dim3 g((unsigned)(grid > 0 ? grid : 1));
     if (lengths_from_offs && order) return hipErrorInvalidValue;
     const int lfo = lengths_from_offs ? 1 : 0;
     if (count)
         hipLaunchKernelGGL(search_long_kernel<true>, g, dim3(64), 0, s, ix, reads, offs, b, order, sorted_key,
-                           key_shift, key_mask, long_field, use_table, lfo, nreads, o);
+                           key_shift, key_mask, long_field, use_table, lfo, ends, nreads, o);
     else
         hipLaunchKernelGGL(search_long_kernel<false>, g, dim3(64), 0, s, ix, reads, offs, b, order, sorted_key,
-                           key_shift, key_mask, long_field, use_table, lfo, nreads, o);
+                           key_shift, key_mask, long_field, use_table, lfo, ends, nreads, o);
     return hipGetLastError();
 }
 
