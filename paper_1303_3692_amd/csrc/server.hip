@@ -208,7 +208,7 @@ struct sa_server {
     bool admit_locked();
     int upload_locked();
     bool launch(Slot &sl, std::unique_lock<std::mutex> &lk);
-    bool reap(Slot &sl, bool wait, std::unique_lock<std::mutex> &lk);
+    bool reap(Slot &sl);
     void settle_locked(Slot &sl);
     void scatter_run();
     void finish_locked(Request *r, int status);
@@ -415,14 +415,12 @@ void sa_server::echo_execute(Slot &sl) {
         }
 }
 
-// Collect a finished batch: scatter results (with the lock released: the
-// owners' output arrays stay valid while their requests are pending),
-// then finish complete requests.
-bool sa_server::reap(Slot &sl, bool wait, std::unique_lock<std::mutex> &lk) {
-    (void)lk;
+// Collect a finished batch: hand it to the scatter thread (or, for a
+// failed batch, settle it here at once).
+bool sa_server::reap(Slot &sl) {
     if (!sl.busy || sl.scattering) return false;
     if (!o.test_echo && sl.error == SA_OK) {
-        hipError_t e = wait ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
+        hipError_t e = hipEventQuery(sl.done);
         if (e == hipErrorNotReady) return false;
         if (e != hipSuccess) sl.error = hip_fail(e, "batch execution");
     } else if (o.test_echo && sl.error == SA_OK) {
@@ -489,7 +487,7 @@ void sa_server::run() {
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         bool progress = false;
-        for (Slot &sl : slots) progress |= reap(sl, false, lk);
+        for (Slot &sl : slots) progress |= reap(sl);
         if (!stop) {
             progress |= admit_locked();
             (void)upload_locked();
