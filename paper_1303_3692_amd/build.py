@@ -41,10 +41,11 @@ def hipcc() -> str:
 
 
 def build_id() -> str:
-    """Hash of the sources: tuned launch settings are only reused for the same kernels."""
+    """Hash of the sources of the tuned pipeline (kernels, batch enqueue,
+    tuner): tuned launch settings are only reused for the same kernels."""
     import hashlib
     h = hashlib.sha256()
-    for s in SOURCES + ["kernels.h", "radix_sort.h", "device_state.h", "internal.h"]:
+    for s in ["kernels.hip", "kernels.h", "radix_sort.h", "device.hip", "device_state.h", "tune.hip"]:
         h.update(open(os.path.join(CSRC, s), "rb").read())
     return h.hexdigest()[:12]
 
