@@ -351,7 +351,7 @@ bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
         ~Relock() { l.lock(); }
     } relock{lk};
     // the pieces, expanded on the device into each read's start and end
-    // (relative to the arena) once the reads' upload is done
+    // (relative to the arena base), after any arena uploads of this round
     const int npieces = (int)sl.pieces.size();
     for (int i = 0; i < npieces; i++) {
         const Piece &p = sl.pieces[(size_t)i];
