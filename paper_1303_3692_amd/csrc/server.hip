@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "device_state.h"
+#include "kernels.h"
 
 using namespace samatch;
 
@@ -377,10 +378,18 @@ bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
     sa_dindex *d = refs[(size_t)ref];
     Workspace *ws = workspace_for(d, sl.stream);
     int rc;
+    // the reads come over the bus from the pinned pool: the search kernel
+    // packs them itself (coalesced, with the next chunk's loads in flight),
+    // under the deepest LDS tile that leaves room for its packing areas
+    sa_match_cfg c = resolve_cfg(d, nullptr);
+    if (c.kernel == SA_KERNEL_TUNED) {
+        c.sort = 0;
+        c.inline_pack = 1;
+        while (c.tile_levels > 1 && tuned_lds_bytes(c.tile_levels, c.block, true) > inline_lds_limit()) c.tile_levels--;
+    }
     {
         std::lock_guard<std::mutex> wl(ws->mu);
-        rc = enqueue_batch(d, ws, d_arena, sl.d_se, sl.d_se + o.max_batch_reads, rows, sl.d_out, sl.stream,
-                           resolve_cfg(d, nullptr));
+        rc = enqueue_batch(d, ws, d_arena, sl.d_se, sl.d_se + o.max_batch_reads, rows, sl.d_out, sl.stream, c);
     }
     if (rc) {
         sl.error = rc;
