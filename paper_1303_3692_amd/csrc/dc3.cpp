@@ -1,14 +1,26 @@
-// DC3 (difference cover modulo 3, "skew") suffix array construction of
-// Section III: (1) sort the suffixes starting at i mod 3 != 0 by their
-// first three symbols, naming the triples and recursing when names repeat;
-// (2) sort the suffixes at i mod 3 == 0 by (first symbol, rank of the
-// suffix one position later); (3) merge the two lists, comparing a sample
-// suffix i with a non-sample suffix j by (t_i, rank(i+1)) against
-// (t_j, rank(j+1)) when i mod 3 == 1, and by (t_i, t_{i+1}, rank(i+2))
-// against (t_j, t_{j+1}, rank(j+2)) when i mod 3 == 2.  Linear time.
+// Suffix array by difference cover modulo 3 (Section III), in three steps:
 //
-// Symbol 0 is the terminator below every base, so a suffix that is a
-// proper prefix of another sorts first.
+//   1. the sample suffixes S_i, i mod 3 != 0, are ranked among themselves:
+//      radix-sorted by their first three symbols, and where two triples tie,
+//      ranked through the suffix array of a reduced string whose symbols are
+//      the triples' names (the recursion of the method);
+//   2. the other suffixes (i mod 3 == 0) are radix-sorted by the pair
+//      (first symbol, rank of S_{i+1});
+//   3. the two sorted lists are merged, comparing a sample suffix with a
+//      non-sample one by the tuples of Section III: (t_i, rank(S_{i+1})) for
+//      i mod 3 == 1, (t_i, t_{i+1}, rank(S_{i+2})) for i mod 3 == 2.
+//
+// Layout: one array of ranks indexed by text position (0 for the empty
+// suffix at and past the end), so that every comparison of steps 2 and 3
+// reads a rank by position.  The reduced string of step 1 puts the names of
+// the positions i mod 3 == 1 first, then one separator symbol smaller than
+// every name, then the names of the positions i mod 3 == 2.  The separator
+// ends the first half: a sample suffix whose triples run out before the
+// text does (its last triple ends exactly at the end) then sorts below a
+// longer one with the same triples, as the text's suffixes do.
+//
+// Symbols are 1..K; 0 stands for "past the end" and sorts below every
+// symbol, so a suffix that is a proper prefix of another sorts first.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -18,106 +30,110 @@
 namespace samatch {
 namespace {
 
-// Stable counting sort of the indices src[0..cnt) by key[src[i]] into dst.
-void radix_pass(const int32_t *src, int32_t *dst, const int32_t *key, int64_t cnt, int32_t K,
-                std::vector<int64_t> &bucket) {
-    bucket.assign((size_t)K + 2, 0);
-    for (int64_t i = 0; i < cnt; i++) bucket[(size_t)key[src[i]] + 1]++;
-    for (int32_t k = 1; k <= K + 1; k++) bucket[k] += bucket[k - 1];
-    for (int64_t i = 0; i < cnt; i++) dst[bucket[(size_t)key[src[i]]]++] = src[i];
+using Positions = std::vector<int32_t>;
+
+// Stable counting sort of `items` by key(item) in 0..kmax.
+template <class Key>
+Positions counting_sort(const Positions &items, int64_t kmax, Key key) {
+    std::vector<int64_t> start((size_t)kmax + 2, 0);
+    for (int32_t it : items) start[(size_t)key(it) + 1]++;
+    for (size_t v = 1; v < start.size(); v++) start[v] += start[v - 1];
+    Positions out(items.size());
+    for (int32_t it : items) out[(size_t)start[(size_t)key(it)]++] = it;
+    return out;
 }
 
-inline bool pair_leq(int32_t a1, int32_t a2, int32_t b1, int32_t b2) {
-    return a1 < b1 || (a1 == b1 && a2 <= b2);
+// Suffix array of a short string by direct comparison of its suffixes.
+void sort_directly(const int32_t *s, int64_t n, int32_t *sa) {
+    for (int64_t i = 0; i < n; i++) sa[i] = (int32_t)i;
+    std::sort(sa, sa + n, [&](int32_t a, int32_t b) {
+        return std::lexicographical_compare(s + a, s + n, s + b, s + n);
+    });
 }
-inline bool triple_leq(int32_t a1, int32_t a2, int32_t a3, int32_t b1, int32_t b2, int32_t b3) {
-    return a1 < b1 || (a1 == b1 && pair_leq(a2, a3, b2, b3));
-}
 
-void skew(const int32_t *s, int32_t *sa, int64_t n, int32_t K) {
-    if (n == 1) { sa[0] = 0; return; }
-    // counts of positions with i mod 3 == 0, 1, 2
-    const int64_t n0 = (n + 2) / 3, n1 = (n + 1) / 3, n2 = n / 3;
-    // When n mod 3 == 1 a dummy sample position n (all-terminator triple) is
-    // added to the mod-1 group so that the two groups join correctly.
-    const int64_t n02 = n0 + n2;
-    std::vector<int32_t> s12((size_t)n02 + 3, 0), sa12((size_t)n02 + 3, 0);
-    std::vector<int64_t> bucket;
+void construct(const int32_t *s, int64_t n, int32_t K, int32_t *sa) {
+    if (n < 16) {
+        sort_directly(s, n, sa);
+        return;
+    }
+    auto sym = [&](int64_t i) -> int64_t { return i < n ? s[i] : 0; };
 
-    int64_t j = 0;
-    for (int64_t i = 0; i < n + (n0 - n1); i++)
-        if (i % 3 != 0) s12[j++] = (int32_t)i;
+    // ---- step 1: rank the sample suffixes
+    Positions sample;
+    sample.reserve((size_t)(n - (n + 2) / 3));
+    for (int64_t i = 1; i < n; i++)
+        if (i % 3 != 0) sample.push_back((int32_t)i);
+    // by the third symbol, then the second, then the first (stable passes)
+    Positions by_triple = counting_sort(sample, K, [&](int32_t i) { return sym(i + 2); });
+    by_triple = counting_sort(by_triple, K, [&](int32_t i) { return sym(i + 1); });
+    by_triple = counting_sort(by_triple, K, [&](int32_t i) { return sym(i); });
 
-    // Step 1: sort sample positions by their triples (least significant first).
-    radix_pass(s12.data(), sa12.data(), s + 2, n02, K, bucket);
-    radix_pass(sa12.data(), s12.data(), s + 1, n02, K, bucket);
-    radix_pass(s12.data(), sa12.data(), s, n02, K, bucket);
-
-    // Name the triples in sorted order; equal triples share a name.
-    int32_t name = 0, c0 = -1, c1 = -1, c2 = -1;
-    for (int64_t i = 0; i < n02; i++) {
-        const int32_t p = sa12[i];
-        if (s[p] != c0 || s[p + 1] != c1 || s[p + 2] != c2) {
-            name++;
-            c0 = s[p]; c1 = s[p + 1]; c2 = s[p + 2];
-        }
-        // mod-1 names first, then mod-2 names: the reduced string R1 R2
-        if (p % 3 == 1) s12[p / 3] = name;
-        else s12[p / 3 + n0] = name;
+    // names: 2, 3, ... in triple order, equal triples alike (1 is the
+    // separator of the reduced string)
+    std::vector<int32_t> name((size_t)n + 3, 0);
+    int32_t next_name = 1;
+    for (size_t r = 0; r < by_triple.size(); r++) {
+        const int32_t i = by_triple[r];
+        const bool same = r > 0 && sym(i) == sym(by_triple[r - 1]) && sym(i + 1) == sym(by_triple[r - 1] + 1) &&
+                          sym(i + 2) == sym(by_triple[r - 1] + 2);
+        if (!same) next_name++;
+        name[(size_t)i] = next_name;
     }
 
-    if (name < n02) {
-        // names repeat: sort the reduced string recursively
-        skew(s12.data(), sa12.data(), n02, name);
-        for (int64_t i = 0; i < n02; i++) s12[sa12[i]] = (int32_t)(i + 1);
+    // rank[i]: 1-based rank of S_i among the sample suffixes; 0 at and past
+    // the end (the empty suffix, below everything)
+    std::vector<int32_t> rank((size_t)n + 3, 0);
+    Positions sample_sorted;
+    if ((size_t)(next_name - 1) == sample.size()) {
+        sample_sorted = by_triple;  // all triples distinct: their order is the suffixes' order
     } else {
-        for (int64_t i = 0; i < n02; i++) sa12[s12[i] - 1] = (int32_t)i;
+        std::vector<int32_t> reduced;
+        reduced.reserve(sample.size() + 1);
+        Positions back;  // text position of each reduced-string position (-1: separator)
+        back.reserve(sample.size() + 1);
+        for (int64_t i = 1; i < n; i += 3) {
+            reduced.push_back(name[(size_t)i]);
+            back.push_back((int32_t)i);
+        }
+        reduced.push_back(1);
+        back.push_back(-1);
+        for (int64_t i = 2; i < n; i += 3) {
+            reduced.push_back(name[(size_t)i]);
+            back.push_back((int32_t)i);
+        }
+        std::vector<int32_t> rsa(reduced.size());
+        construct(reduced.data(), (int64_t)reduced.size(), next_name, rsa.data());
+        sample_sorted.reserve(sample.size());
+        for (int32_t r : rsa)
+            if (back[(size_t)r] >= 0) sample_sorted.push_back(back[(size_t)r]);
     }
+    for (size_t r = 0; r < sample_sorted.size(); r++) rank[(size_t)sample_sorted[r]] = (int32_t)(r + 1);
 
-    // Step 2: the mod-0 suffixes, ordered by (first symbol, rank of i+1).
-    // The sample order already sorts them by the rank of i+1; one stable
-    // pass on the first symbol finishes the job.
-    std::vector<int32_t> s0((size_t)n0), sa0((size_t)n0);
-    j = 0;
-    for (int64_t i = 0; i < n02; i++)
-        if (sa12[i] < n0) s0[j++] = 3 * sa12[i];
-    radix_pass(s0.data(), sa0.data(), s, n0, K, bucket);
+    // ---- step 2: the suffixes at i mod 3 == 0 by (t_i, rank(S_{i+1}))
+    Positions others;
+    others.reserve((size_t)((n + 2) / 3));
+    for (int64_t i = 0; i < n; i += 3) others.push_back((int32_t)i);
+    const int64_t max_rank = (int64_t)sample_sorted.size();
+    others = counting_sort(others, max_rank, [&](int32_t i) { return (int64_t)rank[(size_t)i + 1]; });
+    others = counting_sort(others, K, [&](int32_t i) { return sym(i); });
 
-    // Step 3: merge.  The rank of sample position i is s12[i/3] when
-    // i mod 3 == 1 and s12[i/3 + n0] when i mod 3 == 2 (0 past the end).
-    auto pos12 = [&](int64_t t) -> int64_t {
-        return sa12[t] < n0 ? (int64_t)sa12[t] * 3 + 1 : ((int64_t)sa12[t] - n0) * 3 + 2;
+    // ---- step 3: merge, comparing across the lists by Section III's tuples
+    auto sample_below = [&](int32_t i, int32_t j) {  // S_i < S_j, i a sample position, j not
+        if (sym(i) != sym(j)) return sym(i) < sym(j);
+        if (i % 3 == 1) return rank[(size_t)i + 1] < rank[(size_t)j + 1];
+        if (sym(i + 1) != sym(j + 1)) return sym(i + 1) < sym(j + 1);
+        return rank[(size_t)i + 2] < rank[(size_t)j + 2];
     };
-    int64_t p = 0, t = n0 - n1, k = 0;  // skip the dummy sample suffix
-    while (k < n) {
-        const int64_t i = pos12(t);
-        const int64_t jj = sa0[p];
-        bool sample_first;
-        if (sa12[t] < n0) {  // i mod 3 == 1
-            sample_first = pair_leq(s[i], s12[sa12[t] + n0], s[jj], s12[jj / 3]);
-        } else {             // i mod 3 == 2
-            sample_first = triple_leq(s[i], s[i + 1], s12[sa12[t] - n0 + 1],
-                                      s[jj], s[jj + 1], s12[jj / 3 + n0]);
-        }
-        if (sample_first) {
-            sa[k++] = (int32_t)i;
-            if (++t == n02) {
-                while (p < n0) sa[k++] = sa0[p++];
-            }
-        } else {
-            sa[k++] = (int32_t)jj;
-            if (++p == n0) {
-                while (t < n02) sa[k++] = (int32_t)pos12(t++);
-            }
-        }
-    }
+    // std::merge takes from the second list when comp(second, first) holds
+    std::merge(sample_sorted.begin(), sample_sorted.end(), others.begin(), others.end(), sa,
+               [&](int32_t j_other, int32_t i_sample) { return !sample_below(i_sample, j_other); });
 }
 
 }  // namespace
 
 void dc3_suffix_array(const int32_t *s, int32_t *sa, int64_t n, int32_t K) {
     if (n <= 0) return;
-    skew(s, sa, n, K);
+    construct(s, n, K, sa);
 }
 
 }  // namespace samatch

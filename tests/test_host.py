@@ -60,6 +60,20 @@ def test_dc3_repetitive_texts():
         assert (S.sa_build(t).suffix_array() == oracle.sa_build(t)).all()
 
 
+def test_dc3_every_length_residue():
+    """Texts of 16-400 bases over one to four letters, every length residue
+    mod 3 (the sample and non-sample groups end differently), periodic and
+    random: the recursion on tied triples runs several levels deep."""
+    rng = np.random.default_rng(5)
+    for n in list(range(16, 80)) + [97, 128, 129, 130, 255, 256, 257, 400]:
+        for letters in ("A", "AC", "ACG", "ACGT"):
+            t = "".join(rng.choice(list(letters), size=n))
+            assert (S.sa_build(t).suffix_array() == oracle.sa_build(t)).all(), (n, letters)
+        period = "".join(rng.choice(list("ACGT"), size=int(rng.integers(1, 6))))
+        t = (period * n)[:n]
+        assert (S.sa_build(t).suffix_array() == oracle.sa_build(t)).all(), (n, period)
+
+
 @pytest.mark.parametrize("cfg,n", [("c1", 300_000), ("c2", 1_000_000), ("c4", 600_000)])
 def test_dc3_generated_references(cfg, n):
     t = gen.make_reference(cfg, n=n).ascii()
