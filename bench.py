@@ -2,13 +2,19 @@
 """Benchmark of the suffix-array matching path on one MI355X.
 
 One step = the whole device path over one batch already resident in HBM:
-pack the ASCII reads to 2-bit words, sort them by prefix, run the search
-kernel (LB search with the LDS tile, RB search or longest-matched-prefix
-searches), scatter the 16-byte results in input order.
+pack the ASCII reads to 2-bit words (sort them by prefix when the launch
+settings say so), run the search kernel (prefix-table bracket or LDS tile,
+LB search, RB search or longest-matched-prefix searches), store the 16-byte
+results in input order.
 
-Default workload (c2): a 16 Mbp order-3 Markov reference (GC 0.41) with 5 %
-tandem repeats, and 4,000,000 reads of 100 bp (70 % sampled from the
-reference with 0-2 % substitutions, 30 % random), all synthetic and seeded.
+Default workload (c4, the largest single-GPU one): a 250 Mbp order-3 Markov
+reference with 10 % interspersed repeats (copies of twenty 300 bp elements
+at 10 % divergence), and 64,000,000 reads of 150 bp (80 % sampled from the
+reference at 1 % substitutions, 20 % random), all synthetic and seeded.
+
+The timed steps write into a result buffer filled with a sentinel first, and
+their output is compared with the instrumented run's and with the oracle's
+on the CPU sample, so a timed kernel that skipped work would fail the run.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -55,7 +61,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--config", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-tune", action="store_true", help="use the built-in launch defaults")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
@@ -194,23 +200,41 @@ def main():
         return (c.kernel == S.SA_KERNEL_TUNED and c.inline_pack == 1 and c.sort == 0 and
                 ((tile + 15) // 16 * 16 + (c.block // 64) * 4640) <= 160 * 1024 - 256)
 
-    def alg_bytes(cnt, c):
-        # per read: its input (the ASCII bytes and an 8-byte offset when the
-        # search kernel packs it, else the 2-bit packed words) + the 16-byte
-        # result; per global probe: a 4-byte SA entry plus the 8-byte words
-        # it compares (row keys and text words)
-        read_bytes = int(lens.sum()) + 8 * N if packs_inline(c) else int(((lens + 3) // 4).sum())
-        return read_bytes + 16 * N + 4 * cnt["global_probes"] + 8 * (cnt["text_words"] + cnt["key_words"])
+    packed_bytes = int(((lens + 3) // 4).sum())
+    ascii_bytes = int(lens.sum()) + 8 * N
+
+    def probe_bytes(cnt):
+        # per global probe a 4-byte SA entry plus the 8-byte words it
+        # compares (row-record words and text words); per prefix-table
+        # lookup its two 4-byte entries
+        return 4 * cnt["global_probes"] + 8 * (cnt["text_words"] + cnt["key_words"]) + 8 * cnt["table_lookups"]
+
+    def alg_bytes(cnt, c, ingest=False):
+        # per read: the 2-bit packed read (ceil(m/4) bytes) + the 16-byte
+        # result + its probes.  ingest=True counts instead what the fused
+        # kernel reads as input: the ASCII bytes and an 8-byte offset
+        read_bytes = ascii_bytes if (ingest and packs_inline(c)) else packed_bytes
+        return read_bytes + 16 * N + probe_bytes(cnt)
+
+    SENTINEL = -7
+
+    def timed_output(c, k):
+        # fill the results with a sentinel outside the timed region, run k
+        # steps, and return the elapsed time and what the timed steps wrote
+        d_out.fill_(SENTINEL)
+        el = run_steps(c, k)
+        res = d_out.cpu().numpy()
+        assert (res[:, 0] != SENTINEL).all() and (res[:, 3] != SENTINEL).all(), "timed steps left results unwritten"
+        return el, res
 
     # ---- tuned path
     cnt = counts(cfg)
-    check = d_out.clone()
+    check = d_out.cpu().numpy()
     run_steps(cfg, args.warmup)
-    elapsed = run_steps(cfg, args.steps)
+    elapsed, out = timed_output(cfg, args.steps)
     ms_step = 1000.0 * elapsed / args.steps
+    assert (out == check).all(), "instrumented and timed runs disagree"
     stages = stage_times(cfg, max(3, min(args.steps, 10)))
-    out = d_out.cpu().numpy()
-    assert (out == check.cpu().numpy()).all(), "counting and timed runs disagree"
     matched = int(out[:, 2].astype(np.int64).sum())
     exact = float((out[:, 3] & 1).mean())
     log(f"tuned: {ms_step:.3f} ms/step, stages {stages}")
@@ -222,11 +246,10 @@ def main():
         pcnt = counts(pc)
         run_steps(pc, 1)
         pk = max(2, args.steps // 4)
-        pel = run_steps(pc, pk)
-        pst = stage_times(pc, 3)
-        pout = d_out.cpu().numpy()
+        pel, pout = timed_output(pc, pk)
         assert (pout[:, :3] == out[:, :3]).all() and ((pout[:, 3] & 1) == (out[:, 3] & 1)).all(), \
             "plain and tuned kernels disagree"
+        pst = stage_times(pc, 3)
         plain = {"reads_per_s": N * pk / pel, "ms_per_step": 1000.0 * pel / pk, "search_ms": pst["search"],
                  "global_probes_per_read": pcnt["global_probes"] / N,
                  "alg_bytes_per_read": alg_bytes(pcnt, pc) / N,
@@ -288,28 +311,33 @@ def main():
     del loc_offs, loc_pos
 
     B = alg_bytes(cnt, cfg)
+    B_ingest = alg_bytes(cnt, cfg, ingest=True)
     achieved = B / (stages["search"] * 1e-3) / 1e9
-    # HBM traffic per launch from the committed rocprofv3 counters, only when
-    # they were taken on these kernel sources and this workload
-    traffic = None
+    # HBM traffic per launch and the L2 hit rate from the committed
+    # rocprofv3 counters, only when they were taken on these kernel sources
+    # and this workload
+    traffic, l2_hit = None, None
     counters = os.path.join(ROOT, "profiles", f"search_tuned_{args.config}_counters.json")
     if os.path.exists(counters):
         prof = json.load(open(counters))
         if prof.get("kernel_src") == kernel_source_hash() and prof.get("workload") == args.config:
             traffic = round(prof["traffic_bytes"])
+            l2_hit = prof.get("l2_hit_rate")
     touched = cnt["touched_bytes"]
-    # the search's scattered accesses (64-byte segments touched, less the
-    # coalesced input and results) against the rate this device serves
-    # random 16-byte loads from a table the size of the row records
-    coalesced = B - (4 * cnt["global_probes"] + 8 * (cnt["text_words"] + cnt["key_words"]))
-    scattered = max(0, touched - coalesced) / 64
+    # the search's scattered accesses (64-byte segments of the index its
+    # loads address) against the rate this device serves random 16-byte
+    # loads from a table the size of the row records
+    scattered = cnt["index_segments"]
     ceiling = S.sa_random_read_rate(0, max(8, min(28, int(np.ceil(np.log2(max(2, len(d))))))))
     scattered_rate = scattered / (stages["search"] * 1e-3)
     log(f"random 16-byte loads: {ceiling / 1e9:.1f} G/s; search scattered segments {scattered_rate / 1e9:.1f} G/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "l2_hit_rate": l2_hit,
                 "kernel": "search_tuned_kernel", "packs_reads": packs_inline(cfg),
                 "alg_bytes_per_launch": B, "alg_bytes_per_read": round(B / N, 2),
+                # the same with the input counted as the fused kernel reads it (ASCII + offsets)
+                "ingest_alg_bytes_per_launch": B_ingest,
+                "frac_ingest_inclusive": round(B_ingest / (stages["search"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
                 "launch_ms": round(stages["search"], 4), "kernel_src": kernel_source_hash(),
                 # bytes touched: 64-byte segments addressed per wave access, counted by the instrumented kernel
                 "touched_bytes_per_launch": touched, "touched_GBps": round(touched / (stages["search"] * 1e-3) / 1e9, 2),
@@ -377,7 +405,11 @@ def main():
         "probes_per_read": {"global": round(cnt["global_probes"] / N, 3), "lds": round(cnt["tile_probes"] / N, 3),
                             "text_words": round(cnt["text_words"] / N, 3), "key_words": round(cnt["key_words"] / N, 3),
                             "table_lookups": round(cnt["table_lookups"] / N, 3),
-                            "touched_bytes": round(cnt["touched_bytes"] / N, 1)},
+                            "touched_bytes": round(cnt["touched_bytes"] / N, 1),
+                            # memory requests of the searches: 64-byte segments of the index that the
+                            # wave's loads address (scattered), and index loads issued per lane
+                            "index_segments": round(cnt["index_segments"] / N, 3),
+                            "index_loads": round(cnt["index_loads"] / N, 3)},
         "index": {"device_build_s": round(t_index, 3), "sort_rounds": built["steps"],
                   "sorted_pairs": built["sorted_pairs"]},
         "plain": plain,

@@ -205,9 +205,12 @@ int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]);
  * row records (the first 32 bases of each probe included), c[6]
  * prefix-table lookups (two adjacent 4-byte entries each), c[7] bytes
  * touched by the search kernels: for every global load or store of a wave,
- * the distinct 64-byte segments its active lanes address, times 64.
+ * the distinct 64-byte segments its active lanes address, times 64; c[8]
+ * the part of c[7] / 64 that the loads from the index make (prefix table,
+ * row records, suffix array, text: scattered addresses), the memory
+ * requests of the searches; c[9] those index loads counted per lane.
  * Waits for that batch. */
-int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[8]);
+int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[10]);
 
 /* Measurement helper, not part of the matching path: the rate (loads per
  * second, into *loads_per_s) at which the device serves random 16-byte
@@ -224,9 +227,21 @@ int sa_random_read_rate(int device, int log2_entries, double *loads_per_s);
  * the index's default, and return it in best (nullable).  best_ms receives
  * its time per batch (nullable).  If cache_path is non-NULL the result is
  * read from / appended to that JSON-lines file keyed by (device name, n,
- * length histogram). */
+ * length histogram).  Every candidate's results are compared on the device
+ * with the first candidate's; a difference fails the call (SA_EDEVICE). */
 int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_offs, int64_t nreads,
             void *hip_stream, const char *cache_path, sa_match_cfg *best, double *best_ms);
+
+/* The configurations sa_tune would time on a batch with these offsets:
+ * every tile depth and workgroup shape of its first stage, then the
+ * variants of its later stages (work-split block size, search start, sort
+ * width, packing pass, bucket layouts) taken around `around` (NULL: the
+ * index's current defaults; bucket layouts as if sorted).  Each one must
+ * give the same results (the intervals of Section IV are unique), which
+ * the parity tests check.  Writes min(*count, capacity) of them to out;
+ * *count receives the total. */
+int sa_tune_candidates(const sa_dindex *d, const int64_t *d_offs, int64_t nreads, void *hip_stream,
+                       const sa_match_cfg *around, sa_match_cfg *out, int capacity, int *count);
 
 /* ------------------------------------------------------------------ locate */
 

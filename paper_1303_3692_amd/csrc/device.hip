@@ -378,7 +378,7 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
     }
     if (k > 0) {
         const size_t entries = ((size_t)1 << (2 * k)) + 1;
-        if ((e = hipMalloc((void **)&d->d_ptab, entries * sizeof(uint32_t))) != hipSuccess)
+        if ((e = hipMalloc((void **)&d->d_ptab, entries * sizeof(PrefixEntry))) != hipSuccess)
             return hip_fail(e, "prefix table allocation");
         v.ptab = d->d_ptab;
         v.ptab_k = k;
@@ -626,7 +626,7 @@ extern "C" int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]
     return SA_OK;
 }
 
-extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[8]) {
+extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[10]) {
     clear_error();
     if (!d || !c) return fail(SA_EINVAL, "NULL argument");
     DeviceGuard g(d->device);
@@ -634,10 +634,10 @@ extern "C" int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[8
     if (!ws) return fail(SA_EINVAL, "no batch on this stream");
     std::lock_guard<std::mutex> lk(ws->mu);
     if (!ws->counted) return fail(SA_EINVAL, "the last batch on this stream was not counted");
-    unsigned long long h[8];
+    unsigned long long h[10];
     hipError_t e = hipMemcpyAsync(h, ws->b.stats, sizeof h, hipMemcpyDeviceToHost, static_cast<hipStream_t>(hip_stream));
     if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "counter download");
-    for (int i = 0; i < 8; i++) c[i] = (int64_t)h[i];
+    for (int i = 0; i < 10; i++) c[i] = (int64_t)h[i];
     return SA_OK;
 }

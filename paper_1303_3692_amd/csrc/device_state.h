@@ -101,7 +101,7 @@ struct sa_dindex {
     uint64_t *d_tile_key = nullptr;
     int32_t *d_tile_sa = nullptr;
     samatch::RowRec *d_rows = nullptr;
-    uint32_t *d_ptab = nullptr;
+    samatch::PrefixEntry *d_ptab = nullptr;
     int tile_levels = 0;  // levels stored (the kernel may use fewer)
     samatch::SaBuildInfo built{};  // when the suffix array was built on the device
     samatch::DevIndex view{};

@@ -11,8 +11,8 @@ namespace samatch {
 constexpr int kWMax = 10;                 // packed words per read slot of the short-read path
 constexpr int kShortMax = kWMax * 32;     // longest read of the short-read path (320 bases)
 constexpr int kLongWords = SA_MAX_READ / 32;  // words of a read on the long-read path
-constexpr int kStatWords = 9;
-constexpr int kLongFlag = 8;
+constexpr int kStatWords = 11;
+constexpr int kLongFlag = 10;
 constexpr int kMaxTileLevels = 13;        // 8191 nodes x 12 B = 96 KiB of LDS
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS of a gfx950 compute unit
 constexpr int kInlineVec = 768;           // 16-byte pieces of ASCII a wave packs in the search kernel (12 KB)
@@ -48,6 +48,17 @@ struct alignas(16) StNode {
     int32_t child[4];
 };
 
+// Prefix-table entry of a k-base string v: T[v], the first SA row whose
+// suffix is not below v, then the text position and first 32 bases of the
+// suffix at the first pivot row of the search bracket (T[v] - 1, T[v+1]),
+// or at row T[v] when the bracket is empty (pos = -1 when that row is n).
+// One 16-byte load answers the lookup and the bracket's first probe.
+struct alignas(16) PrefixEntry {
+    uint32_t row;
+    int32_t pos;
+    uint64_t key0;
+};
+
 // Device view of a resident index, passed to kernels by value.
 struct DevIndex {
     const uint64_t *text;      // packed text, 2 bits per base, zero padded
@@ -55,7 +66,7 @@ struct DevIndex {
     const uint64_t *tile_key;  // first 32 bases of the pivot suffix of each tree node
     const int32_t *tile_sa;    // text position of each tree node's pivot suffix
     const RowRec *rows;        // one record per SA row
-    const uint32_t *ptab;      // prefix table, 4^ptab_k + 1 entries (NULL when ptab_k == 0)
+    const PrefixEntry *ptab;   // prefix table, 4^ptab_k + 1 entries (NULL when ptab_k == 0)
     int32_t n;
     int32_t ptab_k;            // bases indexed by the prefix table (0: no table)
     // the rows of the kShort shortest suffixes (lengths 1..kShort), ascending
@@ -82,7 +93,7 @@ struct BatchBuffers {
     uint32_t *val[2];    // read ids (ping-pong)
     uint32_t *hist;      // 256 * sort blocks
     uint32_t *digit_total;  // 256
-    unsigned long long *stats;  // kStatWords words zeroed by pack: 8 counters of the instrumented
+    unsigned long long *stats;  // kStatWords words zeroed by pack: 10 counters of the instrumented
                                 // search, then kLongFlag (set when a batch holds a long read)
 };
 
@@ -92,8 +103,9 @@ hipError_t prepare_kernels();
 
 hipError_t launch_build_rows(const uint64_t *text, const int32_t *sa, int32_t n, RowRec *rows, hipStream_t s);
 
-// T[v] = first SA row whose suffix is not below the k-base string v.
-hipError_t launch_build_prefix_table(const DevIndex &ix, int k, uint32_t *tab, hipStream_t s);
+// Fills the 4^k + 1 entries of a prefix table (see PrefixEntry); ix.rows
+// must hold the row records.
+hipError_t launch_build_prefix_table(const DevIndex &ix, int k, PrefixEntry *tab, hipStream_t s);
 
 hipError_t launch_build_tile(const uint64_t *text, const int32_t *sa, int32_t n, int levels,
                              uint64_t *key, int32_t *tsa, hipStream_t s);

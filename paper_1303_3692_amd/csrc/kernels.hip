@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "pivot.h"
 #include "radix_sort.h"
 
 namespace samatch {
@@ -42,14 +43,24 @@ struct NoCount {
     __device__ __forceinline__ void text_words(uint32_t, uint32_t) {}
     __device__ __forceinline__ void rec_word() {}
     __device__ __forceinline__ void touch(const void *, int) {}
+    __device__ __forceinline__ void index_touch(const void *, int) {}
 };
 // touch(p, bytes): one global access of this lane; the 64-byte segments
 // that the wave's active lanes address together are added to `touched`
 // (credited to the first active lane), the bytes-touched measure of a
-// wave instruction.
+// wave instruction.  index_touch: the same for a load from the index
+// (prefix table, row records, suffix array, text), whose addresses are
+// scattered; its segments and the load itself are also counted apart
+// (`scattered`, `index_loads`), the requests a search makes.
 struct Count {
-    uint32_t global = 0, words = 0, tile = 0, keys = 0, table = 0;
-    unsigned long long touched = 0;
+    uint32_t global = 0, words = 0, tile = 0, keys = 0, table = 0, index_loads = 0;
+    unsigned long long touched = 0, scattered = 0;
+    __device__ __forceinline__ void index_touch(const void *p, int bytes) {
+        const unsigned long long before = touched;
+        touch(p, bytes);
+        scattered += (touched - before) >> 6;
+        ++index_loads;
+    }
     __device__ __forceinline__ void touch(const void *p, int bytes) {
         const uint64_t a = (uint64_t)(uintptr_t)p;
         const uint64_t s0 = a >> 6;
@@ -90,10 +101,60 @@ __device__ __forceinline__ uint64_t text_word(const uint64_t *__restrict__ text,
 
 template <class Cnt>
 __device__ __forceinline__ uint64_t text_word(const uint64_t *__restrict__ text, uint32_t b, Cnt &cnt) {
-    cnt.touch(text + (b >> 5), 8);
-    cnt.touch(text + (b >> 5) + 1, 8);
+    cnt.index_touch(text + (b >> 5), 8);
+    cnt.index_touch(text + (b >> 5) + 1, 8);
     return text_word(text, b);
 }
+
+// Two consecutive 64-bit words with one 16-byte load from an address that
+// is only 8-byte aligned (global loads of several dwords need dword
+// alignment on this device).
+typedef uint64_t u64x2_a8 __attribute__((ext_vector_type(2), aligned(8)));
+__device__ __forceinline__ u64x2_a8 load_u64x2(const uint64_t *p) { return *reinterpret_cast<const u64x2_a8 *>(p); }
+
+// Two consecutive 32-bit words with one 8-byte load, 4-byte aligned.
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+__device__ __forceinline__ u32x2_a4 load_u32x2(const uint32_t *p) { return *reinterpret_cast<const u32x2_a4 *>(p); }
+
+// The words of one suffix taken in order: word k (bases p + 32k ..
+// p + 32k + 31) joins text words wi + k and wi + k + 1 (wi = p / 32) by a
+// funnel shift.  Text words come two per 16-byte load and each is loaded
+// once per comparison, so k consecutive suffix words cost 1 + k/2 loads
+// (the text carries zero padding words after its end for the loads past it).
+struct TextRun {
+    const uint64_t *base;  // text + p / 32
+    uint32_t sh;           // 2 * (p % 32)
+    uint64_t a, b, c;      // text words wi + k, wi + k + 1 and, when `spare`, wi + k + 2
+    bool started, spare;
+
+    __device__ __forceinline__ TextRun(const uint64_t *__restrict__ text, uint32_t p)
+        : base(text + (p >> 5)), sh((p & 31u) << 1), a(0), b(0), c(0), started(false), spare(false) {}
+
+    // word k of the suffix; successive calls take successive k
+    template <class Cnt>
+    __device__ __forceinline__ uint64_t word(int k, Cnt &cnt) {
+        if (!started) {
+            const u64x2_a8 v = load_u64x2(base + k);
+            cnt.index_touch(base + k, 16);
+            a = v.x;
+            b = v.y;
+            started = true;
+        } else {
+            a = b;
+            if (spare) {
+                b = c;
+                spare = false;
+            } else {
+                const u64x2_a8 v = load_u64x2(base + k + 1);
+                cnt.index_touch(base + k + 1, 16);
+                b = v.x;
+                c = v.y;
+                spare = true;
+            }
+        }
+        return (a << sh) | ((b >> 1) >> (63u - sh));
+    }
+};
 
 // Compare the query P[0..plen) with the suffix at text position p, skipping
 // the first 32*k0 bases (known to match).  Returns -1 when P sorts before
@@ -161,6 +222,7 @@ __device__ __forceinline__ int compare_row(const DevIndex &ix, const Q &q, int p
     int sign = (lim == plen) ? 0 : 1;
     bool done = false;
     uint32_t text_first = 0, text_end = 0;
+    TextRun run(ix.text, (uint32_t)p);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         if (!done && k >= k0 && (k << 5) < lim) {
@@ -170,9 +232,9 @@ __device__ __forceinline__ int compare_row(const DevIndex &ix, const Q &q, int p
             } else if (rec != nullptr && k < kRecWords) {
                 t = reinterpret_cast<const uint64_t *>(rec)[1 + k];  // word k of the record
                 cnt.rec_word();
-                cnt.touch(reinterpret_cast<const uint64_t *>(rec) + 1 + k, 8);
+                cnt.index_touch(reinterpret_cast<const uint64_t *>(rec) + 1 + k, 8);
             } else {
-                t = text_word(ix.text, (uint32_t)p + ((uint32_t)k << 5), cnt);
+                t = run.word(k, cnt);
                 if (text_end == 0) text_first = (uint32_t)p + ((uint32_t)k << 5);
                 text_end = (uint32_t)p + (uint32_t)min_i(lim, (k << 5) + 32);
             }
@@ -193,10 +255,6 @@ __device__ __forceinline__ int compare_row(const DevIndex &ix, const Q &q, int p
     return sign;
 }
 
-__device__ __forceinline__ int midpoint(int L, int R) {
-    return L + (int)((uint32_t)(R - L) >> 1);
-}
-
 // Binary search over rows (L, R] with known common-prefix lengths at the
 // bounds (lcpL, lcpR, 0 for the open ends).  Every row strictly between
 // them shares min(lcpL, lcpR) leading bases with the query, so each probe
@@ -209,7 +267,7 @@ __device__ __forceinline__ int bounded_search(const DevIndex &ix, const Q &q, in
     while (R > L + 1) {
         const int piv = midpoint(L, R);
         const RowHead row = row_head(ix.rows, piv);
-        cnt.touch(ix.rows + piv, 16);
+        cnt.index_touch(ix.rows + piv, 16);
         int lcp;
         cnt.key_probe();
         const int sign = compare_row<W>(ix, q, plen, ix.rows + piv, row.pos, row.key0, min_i(lcpL, lcpR), lcp, cnt);
@@ -263,7 +321,7 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
     while (st.R > st.L + 1) {
         const int piv = midpoint(st.L, st.R);
         const RowHead row = row_head(ix.rows, piv);
-        cnt.touch(ix.rows + piv, 16);
+        cnt.index_touch(ix.rows + piv, 16);
         int lcp;
         cnt.key_probe();
         const int sign =
@@ -304,35 +362,50 @@ __device__ __forceinline__ int short_at(const DevIndex &ix, int row) {
 // bound inside, the other bound's common-prefix length (below k) never
 // decides anything and starts as 0; when the bracket is empty, both
 // neighbours are probed for their exact common-prefix lengths.
+// The table entry also holds the bracket's first pivot suffix (position
+// and first 32 bases), so the first probe needs no load of its own; for an
+// empty bracket it holds the right neighbour.
 template <int W, class Q, class Cnt>
 __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, int plen, LbState &st,
                                                 Cnt &cnt) {
     const int K = ix.ptab_k;
     const uint32_t v = (uint32_t)(q[0] >> (64 - 2 * K));
-    const int lo_k = (int)ix.ptab[v];
-    const int hi_k = (int)ix.ptab[v + 1];
-    cnt.touch(ix.ptab + v, 8);
+    const PrefixEntry ent = ix.ptab[v];
+    const int hi_k = (int)ix.ptab[v + 1].row;
+    const int lo_k = (int)ent.row;
+    cnt.index_touch(ix.ptab + v, 16);
+    cnt.index_touch(&ix.ptab[v + 1].row, 4);
     cnt.table_probe();
     if (short_rows_in(ix, lo_k, hi_k)) return false;
     st.L = lo_k - 1; st.R = hi_k; st.lcpL = 0; st.lcpR = 0;
     st.Llt = -1; st.lcpLlt = 0; st.Rlt = ix.n; st.lcpRlt = 0;
     if (hi_k == lo_k) {
-        const int rl = st.L >= 0 ? st.L : 0;
-        const int rr = st.R < ix.n ? st.R : ix.n - 1;
-        const RowHead xl = row_head(ix.rows, rl), xr = row_head(ix.rows, rr);
-        cnt.touch(ix.rows + rl, 16);
-        cnt.touch(ix.rows + rr, 16);
         int a = 0, c = 0;
-        if (st.L >= 0) { cnt.key_probe(); compare_row<W>(ix, q, plen, ix.rows + rl, xl.pos, xl.key0, 0, a, cnt); }
-        if (st.R < ix.n) { cnt.key_probe(); compare_row<W>(ix, q, plen, ix.rows + rr, xr.pos, xr.key0, 0, c, cnt); }
+        if (st.L >= 0) {
+            const RowHead xl = row_head(ix.rows, st.L);
+            cnt.index_touch(ix.rows + st.L, 16);
+            cnt.key_probe();
+            compare_row<W>(ix, q, plen, ix.rows + st.L, xl.pos, xl.key0, 0, a, cnt);
+        }
+        if (st.R < ix.n) {
+            cnt.key_probe();
+            compare_row<W>(ix, q, plen, ix.rows + st.R, ent.pos, ent.key0, 0, c, cnt);
+        }
         st.lcpL = a;
         st.lcpR = c;
         return true;
     }
+    {
+        const int piv = midpoint(st.L, st.R);
+        int lcp;
+        cnt.key_probe();
+        const int sign = compare_row<W>(ix, q, plen, ix.rows + piv, ent.pos, ent.key0, 0, lcp, cnt);
+        lb_update(st, sign, piv, lcp);
+    }
     while (st.R > st.L + 1) {
         const int piv = midpoint(st.L, st.R);
         const RowHead row = row_head(ix.rows, piv);
-        cnt.touch(ix.rows + piv, 16);
+        cnt.index_touch(ix.rows + piv, 16);
         int lcp;
         cnt.key_probe();
         const int sign =
@@ -352,10 +425,10 @@ __device__ __forceinline__ void table_interval(const DevIndex &ix, uint64_t q0, 
     const uint32_t u = (uint32_t)(q0 >> (64 - 2 * l));
     const uint32_t ulo = u << (2 * (K - l));
     const uint32_t w = ulo + (1u << (2 * (K - l)));
-    lo = (int)ix.ptab[ulo];
-    hi = (int)ix.ptab[w];
-    cnt.touch(ix.ptab + ulo, 4);
-    cnt.touch(ix.ptab + w, 4);
+    lo = (int)ix.ptab[ulo].row;
+    hi = (int)ix.ptab[w].row;
+    cnt.index_touch(&ix.ptab[ulo].row, 4);
+    cnt.index_touch(&ix.ptab[w].row, 4);
     cnt.table_probe();
     for (;;) {
         const int si = lo > 0 ? short_at(ix, lo - 1) : -1;
@@ -440,7 +513,7 @@ __device__ __forceinline__ uint64_t row_order_key(const DevIndex &ix, int k, int
 }
 
 // T[v] = first row whose order key reaches 2v + 1 (binary search per entry).
-__global__ void build_prefix_table_kernel(DevIndex ix, int k, int64_t entries, uint32_t *__restrict__ tab) {
+__global__ void build_prefix_table_kernel(DevIndex ix, int k, int64_t entries, PrefixEntry *__restrict__ tab) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= entries) return;
     const uint64_t target = 2 * (uint64_t)v + 1;
@@ -450,7 +523,26 @@ __global__ void build_prefix_table_kernel(DevIndex ix, int k, int64_t entries, u
         if (row_order_key(ix, k, mid) >= target) hi = mid;
         else lo = mid + 1;
     }
-    tab[v] = (uint32_t)lo;
+    tab[v].row = (uint32_t)lo;
+}
+
+// Second pass: each entry's first pivot row of its bracket (T[v] - 1,
+// T[v+1]), or T[v] for an empty bracket, and that row's position and first
+// 32 bases from its record.
+__global__ void fill_prefix_pivots_kernel(DevIndex ix, int64_t entries, PrefixEntry *__restrict__ tab) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= entries) return;
+    const int lo = (int)tab[v].row;
+    const int hi = v + 1 < entries ? (int)tab[v + 1].row : lo;
+    const int piv = hi > lo ? midpoint(lo - 1, hi) : lo;
+    if (piv < ix.n) {
+        const RowHead h = row_head(ix.rows, piv);
+        tab[v].pos = h.pos;
+        tab[v].key0 = h.key0;
+    } else {
+        tab[v].pos = -1;
+        tab[v].key0 = 0;
+    }
 }
 
 // ------------------------------------------------------------------ tile
@@ -1123,6 +1215,8 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         wave_add(&b.stats[5], cnt.keys);
         wave_add(&b.stats[6], cnt.table);
         wave_add64(&b.stats[7], cnt.touched);
+        wave_add64(&b.stats[8], cnt.scattered);
+        wave_add(&b.stats[9], cnt.index_loads);
     }
 }
 
@@ -1138,7 +1232,7 @@ __device__ __forceinline__ int plain_search(const DevIndex &ix, const uint64_t (
         const int piv = midpoint(L, R);
         int lcp;
         cnt.global_probe();
-        cnt.touch(ix.sa + piv, 4);
+        cnt.index_touch(ix.sa + piv, 4);
         const int sign = compare_from<kWMax>(ix.text, ix.n, q, plen, ix.sa[piv], 0, lcp, cnt);
         if (UPPER ? (sign < 0) : (sign <= 0)) R = piv; else L = piv;
     }
@@ -1175,13 +1269,13 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
             int l = 0, lcp;
             if (lo > 0) {
                 cnt.global_probe();
-                cnt.touch(ix.sa + lo - 1, 4);
+                cnt.index_touch(ix.sa + lo - 1, 4);
                 compare_from<kWMax>(ix.text, ix.n, q, mv, ix.sa[lo - 1], 0, lcp, cnt);
                 l = max_i(l, lcp);
             }
             if (lo < ix.n) {
                 cnt.global_probe();
-                cnt.touch(ix.sa + lo, 4);
+                cnt.index_touch(ix.sa + lo, 4);
                 compare_from<kWMax>(ix.text, ix.n, q, mv, ix.sa[lo], 0, lcp, cnt);
                 l = max_i(l, lcp);
             }
@@ -1199,6 +1293,8 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
         wave_add(&b.stats[3], m >= 0 && !long_read ? 1u : 0u);
         wave_add(&b.stats[4], m >= 0 && !long_read ? (uint32_t)max_i(1, (m + 31) >> 5) : 0u);
         wave_add64(&b.stats[7], cnt.touched);
+        wave_add64(&b.stats[8], cnt.scattered);
+        wave_add(&b.stats[9], cnt.index_loads);
     }
 }
 
@@ -1404,6 +1500,8 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         wave_add(&b.stats[5], cnt.keys);
         wave_add(&b.stats[6], cnt.table);
         wave_add64(&b.stats[7], cnt.touched);
+        wave_add64(&b.stats[8], cnt.scattered);
+        wave_add(&b.stats[9], cnt.index_loads);
     }
 }
 
@@ -1588,9 +1686,11 @@ hipError_t launch_search_tuned(const DevIndex &ix, int levels, int use_table, in
     }
 }
 
-hipError_t launch_build_prefix_table(const DevIndex &ix, int k, uint32_t *tab, hipStream_t s) {
+hipError_t launch_build_prefix_table(const DevIndex &ix, int k, PrefixEntry *tab, hipStream_t s) {
     const int64_t entries = ((int64_t)1 << (2 * k)) + 1;
     hipLaunchKernelGGL(build_prefix_table_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix, k,
+                       entries, tab);
+    hipLaunchKernelGGL(fill_prefix_pivots_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix,
                        entries, tab);
     return hipGetLastError();
 }

@@ -130,7 +130,132 @@ std::vector<std::vector<int>> bucket_layouts(const std::vector<int64_t> &hist) {
     return out;
 }
 
+// Counts the reads whose 16-byte results differ between a and b.
+__global__ void count_diff_kernel(const int4 *__restrict__ a, const int4 *__restrict__ b, int64_t n,
+                                  unsigned long long *__restrict__ diff) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool d = false;
+    if (i < n) {
+        const int4 x = a[i], y = b[i];
+        d = x.x != y.x || x.y != y.y || x.z != y.z || x.w != y.w;
+    }
+    const unsigned long long m = __ballot(d);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(diff, (unsigned long long)__popcll(m));
+}
+
+// A tuned configuration with the built-in search start, sort and packing.
+sa_match_cfg base_cfg(const sa_dindex *d) {
+    sa_match_cfg c{};
+    c.kernel = SA_KERNEL_TUNED;
+    c.tile_levels = std::min(12, d->tile_levels);
+    c.block = 256;
+    c.blocks_per_cu = 8;
+    c.nbuckets = 1;
+    c.bucket_edge[0] = SA_MAX_READ;
+    c.sort = d->view.ptab_k > 0 ? 0 : 1;
+    c.inline_pack = 1;
+    c.group = 4;
+    c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
+    return c;
+}
+
+// Stage 1: tile depth x workgroup shape.  With the prefix table the tile
+// serves only reads with a non-base among their first k bases, so its depth
+// changes little but the LDS it takes (and with it how many workgroups fit
+// a compute unit): three depths are tried instead of every one.
+std::vector<sa_match_cfg> stage1_candidates(const sa_dindex *d) {
+    std::vector<int> levels;
+    if (d->view.ptab_k > 0) {
+        for (int t : {1, 8, 12})
+            if (t <= d->tile_levels) levels.push_back(t);
+    } else {
+        for (int t = std::min(13, d->tile_levels); t >= std::max(1, std::min(9, d->tile_levels)); t--)
+            levels.push_back(t);
+    }
+    std::vector<sa_match_cfg> out;
+    for (int lv : levels)
+        for (int block : {256, 512, 1024})
+            for (int per_cu : {1, 2, 4, 8}) {
+                if (block * per_cu > 4096) continue;
+                sa_match_cfg c = base_cfg(d);
+                c.tile_levels = lv;
+                c.block = block;
+                c.blocks_per_cu = per_cu;
+                out.push_back(c);
+            }
+    return out;
+}
+
+// Stage 1b, around the best shape: block size of the work split, the search
+// start (prefix table or LDS tile only), the sort width, and packing in the
+// search kernel or in a pass of its own.
+std::vector<sa_match_cfg> stage1b_candidates(const sa_dindex *d, const sa_match_cfg &top) {
+    std::vector<sa_match_cfg> out;
+    for (int g : {1, 2, 8, 16}) {
+        sa_match_cfg c = top;
+        c.group = g;
+        out.push_back(c);
+    }
+    if (d->view.ptab_k > 0) {
+        sa_match_cfg c = top;
+        c.prefix_table = !top.prefix_table;
+        out.push_back(c);
+    }
+    for (int bits : {0, 8, 16, 24}) {
+        sa_match_cfg c = top;
+        c.sort = bits;
+        out.push_back(c);
+    }
+    if (top.sort == 0) {
+        sa_match_cfg c = top;
+        c.inline_pack = !top.inline_pack;
+        out.push_back(c);
+    }
+    return out;
+}
+
+// Stage 2, around the best so far: bucket layouts.  Buckets only order the
+// reads through the sort keys, so they are tried only when the reads are
+// sorted.
+std::vector<sa_match_cfg> stage2_candidates(const sa_match_cfg &top, const std::vector<int64_t> &hist) {
+    std::vector<sa_match_cfg> out;
+    if (top.sort == 0) return out;
+    for (const auto &edges : bucket_layouts(hist)) {
+        if (edges.size() == 1) continue;
+        sa_match_cfg c = top;
+        c.nbuckets = (int)edges.size();
+        for (size_t i = 0; i < edges.size(); i++) c.bucket_edge[i] = edges[i];
+        out.push_back(c);
+    }
+    return out;
+}
+
 }  // namespace
+
+extern "C" int sa_tune_candidates(const sa_dindex *d, const int64_t *d_offs, int64_t nreads, void *hip_stream,
+                                  const sa_match_cfg *around, sa_match_cfg *out, int capacity, int *count) {
+    clear_error();
+    if (!d || !d_offs || nreads < 1 || !count || capacity < 0 || (capacity > 0 && !out))
+        return fail(SA_EINVAL, "bad argument");
+    DeviceGuard g(d->device);
+    if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
+    std::vector<int64_t> hist;
+    int rc = length_histogram(d_offs, nreads, static_cast<hipStream_t>(hip_stream), hist);
+    if (rc) return rc;
+    const sa_match_cfg top = resolve_cfg(d, around);
+    std::vector<sa_match_cfg> all = stage1_candidates(d);
+    for (const auto &c : stage1b_candidates(d, top)) all.push_back(c);
+    sa_match_cfg sorted = top;
+    if (sorted.sort == 0) sorted.sort = 1;
+    for (const auto &c : stage2_candidates(sorted, hist)) all.push_back(c);
+    std::vector<sa_match_cfg> valid;
+    for (const auto &c : all)
+        if (check_cfg(d, c) == SA_OK) valid.push_back(c);
+    clear_error();
+    *count = (int)valid.size();
+    for (int i = 0; i < capacity && i < (int)valid.size(); i++) out[i] = valid[(size_t)i];
+    return SA_OK;
+}
 
 extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_offs, int64_t nreads,
                        void *hip_stream, const char *cache_path, sa_match_cfg *best, double *best_ms) {
@@ -151,20 +276,48 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
         if (best_ms) *best_ms = found_ms;
         return SA_OK;
     }
-    sa_hit *d_out = nullptr;
+    // every candidate's results are compared on the device with the first
+    // one's: results are unique, so a launch setting that changed them would
+    // be a defect, and the tuner fails instead of keeping it
+    sa_hit *d_out = nullptr, *d_ref = nullptr;
+    unsigned long long *d_diff = nullptr;
     hipError_t e = hipMalloc((void **)&d_out, sizeof(sa_hit) * (size_t)nreads);
-    if (e != hipSuccess) return hip_fail(e, "tuner output");
+    if (e == hipSuccess) e = hipMalloc((void **)&d_ref, sizeof(sa_hit) * (size_t)nreads);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_diff, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        (void)hipFree(d_out);
+        (void)hipFree(d_ref);
+        return hip_fail(e, "tuner output");
+    }
     hipEvent_t t0, t1;
     (void)hipEventCreate(&t0);
     (void)hipEventCreate(&t1);
     Workspace *ws = workspace_for(d, s);
     sa_match_cfg top = d->defaults;
     double top_ms = 1e30;
+    bool have_ref = false;
     auto time_cfg = [&](const sa_match_cfg &c, double &ms) -> int {
         if (check_cfg(d, c) != SA_OK) return SA_EINVAL;
         std::lock_guard<std::mutex> lk(ws->mu);
-        int r = enqueue_batch(d, ws, d_reads, d_offs, nullptr, nreads, d_out, s, c);  // warm-up
+        int r = enqueue_batch(d, ws, d_reads, d_offs, nullptr, nreads, have_ref ? d_out : d_ref, s, c);  // warm-up
         if (r) return r;
+        if (have_ref) {
+            unsigned long long diff = 0;
+            hipError_t ee = hipMemsetAsync(d_diff, 0, sizeof diff, s);
+            if (ee == hipSuccess) {
+                hipLaunchKernelGGL(count_diff_kernel, dim3((unsigned)((nreads + 255) / 256)), dim3(256), 0, s,
+                                   reinterpret_cast<const int4 *>(d_out), reinterpret_cast<const int4 *>(d_ref),
+                                   nreads, d_diff);
+                ee = hipGetLastError();
+            }
+            if (ee == hipSuccess) ee = hipMemcpyAsync(&diff, d_diff, sizeof diff, hipMemcpyDeviceToHost, s);
+            if (ee == hipSuccess) ee = hipStreamSynchronize(s);
+            if (ee != hipSuccess) return hip_fail(ee, "tuner check");
+            if (diff)
+                return fail(SA_EDEVICE, "tuner: a candidate configuration gave different results for " +
+                                            std::to_string(diff) + " reads");
+        }
+        have_ref = true;
         float best_rep = 1e30f;
         for (int rep = 0; rep < 3; rep++) {
             (void)hipEventRecord(t0, s);
@@ -185,76 +338,35 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
                          c.nbuckets, ms);
         return SA_OK;
     };
-    // stage 1: tile depth x workgroup shape with one bucket, the search
-    // start, sort and packing of the built-in defaults
-    const int base_sort = d->view.ptab_k > 0 ? 0 : 1;
-    std::vector<int> levels;
-    for (int t = std::min(13, d->tile_levels); t >= std::max(1, std::min(9, d->tile_levels)); t--) levels.push_back(t);
-    for (int lv : levels) {
-        for (int block : {256, 512, 1024}) {
-            for (int per_cu : {1, 2, 4, 8}) {
-                if (block * per_cu > 4096) continue;
-                sa_match_cfg c{};
-                c.kernel = SA_KERNEL_TUNED;
-                c.tile_levels = lv;
-                c.block = block;
-                c.blocks_per_cu = per_cu;
-                c.nbuckets = 1;
-                c.bucket_edge[0] = SA_MAX_READ;
-                c.sort = base_sort;
-                c.inline_pack = 1;
-                c.group = 4;
-                c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
-                double ms = 0;
-                rc = time_cfg(c, ms);
-                if (rc == SA_EINVAL) continue;
-                if (rc) goto done;
-                if (ms < top_ms) { top_ms = ms; top = c; }
-            }
+    auto try_all = [&](const std::vector<sa_match_cfg> &cands) -> int {
+        for (const auto &c : cands) {
+            double ms = 0;
+            const int r = time_cfg(c, ms);
+            if (r == SA_EINVAL) continue;
+            if (r) return r;
+            if (ms < top_ms) { top_ms = ms; top = c; }
+        }
+        return SA_OK;
+    };
+    rc = try_all(stage1_candidates(d));
+    if (rc == SA_OK) rc = try_all(stage1b_candidates(d, top));
+    if (rc == SA_OK) rc = try_all(stage2_candidates(top, hist));
+    if (rc == SA_OK && top_ms >= 1e30) rc = fail(SA_EINVAL, "tuner: no valid candidate");
+    if (rc == SA_OK) {
+        clear_error();
+        d->defaults = top;
+        if (best) *best = top;
+        if (best_ms) *best_ms = top_ms;
+        if (cache_path) {
+            std::ofstream f(cache_path, std::ios::app);
+            if (f) f << "{\"key\":\"" << key << "\"," << cfg_json(top) << ",\"ms\":" << top_ms << "}\n";
         }
     }
-    // stage 1b: block size of the work split with the best shape, the
-    // search start (prefix table or LDS tile only), the sort width, and
-    // packing in the search kernel or in a pass of its own
-    static const int kGroups[4] = {1, 2, 8, 16};
-    static const int kSortBits[4] = {0, 8, 16, 24};
-    for (int variant = 0; variant < 10; variant++) {
-        sa_match_cfg c = top;
-        if (variant < 4) c.group = kGroups[variant];
-        else if (variant == 4 && d->view.ptab_k > 0) c.prefix_table = !top.prefix_table;
-        else if (variant >= 5 && variant < 9) c.sort = kSortBits[variant - 5];
-        else if (variant == 9 && top.sort == 0) c.inline_pack = !top.inline_pack;
-        else continue;
-        double ms = 0;
-        rc = time_cfg(c, ms);
-        if (rc == SA_EINVAL) continue;
-        if (rc) goto done;
-        if (ms < top_ms) { top_ms = ms; top = c; }
-    }
-    // stage 2: bucket layouts with the best shape
-    for (const auto &edges : bucket_layouts(hist)) {
-        if (edges.size() == 1) continue;
-        sa_match_cfg c = top;
-        c.nbuckets = (int)edges.size();
-        for (size_t i = 0; i < edges.size(); i++) c.bucket_edge[i] = edges[i];
-        double ms = 0;
-        rc = time_cfg(c, ms);
-        if (rc == SA_EINVAL) continue;
-        if (rc) goto done;
-        if (ms < top_ms) { top_ms = ms; top = c; }
-    }
-    rc = SA_OK;
-    d->defaults = top;
-    if (best) *best = top;
-    if (best_ms) *best_ms = top_ms;
-    if (cache_path) {
-        std::ofstream f(cache_path, std::ios::app);
-        if (f) f << "{\"key\":\"" << key << "\"," << cfg_json(top) << ",\"ms\":" << top_ms << "}\n";
-    }
-done:
     (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     (void)hipFree(d_out);
+    (void)hipFree(d_ref);
+    (void)hipFree(d_diff);
     return rc;
 }

@@ -25,7 +25,7 @@ EXPORTS = [
     "sa_build", "sa_build_from_sa", "sa_index_length", "sa_index_copy_sa", "sa_save", "sa_load", "sa_free",
     "sa_upload", "sa_dfree", "sa_dindex_length", "sa_build_device", "sa_download", "sa_dindex_build_info",
     "sa_default_cfg", "match_batch", "match_batch_dev",
-    "sa_stage_times", "sa_probe_counts", "sa_tune", "sa_random_read_rate",
+    "sa_stage_times", "sa_probe_counts", "sa_tune", "sa_tune_candidates", "sa_random_read_rate",
     "sa_locate_dev", "sa_locate",
     "st_build", "st_free", "st_node_count", "st_root", "st_copy_nodes", "st_index_bytes", "st_upload", "st_dfree",
     "st_match_batch_dev",
@@ -101,6 +101,7 @@ def lib():
             "sa_probe_counts": ([p, p, ctypes.POINTER(ctypes.c_int64)], i32),
             "sa_random_read_rate": ([i32, i32, ctypes.POINTER(ctypes.c_double)], i32),
             "sa_tune": ([p, p, p, i64, p, ctypes.c_char_p, ctypes.POINTER(MatchCfg), ctypes.POINTER(ctypes.c_double)], i32),
+            "sa_tune_candidates": ([p, p, i64, p, p, p, i32, ctypes.POINTER(ctypes.c_int)], i32),
             "sa_locate_dev": ([p, p, i64, i32, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_int64)], i32),
             "sa_locate": ([p, p, i64, i32, i32, p, p, i64, ctypes.POINTER(ctypes.c_int64)], i32),
             "st_build": ([p, pp], i32),
@@ -316,10 +317,11 @@ def sa_stage_times(d: DIndex, stream=None) -> dict:
 
 def sa_probe_counts(d: DIndex, stream=None) -> dict:
     """Probe counts of the last counted batch on this stream."""
-    c = (ctypes.c_int64 * 8)()
+    c = (ctypes.c_int64 * 10)()
     _check(lib().sa_probe_counts(d.ptr, _stream_handle(stream), c), "sa_probe_counts")
     return {"global_probes": c[0], "text_words": c[1], "tile_probes": c[2], "reads": c[3], "query_words": c[4],
-            "key_words": c[5], "table_lookups": c[6], "touched_bytes": c[7]}
+            "key_words": c[5], "table_lookups": c[6], "touched_bytes": c[7], "index_segments": c[8],
+            "index_loads": c[9]}
 
 
 def sa_random_read_rate(device: int = 0, log2_entries: int = 24) -> float:
@@ -450,6 +452,21 @@ def sa_tune(d: DIndex, d_reads, d_offs, nreads: int | None = None, stream=None, 
                          _stream_handle(stream), cache_path.encode() if cache_path else None, ctypes.byref(best),
                          ctypes.byref(ms)), "sa_tune")
     return best, ms.value
+
+
+def sa_tune_candidates(d: DIndex, d_offs, nreads: int | None = None, stream=None,
+                       around: MatchCfg | None = None) -> list:
+    """The configurations sa_tune would time on a batch with these device
+    offsets (later stages taken around `around`, default the index's
+    defaults)."""
+    n = (d_offs.numel() - 1) if nreads is None else nreads
+    count = ctypes.c_int()
+    args = (d.ptr, ctypes.c_void_p(d_offs.data_ptr()), n, _stream_handle(stream),
+            ctypes.byref(around) if around is not None else None)
+    _check(lib().sa_tune_candidates(*args, None, 0, ctypes.byref(count)), "sa_tune_candidates")
+    out = (MatchCfg * max(1, count.value))()
+    _check(lib().sa_tune_candidates(*args, out, count.value, ctypes.byref(count)), "sa_tune_candidates")
+    return [out[i] for i in range(count.value)]
 
 
 # ------------------------------------------------------------------ serving
