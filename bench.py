@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=2, help="--serve: pipelines the server runs at once")
     ap.add_argument("--serve-levels", default="0.5,0.8,0.95", help="--serve: loads relative to the offline rate")
     ap.add_argument("--no-graph", action="store_true", help="launch the kernels directly instead of replaying a graph")
+    ap.add_argument("--prefix-bases", type=int, default=-1,
+                    help="rebuild the index's prefix table for this many bases (0: none; default: the library's)")
     ap.add_argument("--per-length", action="store_true",
                     help="also time one batch call per distinct read length (default for c3)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -139,6 +141,10 @@ def main():
     t_index = time.perf_counter() - t
     built = d.build_info()
     log(f"index: built on the device in {t_index:.2f}s ({built})")
+    if args.prefix_bases >= 0:
+        d.set_prefix_table(args.prefix_bases)
+    index_bytes = d.index_bytes()
+    log(f"index bytes: {index_bytes}")
 
     N = reads.count
     d_reads = torch.from_numpy(reads.data).to(dev)
@@ -411,7 +417,10 @@ def main():
                             "index_segments": round(cnt["index_segments"] / N, 3),
                             "index_loads": round(cnt["index_loads"] / N, 3)},
         "index": {"device_build_s": round(t_index, 3), "sort_rounds": built["steps"],
-                  "sorted_pairs": built["sorted_pairs"]},
+                  "sorted_pairs": built["sorted_pairs"],
+                  # device bytes the timed (tuned) path reads, by part; the plain kernel reads text + suffix array
+                  "bytes": index_bytes, "tuned_path_bytes": sum(index_bytes.values()),
+                  "plain_path_bytes": index_bytes["text"] + index_bytes["suffix_array"]},
         "plain": plain,
         "speedup_vs_plain": round(value / plain["reads_per_s"], 3) if plain else None,
         "per_length": per_length,
@@ -551,7 +560,19 @@ def st_bench(args, np, torch, gen, S, ref, reads, text):
     ms_st = timed(lambda: S.st_match_batch_dev(sd, d_reads, d_offs, out_st, stream=stream), args.steps)
     same = bool((out_sa.cpu().numpy() == out_st.cpu().numpy()).all())
     assert same, "suffix-tree and suffix-array results differ"
-    sa_bytes = 4 * ref.n + 8 * ((ref.n + 31) // 32)
+    out_pl = torch.zeros((N, 4), dtype=torch.int32, device=dev)
+    pc = S.cfg(d, kernel=S.SA_KERNEL_PLAIN)
+    ms_pl = timed(lambda: S.match_batch_dev(d, d_reads, d_offs, out_pl, stream=stream, config=pc), max(2, args.steps // 4))
+    pl = out_pl.cpu().numpy()
+    sa_out = out_sa.cpu().numpy()
+    assert (pl[:, :3] == sa_out[:, :3]).all() and ((pl[:, 3] & 1) == (sa_out[:, 3] & 1)).all(), "plain kernel differs"
+    # device bytes each path reads: the tuned path every part of the index,
+    # the plain kernel (the paper's search) the text and the suffix array,
+    # the tree its nodes, the suffix array (leaves) and the text
+    ib = d.index_bytes()
+    tuned_bytes = sum(ib.values())
+    sa_bytes = ib["text"] + ib["suffix_array"]
+    st_bytes = st.device_bytes()
     line = {
         "metric": "reads/s: flattened suffix tree vs suffix array, same reads, identical results",
         "value": round(N / (ms_st * 1e-3), 1), "unit": "reads/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
@@ -561,9 +582,12 @@ def st_bench(args, np, torch, gen, S, ref, reads, text):
         "suffix_tree": {"ms_per_batch": round(ms_st, 4), "reads_per_s": round(N / (ms_st * 1e-3), 1),
                         "nodes": st.node_count(), "device_bytes": st.device_bytes(),
                         "host_build_s": round(t_st, 2)},
-        "suffix_array": {"ms_per_batch": round(ms_sa, 4), "reads_per_s": round(N / (ms_sa * 1e-3), 1),
-                         "device_bytes_sa_and_text": sa_bytes, "launch": cfg.as_dict()},
-        "sa_bytes_over_st_bytes": round(sa_bytes / st.device_bytes(), 4),
+        "suffix_array_tuned": {"ms_per_batch": round(ms_sa, 4), "reads_per_s": round(N / (ms_sa * 1e-3), 1),
+                               "device_bytes": tuned_bytes, "bytes_by_part": ib, "launch": cfg.as_dict()},
+        "suffix_array_plain": {"ms_per_batch": round(ms_pl, 4), "reads_per_s": round(N / (ms_pl * 1e-3), 1),
+                               "device_bytes": sa_bytes},
+        "plain_sa_bytes_over_st_bytes": round(sa_bytes / st_bytes, 4),
+        "tuned_sa_bytes_over_st_bytes": round(tuned_bytes / st_bytes, 4),
         "identical": same,
     }
     print(json.dumps(line), flush=True)
@@ -613,28 +637,51 @@ def serve_bench(args, np, torch, gen, S):
     log(f"{len(pool)} distinct requests ({sum(r.count for _, r in pool)} reads) generated in "
         f"{time.perf_counter() - t:.1f}s")
     levels = []
+    touched_per_read = None
     for k, rho in enumerate(float(x) for x in args.serve_levels.split(",")):
         lam = rho * x_off / mean_size
         nreq = args.serve_warmup + args.serve_requests
         stream = gen.request_stream(refs, nreq, lam, seed_sub=k, pool=pool)
-        srv = S.Server(dix, max_batch_reads=1 << 20, nstreams=args.serve_streams)
-        # the client: native threads of the library submit each request at
-        # its scheduled time (open loop), so no interpreter lock sits in
-        # the measured loop
-        outs, sched, stats = srv.replay([r.ref for r in stream], [r.reads.data for r in stream],
-                                        [r.reads.offs for r in stream],
-                                        [int(r.t_arrival * 1e9) for r in stream], nthreads=8)
-        srv.destroy()
+
+        def serve(measure):
+            # the client: native threads of the library submit each request
+            # at its scheduled time (open loop), so no interpreter lock sits
+            # in the measured loop; measure 1 times each batch's search
+            # stage with events, measure 2 runs the instrumented kernels
+            srv = S.Server(dix, max_batch_reads=1 << 20, nstreams=args.serve_streams, measure=measure)
+            res = srv.replay([r.ref for r in stream], [r.reads.data for r in stream], [r.reads.offs for r in stream],
+                             [int(r.t_arrival * 1e9) for r in stream], nthreads=32)
+            tot = srv.stats()
+            srv.destroy()
+            return res, tot
+
+        if touched_per_read is None:
+            # bytes the served search kernels touch per read, from one
+            # instrumented pass over this stream (its timing is not used)
+            _, tot2 = serve(2)
+            touched_per_read = tot2["touched_bytes"] / max(1, tot2["reads"])
+            log(f"served search kernels: {touched_per_read:.1f} bytes touched per read")
+        (outs, sched, stats), tot = serve(1)
         done = {i: (stats[i]["status"], stats[i]) for i in range(nreq)}
         meas = range(args.serve_warmup, nreq)
         lat = [(done[i][1]["t_done_ns"] - int(sched[i])) / 1e6 for i in meas if done[i][0] == S.SA_OK]
         reads_meas = sum(stream[i].reads.count for i in meas)
         span = (max(done[i][1]["t_done_ns"] for i in meas) - min(int(sched[i]) for i in meas)) / 1e9
         late = sum(1 for i in range(nreq) if done[i][1]["t_submit_ns"] - int(sched[i]) > 5_000_000)
+        search_s = tot["search_ms"] * 1e-3
         lv = {"rho": rho, "requests_per_s": round(lam, 1), "p50_ms": round(percentile(lat, 0.50), 3),
               "p99_ms": round(percentile(lat, 0.99), 3), "served_reads_per_s": round(reads_meas / span, 1),
               "offered_reads_per_s": round(rho * x_off, 1), "failed": sum(1 for v in done.values() if v[0] != 0),
-              "submits_late_over_5ms": late}
+              "submits_late_over_5ms": late,
+              # the served search kernels: their device time over all batches
+              # (warm-up included), reads per second of it, and bytes touched
+              # per second of it against the 8 TB/s peak
+              "batches": tot["batches"], "search_ms": round(tot["search_ms"], 3),
+              "search_reads_per_s": round(tot["reads"] / search_s, 1) if search_s > 0 else None,
+              "search_touched_GBps": round(touched_per_read * tot["reads"] / search_s / 1e9, 2) if search_s > 0 else None,
+              "search_touched_frac": round(touched_per_read * tot["reads"] / search_s / 1e9 / HBM_PEAK_GBS, 4)
+              if search_s > 0 else None,
+              "upload_bytes": tot["upload_bytes"]}
         levels.append(lv)
         log(f"rho={rho}: {lv}")
     line = {
@@ -645,6 +692,7 @@ def serve_bench(args, np, torch, gen, S):
                                "1-100,000 reads each (log-uniform), 30-300 bp", "requests_per_level": args.serve_requests,
                    "distinct_requests": args.serve_pool},
         "offline_reads_per_s": round(x_off, 1), "levels": levels,
+        "served_touched_bytes_per_read": round(touched_per_read, 1),
     }
     print(json.dumps(line), flush=True)
 

@@ -104,9 +104,10 @@ void sa_free(sa_index *ix);                           /* NULL is a no-op        
  * never touch the text), the table of the top levels of the
  * implicit binary-search tree that the tuned kernel stages in LDS (the tile
  * of Section IV), and, for n >= 4096, a prefix table: for every string v of
- * k = round(log4 n) + 1 bases (4 <= k <= 14), the first SA row whose suffix is
- * not below v (4^k + 1 int32 entries).  The host index may be freed
- * afterwards.  Released with sa_dfree (NULL is a no-op). */
+ * k = round(log4 n) bases (4 <= k <= 14), the first SA row whose suffix is
+ * not below v, with the first pivot suffix of the bracket it opens (4^k + 1
+ * entries of 16 bytes; see sa_set_prefix_table).  The host index may be
+ * freed afterwards.  Released with sa_dfree (NULL is a no-op). */
 int sa_upload(const sa_index *ix, int device, sa_dindex **out);
 void sa_dfree(sa_dindex *d);
 int64_t sa_dindex_length(const sa_dindex *d);
@@ -120,6 +121,22 @@ int64_t sa_dindex_length(const sa_dindex *d);
  * 29 bytes per base during construction, freed before returning).  The text
  * buffer is the caller's and is not kept. */
 int sa_build_device(const char *text, int64_t n, int device, sa_dindex **out);
+
+/* Device bytes of a resident index by part: bytes[0] packed text (with its
+ * padding words), bytes[1] suffix array, bytes[2] row records, bytes[3]
+ * prefix table (0 without one), bytes[4] LDS tile table.  The plain kernel
+ * reads the first two; the tuned kernels all of them. */
+int sa_dindex_bytes(const sa_dindex *d, int64_t bytes[5]);
+
+/* Rebuild the prefix table of a resident index for strings of k bases
+ * (4 <= k <= 14, texts of at least 4096 bases), or drop it (k = 0).  The
+ * default is k = round(log4 n), at most 14.  Entries are 16 bytes: the
+ * first SA row not below the k-base string, and the position and first 32
+ * bases of the suffix at the first pivot of the search bracket it opens.
+ * Resets the index's default search start and sort (prefix table and input
+ * order with a table, tile and prefix sort without); results never change.
+ * Not to be called while batches on this index are in flight. */
+int sa_set_prefix_table(sa_dindex *d, int k);
 
 /* Host copy (packed text and suffix array) of a resident index, e.g. to
  * save one built on the device with sa_save.  Free with sa_free. */
@@ -311,14 +328,27 @@ typedef struct {
     int test_echo;               /* 1: no device work, results are a deterministic echo  */
     int test_fail_batch;         /* > 0: the n-th executed batch fails (error injection) */
     int64_t host_pool_bytes;     /* pinned host memory, mapped for the device, that submit
-                                    copies reads into; the kernels read them there with no
-                                    upload (0: default 1 GiB, < 0: none); when it is full,
-                                    submit waits for room; a request larger than the whole
-                                    pool (or any request without a pool) is copied to pageable
-                                    memory and uploaded into a device arena, sized from free
-                                    HBM less hbm_reserve_bytes, where it needs room to be
-                                    admitted (SA_ENOSPC when it could never fit) */
+                                    copies reads into (0: default 1 GiB, < 0: none); when it
+                                    is full, submit waits for room; a request larger than the
+                                    whole pool (or any request without a pool) is copied to
+                                    pageable memory instead.  Every admitted request is copied
+                                    into a device arena (from the pool by an upload kernel,
+                                    else by the runtime) and searched there */
+    int measure;                 /* 0: off; 1: time each batch's search stage with events;
+                                    2: also run the instrumented search kernels and add up
+                                    the bytes they touch (slower); see sa_server_get_stats */
 } sa_server_opts;
+
+/* Totals of a server since it started.  upload_bytes: request images copied
+ * into the device arena; search_ms (measure >= 1): device time of the
+ * batches' search stages; touched_bytes (measure == 2): bytes touched by the
+ * search kernels, as c[7] of sa_probe_counts. */
+typedef struct {
+    int64_t batches, reads;
+    int64_t upload_bytes;
+    double search_ms;
+    int64_t touched_bytes;
+} sa_server_stats;
 
 typedef struct {
     int64_t t_submit_ns, t_admit_ns, t_done_ns;  /* steady-clock timestamps          */
@@ -326,11 +356,16 @@ typedef struct {
     int64_t nreads;
 } sa_req_stats;
 
-/* Start a request loop over nrefs resident indexes (all on one device):
- * requests are admitted in arrival order while max_inflight_reads allows,
- * batched per reference across requests (continuous batching) on nstreams
- * streams, and their results scattered back by a thread of their own.  The
- * indexes must outlive the server.  opts may be NULL (defaults). */
+/* Start a request loop over nrefs resident indexes (all on one device).
+ * At start the server takes, as its device arena, the device memory then
+ * free (hipMemGetInfo, or test_fake_free_hbm) less hbm_reserve_bytes and
+ * its streams' own buffers (at most 16 GiB); requests are admitted in
+ * arrival order while the arena has room for their reads and offsets and
+ * max_inflight_reads allows (a request that could never fit finishes with
+ * SA_ENOSPC), copied into the arena, batched per reference across requests
+ * (continuous batching) on nstreams streams, and their results scattered
+ * back by a thread of their own.  The indexes must outlive the server.
+ * opts may be NULL (defaults). */
 int sa_server_create(const sa_dindex *const *refs, int nrefs, const sa_server_opts *opts,
                      sa_server **out);
 
@@ -361,6 +396,9 @@ int sa_server_replay(sa_server *s, int64_t nreq, const int32_t *ref, const char 
  * request's error code; st (nullable) receives its timestamps.  A finished
  * ticket may be polled again until sa_server_destroy. Thread-safe. */
 int match_poll(sa_server *s, uint64_t ticket, int64_t timeout_us, sa_req_stats *st);
+
+/* Copy the server's running totals (see sa_server_stats) into *out. */
+int sa_server_get_stats(sa_server *s, sa_server_stats *out);
 
 /* Cancel pending requests (they finish with SA_ECANCELED), wait for
  * in-flight batches, release everything. */

@@ -288,6 +288,55 @@ int run_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t
 
 namespace {
 
+// Prefix-table length of a text of n bases: round(log4 n), so that a
+// table entry's bracket holds about one row, at most kMaxPrefixBases; none
+// below 4096 bases.  (With 4-byte entries, one base more cut the probes per
+// read by a fifth for a 4x larger table; with 16-byte entries that hold the
+// bracket's first pivot, the first probe is free and the table stays near
+// 16 bytes per base.)
+int default_prefix_bases(int64_t n) {
+    if (n < 4096) return 0;
+    const int k = (int)std::lround(std::log2((double)n) / 2.0);
+    return std::max(4, std::min(kMaxPrefixBases, k));
+}
+
+// (Re)build the prefix table of d with k bases (0: none).  Captured graphs
+// hold the old index view, so every workspace drops them.
+int set_prefix_table(sa_dindex *d, int k) {
+    hipError_t e;
+    if (d->d_ptab) {
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "prefix table release");
+        (void)hipFree(d->d_ptab);
+        d->d_ptab = nullptr;
+    }
+    d->view.ptab = nullptr;
+    d->view.ptab_k = 0;
+    d->ptab_bytes = 0;
+    {
+        std::lock_guard<std::mutex> lk(d->mu);
+        for (auto &kv : d->ws) {
+            std::lock_guard<std::mutex> wl(kv.second->mu);
+            kv.second->drop_graphs();
+        }
+    }
+    if (k > 0) {
+        const size_t entries = ((size_t)1 << (2 * k)) + 1;
+        if ((e = hipMalloc((void **)&d->d_ptab, entries * sizeof(PrefixEntry))) != hipSuccess)
+            return hip_fail(e, "prefix table allocation");
+        DevIndex v = d->view;
+        v.ptab = d->d_ptab;
+        v.ptab_k = k;
+        if ((e = launch_build_prefix_table(v, k, d->d_ptab, nullptr)) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess)
+            return hip_fail(e, "prefix table build");
+        d->view = v;
+        d->ptab_bytes = (int64_t)(entries * sizeof(PrefixEntry));
+    }
+    d->defaults.prefix_table = k > 0 ? 1 : 0;
+    d->defaults.sort = k > 0 ? 0 : 1;
+    return SA_OK;
+}
+
 // Device index from the packed text and either a host suffix array
 // (host_sa) or one built here on the device.
 int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, const int32_t *host_sa,
@@ -368,25 +417,8 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
         const unsigned sh = (unsigned)(p & 31) * 2u;
         v.short_key[i] = sh ? (lo << sh) | (hi >> (64u - sh)) : lo;
     }
-    // prefix table over k = log4(n) rounded, plus one, at most kMaxPrefixBases
-    // bases (one base more than log4 n cut the probes per read by a fifth and
-    // the search time by 1-3 % on MI355X, for a table of 4^k + 1 entries)
-    int k = 0;
-    if (n >= 4096) {
-        k = (int)std::lround(std::log2((double)n) / 2.0) + 1;
-        k = std::max(4, std::min(kMaxPrefixBases, k));
-    }
-    if (k > 0) {
-        const size_t entries = ((size_t)1 << (2 * k)) + 1;
-        if ((e = hipMalloc((void **)&d->d_ptab, entries * sizeof(PrefixEntry))) != hipSuccess)
-            return hip_fail(e, "prefix table allocation");
-        v.ptab = d->d_ptab;
-        v.ptab_k = k;
-        if ((e = launch_build_prefix_table(v, k, d->d_ptab, nullptr)) != hipSuccess ||
-            (e = hipDeviceSynchronize()) != hipSuccess)
-            return hip_fail(e, "prefix table build");
-    }
     d->view = v;
+    if (int rc = set_prefix_table(d.get(), default_prefix_bases(n))) return rc;
     sa_match_cfg &c = d->defaults;
     std::memset(&c, 0, sizeof c);
     c.kernel = SA_KERNEL_TUNED;
@@ -451,6 +483,28 @@ extern "C" int sa_download(const sa_dindex *d, sa_index **out) {
         return hip_fail(e, "index download");
     *out = ix.release();
     return SA_OK;
+}
+
+extern "C" int sa_dindex_bytes(const sa_dindex *d, int64_t bytes[5]) {
+    clear_error();
+    if (!d || !bytes) return fail(SA_EINVAL, "NULL argument");
+    const int64_t n = d->n;
+    bytes[0] = (int64_t)sizeof(uint64_t) * (((n + 31) >> 5) + kPadWords);
+    bytes[1] = (int64_t)sizeof(int32_t) * n;
+    bytes[2] = (int64_t)sizeof(RowRec) * n;
+    bytes[3] = d->ptab_bytes;
+    bytes[4] = (int64_t)((((size_t)1 << d->tile_levels) - 1) * (sizeof(uint64_t) + sizeof(int32_t)));
+    return SA_OK;
+}
+
+extern "C" int sa_set_prefix_table(sa_dindex *d, int k) {
+    clear_error();
+    if (!d) return fail(SA_EINVAL, "NULL argument");
+    if (k < 0 || (k > 0 && k < 4) || k > kMaxPrefixBases) return fail(SA_EINVAL, "prefix bases must be 0 or 4..14");
+    if (k > 0 && d->n < 4096) return fail(SA_EINVAL, "a prefix table needs a text of at least 4096 bases");
+    DeviceGuard g(d->device);
+    if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");
+    return set_prefix_table(d, k);
 }
 
 extern "C" int sa_dindex_build_info(const sa_dindex *d, int *steps, int64_t *sorted_pairs) {

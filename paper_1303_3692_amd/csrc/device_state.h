@@ -102,6 +102,7 @@ struct sa_dindex {
     int32_t *d_tile_sa = nullptr;
     samatch::RowRec *d_rows = nullptr;
     samatch::PrefixEntry *d_ptab = nullptr;
+    int64_t ptab_bytes = 0;
     int tile_levels = 0;  // levels stored (the kernel may use fewer)
     samatch::SaBuildInfo built{};  // when the suffix array was built on the device
     samatch::DevIndex view{};

@@ -1,24 +1,27 @@
 // Request loop over resident indexes: continuous batching of reads from
-// many requests, admission by a device-memory budget, several streams in
+// many requests, admission by free device memory, several streams in
 // flight, per-request scatter of results and timestamps.
 //
 // Life of a request: submit copies its reads and offsets into pinned host
-// memory (a pool allocated once and mapped into the device's address space,
-// so the kernels read the request there, over the bus, with no upload;
+// memory (a pool allocated once and mapped into the device's address space;
 // submit waits for room when the pool is full, and only a request larger
-// than the whole pool goes to pageable memory and through the device arena)
-// and queues it.
-// The loop admits queued requests in arrival order while the in-flight
-// read budget allows (and, for a request outside the pool, the device
-// arena, sized from free HBM minus the reserve when the server starts, has
-// room; admission copies it there).  Each free stream slot then takes up to
+// than the whole pool goes to pageable memory) and queues it.  The loop
+// admits queued requests in arrival order while the device arena, the
+// device memory free when the server started less the reserve and the
+// streams' own buffers, has room for the request's image and the in-flight
+// read budget allows.  Each round of admissions is copied into the arena by
+// one upload kernel on a stream of its own that reads the mapped pool over
+// the bus with coalesced 16-byte loads (a request in pageable memory is
+// copied by the runtime instead), so that the search kernels read their
+// reads from HBM, and a round's upload overlaps the searches of the batches
+// admitted before it.  Each free stream slot then takes up to
 // max_batch_reads unscheduled reads of one reference, from the admitted
 // requests of that reference in admission order, and runs one pipeline over
-// them (the reads stay where they are; a small kernel expands the batch's
-// pieces into each read's start and end from the offsets stored with the
-// reads).  A scatter thread copies a finished batch's results into the
-// owners' output arrays while the loop keeps scheduling; a request whose
-// reads are all done is finished and its pool and arena space returned.
+// them (a small kernel expands the batch's pieces into each read's start
+// and end from the offsets stored with the reads).  A scatter thread copies
+// a finished batch's results into the owners' output arrays while the loop
+// keeps scheduling; a request whose reads are all done is finished and its
+// pool and arena space returned.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -126,6 +129,39 @@ __global__ void expand_pieces_kernel(const PieceDev *__restrict__ pieces, int np
     en[r] = p.reads_at + of[k + 1];
 }
 
+// One request image to upload: bytes [src, src + bytes) of the mapped pool
+// to [dst, dst + bytes) of the arena (offsets 256-byte aligned, bytes a
+// multiple of 16), and the first 16-byte unit of it in the round's order.
+struct CopyItem {
+    int64_t src, dst, bytes, unit0;
+};
+constexpr int kUploadItems = 96;  // items per upload launch (passed by value)
+struct UploadList {
+    int count;
+    int64_t units;  // 16-byte units over all items
+    CopyItem item[kUploadItems];
+};
+
+// Copies a round's request images from the mapped host pool to the arena:
+// thread t moves 16-byte units t, t + threads, ... (neighbouring threads
+// neighbouring units, so loads and stores coalesce), each unit's item found
+// by binary search over the items' first units.
+__global__ __launch_bounds__(256) void upload_kernel(const UploadList list, const uint8_t *__restrict__ pool,
+                                                     uint8_t *__restrict__ arena) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < list.units; u += stride) {
+        int lo = 0, hi = list.count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (list.item[mid].unit0 <= u) lo = mid;
+            else hi = mid - 1;
+        }
+        const CopyItem &it = list.item[lo];
+        const int64_t b = (u - it.unit0) << 4;
+        *reinterpret_cast<uint4 *>(arena + it.dst + b) = *reinterpret_cast<const uint4 *>(pool + it.src + b);
+    }
+}
+
 struct Request {
     uint64_t ticket = 0;
     int ref = 0;
@@ -204,12 +240,15 @@ struct sa_server {
     std::condition_variable cv_scatter;
     bool scatter_stop = false;
     std::thread scatter;
+    // totals for sa_server_stats (under mu)
+    sa_server_stats totals{};
 
     void run();
     bool admit_locked();
     int upload_locked();
     bool launch(Slot &sl, std::unique_lock<std::mutex> &lk);
     bool reap(Slot &sl);
+    void measure_batch(Slot &sl);
     void settle_locked(Slot &sl);
     void scatter_run();
     void finish_locked(Request *r, int status);
@@ -237,32 +276,27 @@ void sa_server::finish_locked(Request *r, int status) {
     cv_done.notify_all();
 }
 
-// Admit queued requests in arrival order while the budget allows.  A
-// request in the pinned pool is read by the kernels where it is (the device
-// maps the pool), so it needs no arena space and no upload; any other one is
-// copied to the arena.
+// Admit queued requests in arrival order while the device arena has room
+// for their images and the in-flight read budget allows.  A request that
+// could never fit (larger than the arena, or than the budget) is refused
+// with SA_ENOSPC.
 bool sa_server::admit_locked() {
     bool any = false;
     while (!queued.empty()) {
         Request *r = queued.front();
         const int64_t bytes = image_bytes(r->offs[(size_t)r->nreads], r->nreads);
-        const bool mapped = pool_dev != nullptr && r->pool_off >= 0;
-        if ((!mapped && bytes > arena.capacity()) || r->nreads > o.max_inflight_reads) {
+        if (bytes > arena.capacity() || r->nreads > o.max_inflight_reads) {
             queued.pop_front();
             finish_locked(r, SA_ENOSPC);
             any = true;
             continue;
         }
         if (inflight_reads > 0 && inflight_reads + r->nreads > o.max_inflight_reads) break;
-        if (!mapped) {
-            const int64_t off = arena.alloc(bytes);
-            if (off < 0) break;
-            r->arena_off = off;
-            r->arena_bytes = bytes;
-            r->dev_at = off;
-        } else {
-            r->dev_at = (int64_t)((uintptr_t)(pool_dev + r->pool_off) - (uintptr_t)d_arena);
-        }
+        const int64_t off = arena.alloc(bytes);
+        if (off < 0) break;
+        r->arena_off = off;
+        r->arena_bytes = bytes;
+        r->dev_at = off;
         queued.pop_front();
         r->admitted = true;
         r->t_admit = now_ns();
@@ -270,7 +304,7 @@ bool sa_server::admit_locked() {
         if (r->nreads == 0) {
             finish_locked(r, SA_OK);
         } else {
-            if (!o.test_echo && !mapped) to_upload.push_back(r);
+            if (!o.test_echo) to_upload.push_back(r);
             active[(size_t)r->ref].push_back(r);
         }
         any = true;
@@ -278,19 +312,44 @@ bool sa_server::admit_locked() {
     return any;
 }
 
-// Copy this round's admitted reads to the arena, then mark the upload
-// stream; every batch launched afterwards waits for that mark (one event
-// for the round instead of one per request).
+// Copy this round's admitted requests to the arena on the upload stream:
+// those in the mapped pool with upload kernels (up to kUploadItems requests
+// per launch), any other one with a runtime copy; then mark the upload
+// stream, and every batch launched afterwards waits for that mark (one
+// event for the round instead of one per request).
 int sa_server::upload_locked() {
     if (to_upload.empty()) return SA_OK;
     std::vector<Request *> rs;
     rs.swap(to_upload);
     hipError_t e = hipSuccess;
-    for (Request *r : rs)
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d_arena + r->arena_off, r->h_reads,
-                               (size_t)image_bytes(r->offs[(size_t)r->nreads], r->nreads), hipMemcpyHostToDevice,
+    UploadList list;
+    list.count = 0;
+    list.units = 0;
+    auto flush = [&]() {
+        if (list.count == 0 || e != hipSuccess) return;
+        const int64_t blocks = std::min<int64_t>((list.units + 255) / 256, 1024);
+        hipLaunchKernelGGL(upload_kernel, dim3((unsigned)blocks), dim3(256), 0, upload_stream, list, pool_dev, d_arena);
+        e = hipGetLastError();
+        list.count = 0;
+        list.units = 0;
+    };
+    for (Request *r : rs) {
+        if (e != hipSuccess) break;
+        const int64_t bytes = image_bytes(r->offs[(size_t)r->nreads], r->nreads);
+        if (pool_dev != nullptr && r->pool_off >= 0) {
+            // whole 16-byte units: both allocations are 256-byte aligned and rounded up to 256 bytes
+            const int64_t units = (bytes + 15) >> 4;
+            list.item[list.count++] = CopyItem{r->pool_off, r->arena_off, units << 4, list.units};
+            list.units += units;
+            if (list.count == kUploadItems) flush();
+        } else {
+            e = hipMemcpyAsync(d_arena + r->arena_off, r->h_reads, (size_t)bytes, hipMemcpyHostToDevice,
                                upload_stream);
+        }
+    }
+    flush();
+    if (e == hipSuccess)
+        for (Request *r : rs) totals.upload_bytes += image_bytes(r->offs[(size_t)r->nreads], r->nreads);
     if (e == hipSuccess) e = hipEventRecord(uploaded, upload_stream);
     if (e == hipSuccess) {
         any_upload = true;
@@ -378,15 +437,19 @@ bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
     sa_dindex *d = refs[(size_t)ref];
     Workspace *ws = workspace_for(d, sl.stream);
     int rc;
-    // the reads come over the bus from the pinned pool: the search kernel
-    // packs them itself (coalesced, with the next chunk's loads in flight),
-    // under the deepest LDS tile that leaves room for its packing areas
+    // the reads are in the arena, each request's back to back: the search
+    // kernel packs them itself (coalesced, with the next chunk's loads in
+    // flight), under the deepest LDS tile that leaves room for its packing
+    // areas
     sa_match_cfg c = resolve_cfg(d, nullptr);
     if (c.kernel == SA_KERNEL_TUNED) {
         c.sort = 0;
         c.inline_pack = 1;
         while (c.tile_levels > 1 && tuned_lds_bytes(c.tile_levels, c.block, true) > inline_lds_limit()) c.tile_levels--;
     }
+    c.use_graph = 0;
+    c.profile = o.measure >= 1 ? 1 : 0;  // stage events, read when the batch is reaped
+    c.count = o.measure == 2 ? 1 : 0;
     {
         std::lock_guard<std::mutex> wl(ws->mu);
         rc = enqueue_batch(d, ws, d_arena, sl.d_se, sl.d_se + o.max_batch_reads, rows, sl.d_out, sl.stream, c);
@@ -432,8 +495,13 @@ bool sa_server::reap(Slot &sl) {
         hipError_t e = hipEventQuery(sl.done);
         if (e == hipErrorNotReady) return false;
         if (e != hipSuccess) sl.error = hip_fail(e, "batch execution");
+        if (e == hipSuccess && o.measure >= 1) measure_batch(sl);
     } else if (o.test_echo && sl.error == SA_OK) {
         echo_execute(sl);
+    }
+    if (sl.error == SA_OK) {
+        totals.batches++;
+        totals.reads += sl.nreads;
     }
     if (sl.error == SA_OK) {  // the scatter thread copies the results out, then settles the slot
         sl.scattering = true;
@@ -443,6 +511,22 @@ bool sa_server::reap(Slot &sl) {
     }
     settle_locked(sl);
     return true;
+}
+
+// Measurement mode: the finished batch's search-stage time from the stage
+// events of its (index, stream) workspace, and with counting on, the bytes
+// its search kernels touched.
+void sa_server::measure_batch(Slot &sl) {
+    Workspace *ws = workspace_for(refs[(size_t)sl.ref], sl.stream);
+    std::lock_guard<std::mutex> wl(ws->mu);
+    float ms = 0;
+    if (ws->profiled && hipEventElapsedTime(&ms, ws->ev[2], ws->ev[3]) == hipSuccess) totals.search_ms += ms;
+    if (ws->counted) {
+        unsigned long long touched = 0;
+        if (hipMemcpy(&touched, ws->b.stats + 7, sizeof touched, hipMemcpyDeviceToHost) == hipSuccess)
+            totals.touched_bytes += (int64_t)touched;
+    }
+    (void)hipGetLastError();
 }
 
 // Account a finished batch whose results (if any) are in the owners'
@@ -579,7 +663,9 @@ extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const s
         o.test_fake_free_hbm = opts->test_fake_free_hbm;
         o.test_echo = opts->test_echo;
         o.test_fail_batch = opts->test_fail_batch;
+        o.measure = opts->measure;
     }
+    if (o.measure < 0 || o.measure > 2) return fail(SA_EINVAL, "measure must be 0, 1 or 2");
     if (o.nstreams > 8) return fail(SA_EINVAL, "nstreams must be at most 8");
     if (o.max_batch_reads > INT32_MAX) return fail(SA_EINVAL, "max_batch_reads too large");
     for (int i = 0; i < nrefs; i++) {
@@ -763,6 +849,14 @@ extern "C" int match_poll(sa_server *s, uint64_t ticket, int64_t timeout_us, sa_
         st->nreads = r->nreads;
     }
     return r->status;
+}
+
+extern "C" int sa_server_get_stats(sa_server *s, sa_server_stats *out) {
+    clear_error();
+    if (!s || !out) return fail(SA_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->totals;
+    return SA_OK;
 }
 
 extern "C" int sa_server_destroy(sa_server *s) {

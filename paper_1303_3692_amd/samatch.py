@@ -24,12 +24,14 @@ SA_KERNEL_TUNED, SA_KERNEL_PLAIN = 0, 1
 EXPORTS = [
     "sa_build", "sa_build_from_sa", "sa_index_length", "sa_index_copy_sa", "sa_save", "sa_load", "sa_free",
     "sa_upload", "sa_dfree", "sa_dindex_length", "sa_build_device", "sa_download", "sa_dindex_build_info",
+    "sa_dindex_bytes", "sa_set_prefix_table",
     "sa_default_cfg", "match_batch", "match_batch_dev",
     "sa_stage_times", "sa_probe_counts", "sa_tune", "sa_tune_candidates", "sa_random_read_rate",
     "sa_locate_dev", "sa_locate",
     "st_build", "st_free", "st_node_count", "st_root", "st_copy_nodes", "st_index_bytes", "st_upload", "st_dfree",
     "st_match_batch_dev",
-    "sa_server_create", "match_submit", "match_poll", "sa_server_replay", "sa_server_destroy", "sa_strerror",
+    "sa_server_create", "match_submit", "match_poll", "sa_server_replay", "sa_server_get_stats",
+    "sa_server_destroy", "sa_strerror",
     "sa_last_error",
 ]
 
@@ -59,7 +61,12 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_reserve_bytes", ctypes.c_int64), ("max_batch_reads", ctypes.c_int64),
                 ("max_inflight_reads", ctypes.c_int64), ("nstreams", ctypes.c_int),
                 ("test_fake_free_hbm", ctypes.c_int64), ("test_echo", ctypes.c_int), ("test_fail_batch", ctypes.c_int),
-                ("host_pool_bytes", ctypes.c_int64)]
+                ("host_pool_bytes", ctypes.c_int64), ("measure", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_int64), ("reads", ctypes.c_int64), ("upload_bytes", ctypes.c_int64),
+                ("search_ms", ctypes.c_double), ("touched_bytes", ctypes.c_int64)]
 
 
 class ReqStats(ctypes.Structure):
@@ -102,6 +109,8 @@ def lib():
             "sa_random_read_rate": ([i32, i32, ctypes.POINTER(ctypes.c_double)], i32),
             "sa_tune": ([p, p, p, i64, p, ctypes.c_char_p, ctypes.POINTER(MatchCfg), ctypes.POINTER(ctypes.c_double)], i32),
             "sa_tune_candidates": ([p, p, i64, p, p, p, i32, ctypes.POINTER(ctypes.c_int)], i32),
+            "sa_dindex_bytes": ([p, p], i32),
+            "sa_set_prefix_table": ([p, i32], i32),
             "sa_locate_dev": ([p, p, i64, i32, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_int64)], i32),
             "sa_locate": ([p, p, i64, i32, i32, p, p, i64, ctypes.POINTER(ctypes.c_int64)], i32),
             "st_build": ([p, pp], i32),
@@ -117,6 +126,7 @@ def lib():
             "match_submit": ([p, i32, p, p, i64, p, ctypes.POINTER(ctypes.c_uint64)], i32),
             "match_poll": ([p, ctypes.c_uint64, i64, ctypes.POINTER(ReqStats)], i32),
             "sa_server_replay": ([p, i64, p, p, p, p, p, p, i32, p, ctypes.POINTER(ReqStats)], i32),
+            "sa_server_get_stats": ([p, p], i32),
             "sa_server_destroy": ([p], i32),
             "sa_strerror": ([i32], ctypes.c_char_p),
             "sa_last_error": ([], ctypes.c_char_p),
@@ -223,6 +233,16 @@ class DIndex:
 
     def __len__(self) -> int:
         return int(lib().sa_dindex_length(self._p))
+
+    def index_bytes(self) -> dict:
+        """Device bytes by part (sa_dindex_bytes)."""
+        b = (ctypes.c_int64 * 5)()
+        _check(lib().sa_dindex_bytes(self.ptr, b), "sa_dindex_bytes")
+        return {"text": b[0], "suffix_array": b[1], "row_records": b[2], "prefix_table": b[3], "tile": b[4]}
+
+    def set_prefix_table(self, k: int) -> None:
+        """Rebuild the prefix table for k-base strings (0: drop it)."""
+        _check(lib().sa_set_prefix_table(self.ptr, k), "sa_set_prefix_table")
 
     def build_info(self) -> dict:
         """Suffix sorting rounds and sorted pairs when built by sa_build_device."""
@@ -534,6 +554,12 @@ class Server:
                   "status": st[i].status, "nreads": st[i].nreads} for i in range(n)]
         _check(rc, "sa_server_replay")
         return [o[:len(f) - 1] for o, f in zip(outs, offss)], sched, stats
+
+    def stats(self) -> dict:
+        """Running totals (sa_server_get_stats)."""
+        st = ServerStats()
+        _check(lib().sa_server_get_stats(self._p, ctypes.byref(st)), "sa_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
     def destroy(self):
         if self._p:

@@ -323,3 +323,37 @@ def test_host_batch_in_chunks(device):
     d1 = S.sa_upload(S.sa_build(text1), 0)
     want1 = oracle.match(text1, oracle.sa_build(text1), short.data, short.offs)
     assert_same(S.match_batch(d1, short.data, short.offs), want1, "by count")
+
+
+@pytest.mark.parametrize("kind", ["iid", "tandem"])
+def test_prefix_table_lengths(device, kind):
+    """The prefix table rebuilt for every length from 4 to 12 bases (and
+    dropped): the oracle's bits each time, with the table's first-pivot
+    entries, empty brackets and end suffixes shorter than k exercised."""
+    say("case: prefix table lengths", kind)
+    rng = random.Random(41 if kind == "iid" else 43)
+    n = 60_000
+    if kind == "iid":
+        text = "".join(rng.choice("ACGT") for _ in range(n))
+    else:
+        text = "".join(rng.choice("ACGT") for _ in range(n // 2)) + ("GATTACA" * n)[: n - n // 2]
+    reads = []
+    for j in range(1, 16):
+        tail = text[-j:]
+        reads += [tail, tail + "A", tail + "T", tail + text[:7]]
+    for _ in range(4000):
+        i = rng.randrange(n)
+        r = text[i:i + rng.randint(1, 120)]
+        if rng.random() < 0.4 and r:
+            j = rng.randrange(len(r))
+            r = r[:j] + rng.choice("ACGT") + r[j + 1:]
+        reads.append(r)
+    reads += ["".join(rng.choice("ACGT") for _ in range(rng.randint(3, 60))) for _ in range(2000)]
+    data, offs = oracle.pack_reads(reads)
+    want = oracle.match(text, oracle.sa_build(text), data, offs)
+    d = S.sa_upload(S.sa_build(text), 0)
+    for k in (4, 5, 6, 7, 8, 9, 10, 11, 12, 0):
+        d.set_prefix_table(k)
+        assert d.index_bytes()["prefix_table"] == (16 * (4 ** k + 1) if k else 0)
+        for name, c in (("default", S.cfg(d)), ("b1024", S.cfg(d, block=1024, blocks_per_cu=1, group=1))):
+            assert_same(run_dev(d, data, offs, device, c), want, f"{kind}/k={k}/{name}")

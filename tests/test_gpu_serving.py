@@ -68,10 +68,10 @@ def test_requests_alone_and_in_the_mix(refs):
 
 @pytest.mark.parametrize("pool", [-1, 0])
 def test_open_loop_stream_and_budget(refs, pool):
-    """pool -1: no pinned pool, every request goes through the device arena
-    under a 4 MB budget (requests wait for admission; one that can never fit
-    is refused).  pool 0: the default mapped pool, read by the kernels in
-    place; the arena budget does not apply and the big request runs."""
+    """Every request is admitted into the device arena under a 4 MB budget
+    (requests wait for admission; one that can never fit is refused), with
+    no pinned pool (pool -1: pageable copies) and with the default mapped
+    pool (pool 0: copied to the arena by the upload kernel)."""
     print("case: serving stream, pool", pool, flush=True)
     rng = np.random.default_rng(13)
     reqs = []
@@ -91,11 +91,7 @@ def test_open_loop_stream_and_budget(refs, pool):
         time.sleep(0.001)
     t_big, out_big = srv.submit(0, big.data, big.offs)
     res = wait_all(srv, [t for t, _ in tickets] + [t_big])
-    if pool < 0:
-        assert res[t_big][0] == S.SA_ENOSPC
-    else:
-        assert res[t_big][0] == S.SA_OK
-        assert (out_big == S.match_batch(refs[0][3], big.data, big.offs)).all()
+    assert res[t_big][0] == S.SA_ENOSPC
     for (t, out), (which, r) in zip(tickets, reqs):
         assert res[t][0] == S.SA_OK
         alone = S.match_batch(refs[which][3], r.data, r.offs)
@@ -123,3 +119,34 @@ def test_replayed_stream(refs):
         assert t <= st["t_submit_ns"] <= st["t_admit_ns"] <= st["t_done_ns"]
         if r.count:
             assert (out == S.match_batch(refs[which][3], r.data, r.offs)).all()
+
+
+@pytest.mark.parametrize("measure", [1, 2])
+def test_measured_serving(refs, measure):
+    """Measurement mode: the same results as the reads matched alone, every
+    request image counted as uploaded to the arena, search time and (with
+    the instrumented kernels) bytes touched reported."""
+    print("case: measured serving", measure, flush=True)
+    rng = np.random.default_rng(15 + measure)
+    reqs = []
+    for i in range(24):
+        which = int(rng.integers(0, 2))
+        spec = gen.ReadSpec(3100 + i, int(rng.integers(1, 4000)), 30, 300, 0.2, 0.0, 0.02)
+        reqs.append((which, gen.make_reads(refs[which][0], spec)))
+    srv = S.Server([r[3] for r in refs], max_batch_reads=2048, nstreams=2, measure=measure)
+    tickets = [srv.submit(which, r.data, r.offs) for which, r in reqs]
+    res = wait_all(srv, [t for t, _ in tickets])
+    st = srv.stats()
+    srv.destroy()
+    for (t, out), (which, r) in zip(tickets, reqs):
+        assert res[t][0] == S.SA_OK
+        assert (out == S.match_batch(refs[which][3], r.data, r.offs)).all()
+    nreads = sum(r.count for _, r in reqs)
+    images = sum(((len(r.data) + 7) // 8) * 8 + 8 * (r.count + 1) for _, r in reqs)
+    assert st["reads"] == nreads and st["batches"] >= 1
+    assert st["upload_bytes"] == images
+    assert st["search_ms"] > 0
+    if measure == 2:
+        assert st["touched_bytes"] > 16 * nreads
+    else:
+        assert st["touched_bytes"] == 0
