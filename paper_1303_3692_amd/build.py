@@ -80,5 +80,71 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     return OUT
 
 
+# Sanitizer builds of the host code, for the CPU tests: every source
+# compiled for the host only (no device code, so no kernel can launch), each
+# -fsanitize= applying to the host pass only.  The sanitizer's runtime is not
+# linked in: the process that loads the library preloads it (runtime_path).
+SANITIZERS = {
+    "address": ["-fsanitize=address", "-fsanitize=undefined"],
+    "thread": ["-fsanitize=thread"],
+}
+
+
+def runtime_path(kind: str) -> str:
+    """The clang sanitizer runtime to preload for a build of `kind`
+    (the address runtime carries the undefined-behaviour handlers too)."""
+    r = subprocess.run([hipcc(), "--print-resource-dir"], capture_output=True, text=True)
+    res = r.stdout.strip() if r.returncode == 0 else ""
+    name = {"address": "libclang_rt.asan-x86_64.so", "thread": "libclang_rt.tsan-x86_64.so"}[kind]
+    path = os.path.join(res, "lib", "linux", name)
+    if not os.path.exists(path):
+        raise RuntimeError(f"sanitizer runtime {name} not found under {res}")
+    return path
+
+
+def build_sanitized(kind: str) -> str:
+    """Host-only library instrumented with the `kind` sanitizer(s); returns
+    its path (under _build/, never next to the product library)."""
+    out_dir = os.path.join(BUILD, f"san_{kind}")
+    os.makedirs(out_dir, exist_ok=True)
+    flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fno-sanitize-recover=all", "--cuda-host-only"]
+    for f in SANITIZERS[kind]:
+        flags += ["-Xarch_host", f]
+    base = [f for f in COMMON if f != "-O3"]
+
+    def one(src: str) -> str:
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmd = [hipcc(), *base, *flags, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
+        objs = list(ex.map(one, SOURCES))
+    # A host-only object still names the device image its source would
+    # embed (__hip_fatbin_<id>).  This build has none: each is defined as an
+    # empty image, so the library loads on a machine without a GPU, and no
+    # kernel exists to launch.
+    names = set()
+    for o in objs:
+        r = subprocess.run(["nm", "-u", o], capture_output=True, text=True, check=True)
+        names.update(w for line in r.stdout.splitlines() for w in line.split() if w.startswith("__hip_fatbin_"))
+    stub = os.path.join(out_dir, "no_device_images.c")
+    with open(stub, "w") as f:
+        for nm in sorted(names):
+            f.write(f"const unsigned char {nm}[64] = {{0}};\n")
+    stub_obj = stub + ".o"
+    subprocess.run(["gcc", "-fPIC", "-c", stub, "-o", stub_obj], check=True)
+    objs.append(stub_obj)
+    out = os.path.join(out_dir, "libsamatch.so")
+    cmd = [hipcc(), "-shared", "-fPIC", "-o", out, *objs, "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)

@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsamatch.so")
+# SAMATCH_LIB names another build of the same library (the sanitizer
+# builds of the CPU tests); by default the one built next to this file.
+LIB_PATH = os.environ.get("SAMATCH_LIB") or os.path.join(HERE, "libsamatch.so")
 
 SA_OK, SA_PENDING = 0, 1
 SA_EINVAL, SA_EALPHABET, SA_ETOOBIG, SA_ENOMEM, SA_EDEVICE = -1, -2, -3, -4, -5
