@@ -210,6 +210,28 @@ int match_batch(const sa_dindex *d, const char *reads, const int64_t *offs, int6
 int match_batch_dev(const sa_dindex *d, const uint8_t *d_reads, const int64_t *d_offs,
                     int64_t nreads, sa_hit *d_out, void *hip_stream, const sa_match_cfg *cfg);
 
+/* Entry point without allocation, for callers that cannot allocate device
+ * memory (code under stream capture, serving loops, hosts that forbid
+ * hipMalloc): the pipeline of match_batch_dev with the same arguments and
+ * results, but its scratch comes from one fixed array of
+ * SA_NOALLOC_SCRATCH_BYTES per device, set aside when the library is loaded
+ * and kept until the process ends, and it calls no allocating routine.  Its
+ * size bounds the batch only on the path with a pack pass (cfg.sort != 0,
+ * the plain kernel, or inline_pack = 0): sa_noalloc_max_reads(1) reads;
+ * inline packing (the default with a prefix table) needs a few counters
+ * whatever the batch size (sa_noalloc_max_reads(0)).  A larger batch ->
+ * SA_ENOSPC before any work.  cfg.use_graph is ignored (launches go to the
+ * stream directly); cfg.profile and cfg.count -> SA_EINVAL.  Every call on
+ * one device shares that device's array and leaves its contents behind (the
+ * kernels clear what must start at zero): calls that overlap on one device,
+ * on any streams, race and must be serialised by the caller. */
+#define SA_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+int match_batch_dev_noalloc(const sa_dindex *d, const uint8_t *d_reads, const int64_t *d_offs,
+                            int64_t nreads, sa_hit *d_out, void *hip_stream, const sa_match_cfg *cfg);
+/* Largest batch match_batch_dev_noalloc takes on the path with a pack pass
+ * (pack_pass = 1) or with inline packing (0). */
+int64_t sa_noalloc_max_reads(int pack_pass);
+
 /* Stage times in milliseconds of the last batch enqueued with cfg.profile
  * on this (index, stream): ms[0] pack, ms[1] prefix sort, ms[2] search,
  * ms[3] whole pipeline.  Waits for that batch.  SA_EINVAL if there is none. */

@@ -21,6 +21,7 @@ SOURCES = [
     "kernels.hip",
     "sa_construct.hip",
     "device.hip",
+    "noalloc.hip",
     "locate.hip",
     "tune.hip",
     "server.hip",

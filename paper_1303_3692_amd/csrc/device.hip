@@ -167,6 +167,11 @@ sa_match_cfg resolve_cfg(const sa_dindex *d, const sa_match_cfg *cfg) {
     return c;
 }
 
+bool packs_inline(const sa_match_cfg &c) {
+    return c.kernel == SA_KERNEL_TUNED && c.inline_pack && c.sort == 0 &&
+           tuned_lds_bytes(c.tile_levels, c.count ? 256 : c.block, true) <= inline_lds_limit();
+}
+
 // Enqueue the whole device pipeline for one batch: pack, optional prefix
 // sort, search.  All launches go to stream s.  d_ends may be NULL (CSR
 // offsets) or give each read's end (reads scattered over d_reads).
@@ -174,23 +179,32 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
                   int64_t nreads, sa_hit *d_out, hipStream_t s, const sa_match_cfg &c) {
     int rc = ws->reserve(nreads);
     if (rc) return rc;
-    const bool prof = c.profile != 0;
+    rc = enqueue_pipeline(d, ws->b, c.profile ? ws->ev : nullptr, d_reads, d_offs, d_ends, nreads, d_out, s, c);
+    if (rc) return rc;
+    ws->profiled = c.profile != 0;
+    ws->counted = c.count != 0;
+    return SA_OK;
+}
+
+int enqueue_pipeline(sa_dindex *d, const BatchBuffers &b, const hipEvent_t *ev, const uint8_t *d_reads,
+                     const int64_t *d_offs, const int64_t *d_ends, int64_t nreads, sa_hit *d_out, hipStream_t s,
+                     const sa_match_cfg &c) {
+    const bool prof = ev != nullptr;
     hipError_t e = hipSuccess;
-    if (prof && (e = hipEventRecord(ws->ev[0], s)) != hipSuccess) return hip_fail(e, "event record");
+    if (prof && (e = hipEventRecord(ev[0], s)) != hipSuccess) return hip_fail(e, "event record");
     // reads in input order: the tuned kernel can pack them itself when its
     // tile and the waves' packing areas fit in LDS
-    const bool inl = c.kernel == SA_KERNEL_TUNED && c.inline_pack && c.sort == 0 &&
-                     tuned_lds_bytes(c.tile_levels, c.count ? 256 : c.block, true) <= inline_lds_limit();
+    const bool inl = packs_inline(c);
     if (inl) {
-        e = launch_clear_stats(ws->b, s);
+        e = launch_clear_stats(b, s);
         if (e != hipSuccess) return hip_fail(e, "stats clear launch");
     } else {
         BucketTable bt = bucket_table(c);
         bt.keys = (c.kernel == SA_KERNEL_TUNED && c.sort) ? 1 : 0;
-        e = launch_pack(d_reads, d_offs, d_ends, nreads, ws->b, bt, s);
+        e = launch_pack(d_reads, d_offs, d_ends, nreads, b, bt, s);
         if (e != hipSuccess) return hip_fail(e, "pack launch");
     }
-    if (prof && (e = hipEventRecord(ws->ev[1], s)) != hipSuccess) return hip_fail(e, "event record");
+    if (prof && (e = hipEventRecord(ev[1], s)) != hipSuccess) return hip_fail(e, "event record");
     const uint32_t *order = nullptr, *sorted_key = nullptr;
     int key_shift = 0;
     uint32_t key_mask = 0;
@@ -204,18 +218,18 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         else while (pbits < 24 && ((int64_t)1 << pbits) < nreads / 64) pbits += 8;
         int which = 0;
         const int lo_bit = 24 - pbits, hi_bit = c.nbuckets > 1 ? 32 : 24;
-        e = launch_sort(ws->b, nreads, lo_bit, hi_bit, &which, s);
+        e = launch_sort(b, nreads, lo_bit, hi_bit, &which, s);
         if (e != hipSuccess) return hip_fail(e, "sort launch");
         if (nreads > 1) {
-            order = ws->b.val[which];
-            sorted_key = ws->b.key[which];
+            order = b.val[which];
+            sorted_key = b.key[which];
             key_shift = lo_bit;
             key_mask = hi_bit - lo_bit >= 32 ? 0xFFFFFFFFu : ((1u << (hi_bit - lo_bit)) - 1u);
         }
     }
-    if (prof && (e = hipEventRecord(ws->ev[2], s)) != hipSuccess) return hip_fail(e, "event record");
+    if (prof && (e = hipEventRecord(ev[2], s)) != hipSuccess) return hip_fail(e, "event record");
     if (c.kernel == SA_KERNEL_PLAIN) {
-        e = launch_search_plain(d->view, ws->b, nreads, d_out, c.count != 0, s);
+        e = launch_search_plain(d->view, b, nreads, d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "plain search launch");
     } else {
         // persistent workgroups; a batch too small to give each of them
@@ -224,21 +238,19 @@ int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int
         const int64_t chunks = (nreads + 63) / 64, gmax = std::max<int64_t>(1, (int64_t)d->cu_count * c.blocks_per_cu);
         const int group = (int)std::max<int64_t>(1, std::min<int64_t>(c.group, chunks / gmax));
         const int grid = (int)std::min<int64_t>(gmax, (chunks + group - 1) / group);
-        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, group, ws->b, order,
+        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, group, b, order,
                                 inl ? d_reads : nullptr, inl ? d_offs : nullptr, inl ? d_ends : nullptr, nreads, d_out,
                                 c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
     // reads longer than kShortMax: their own kernel, over the tail of the sorted order
     const uint32_t long_field = (long_read_key(c.nbuckets) >> key_shift) & key_mask;
-    e = launch_search_long(d->view, d_reads, d_offs, ws->b, order, sorted_key, key_shift, key_mask, long_field,
+    e = launch_search_long(d->view, d_reads, d_offs, b, order, sorted_key, key_shift, key_mask, long_field,
                            c.prefix_table, inl, inl ? d_ends : nullptr,
                            (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)d->cu_count * 8, (nreads + 63) / 64)),
                            nreads, d_out, c.count != 0, s);
     if (e != hipSuccess) return hip_fail(e, "long-read search launch");
-    if (prof && (e = hipEventRecord(ws->ev[3], s)) != hipSuccess) return hip_fail(e, "event record");
-    ws->profiled = prof;
-    ws->counted = c.count != 0;
+    if (prof && (e = hipEventRecord(ev[3], s)) != hipSuccess) return hip_fail(e, "event record");
     return SA_OK;
 }
 

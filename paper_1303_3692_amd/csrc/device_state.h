@@ -75,6 +75,15 @@ int check_cfg(const sa_dindex *d, const sa_match_cfg &c);
 sa_match_cfg resolve_cfg(const sa_dindex *d, const sa_match_cfg *cfg);
 int enqueue_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t *d_offs, const int64_t *d_ends,
                   int64_t nreads, sa_hit *d_out, hipStream_t s, const sa_match_cfg &c);
+// The same pipeline on buffers the caller provides (sized for nreads on the
+// path c takes, see packs_inline); ev: four events for the stage times, or
+// NULL.
+int enqueue_pipeline(sa_dindex *d, const BatchBuffers &b, const hipEvent_t *ev, const uint8_t *d_reads,
+                     const int64_t *d_offs, const int64_t *d_ends, int64_t nreads, sa_hit *d_out, hipStream_t s,
+                     const sa_match_cfg &c);
+// Whether c's tuned search packs reads in input order itself (no pack pass,
+// no sort): then the pipeline's only scratch is b.stats.
+bool packs_inline(const sa_match_cfg &c);
 // enqueue_batch through a captured graph when c.use_graph asks for it (and
 // the stream can be captured), else directly.
 int run_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t *d_offs, const int64_t *d_ends,

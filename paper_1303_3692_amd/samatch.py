@@ -27,7 +27,7 @@ EXPORTS = [
     "sa_build", "sa_build_from_sa", "sa_index_length", "sa_index_copy_sa", "sa_save", "sa_load", "sa_free",
     "sa_upload", "sa_dfree", "sa_dindex_length", "sa_build_device", "sa_download", "sa_dindex_build_info",
     "sa_dindex_bytes", "sa_set_prefix_table",
-    "sa_default_cfg", "match_batch", "match_batch_dev",
+    "sa_default_cfg", "match_batch", "match_batch_dev", "match_batch_dev_noalloc", "sa_noalloc_max_reads",
     "sa_stage_times", "sa_probe_counts", "sa_tune", "sa_tune_candidates", "sa_random_read_rate",
     "sa_locate_dev", "sa_locate",
     "st_build", "st_free", "st_node_count", "st_root", "st_copy_nodes", "st_index_bytes", "st_upload", "st_dfree",
@@ -106,6 +106,8 @@ def lib():
             "sa_default_cfg": ([p, ctypes.POINTER(MatchCfg)], i32),
             "match_batch": ([p, p, p, i64, p, p, ctypes.POINTER(MatchCfg)], i32),
             "match_batch_dev": ([p, p, p, i64, p, p, ctypes.POINTER(MatchCfg)], i32),
+            "match_batch_dev_noalloc": ([p, p, p, i64, p, p, ctypes.POINTER(MatchCfg)], i32),
+            "sa_noalloc_max_reads": ([i32], i64),
             "sa_stage_times": ([p, p, ctypes.POINTER(ctypes.c_double)], i32),
             "sa_probe_counts": ([p, p, ctypes.POINTER(ctypes.c_int64)], i32),
             "sa_random_read_rate": ([i32, i32, ctypes.POINTER(ctypes.c_double)], i32),
@@ -328,6 +330,22 @@ def match_batch_dev(d: DIndex, d_reads, d_offs, d_out, nreads: int | None = None
     _check(lib().match_batch_dev(d.ptr, ctypes.c_void_p(d_reads.data_ptr()), ctypes.c_void_p(d_offs.data_ptr()), n,
                                  ctypes.c_void_p(d_out.data_ptr()), _stream_handle(stream),
                                  ctypes.byref(config) if config is not None else None), "match_batch_dev")
+
+
+def match_batch_dev_noalloc(d: DIndex, d_reads, d_offs, d_out, nreads: int | None = None, stream=None,
+                            config: MatchCfg | None = None) -> None:
+    """match_batch_dev on the library's fixed device scratch (no allocation)."""
+    n = (d_offs.numel() - 1) if nreads is None else nreads
+    _check(lib().match_batch_dev_noalloc(d.ptr, ctypes.c_void_p(d_reads.data_ptr()),
+                                         ctypes.c_void_p(d_offs.data_ptr()), n, ctypes.c_void_p(d_out.data_ptr()),
+                                         _stream_handle(stream),
+                                         ctypes.byref(config) if config is not None else None),
+           "match_batch_dev_noalloc")
+
+
+def sa_noalloc_max_reads(pack_pass: bool) -> int:
+    """Largest batch match_batch_dev_noalloc takes with or without a pack pass."""
+    return int(lib().sa_noalloc_max_reads(1 if pack_pass else 0))
 
 
 def sa_stage_times(d: DIndex, stream=None) -> dict:
