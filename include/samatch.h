@@ -189,7 +189,10 @@ typedef struct {
 /* Fill cfg with the index's current defaults. */
 int sa_default_cfg(const sa_dindex *d, sa_match_cfg *cfg);
 
-/* Match a batch held in host memory and wait for it.  reads: concatenated
+/* Match a batch held in host memory and wait for it: for every read, the
+ * two binary searches of Section IV (Algorithm 1: LB, then RB) over the
+ * suffix array, or, when the read does not occur, the longest prefix that
+ * does and its row range (see "Result per read" above).  reads: concatenated
  * read bytes; offs[nreads+1]: read i is reads[offs[i] .. offs[i+1]) (offs[0]
  * may be nonzero, offsets must not decrease); out[nreads]: results in input
  * order.  Reads longer than SA_MAX_READ -> SA_ETOOBIG before any work.
@@ -202,7 +205,8 @@ int sa_default_cfg(const sa_dindex *d, sa_match_cfg *cfg);
 int match_batch(const sa_dindex *d, const char *reads, const int64_t *offs, int64_t nreads,
                 sa_hit *out, void *hip_stream, const sa_match_cfg *cfg);
 
-/* The same on device memory, asynchronous on hip_stream: d_reads, d_offs
+/* The same searches (Section IV, Algorithm 1) on device memory,
+ * asynchronous on hip_stream: d_reads, d_offs
  * and d_out are device pointers of the index's device; the call returns
  * after enqueueing.  Per-read errors (SA_HIT_TOOLONG) are reported in the
  * flags of out.  Scratch memory is kept per (index, stream) and grows on
@@ -250,16 +254,6 @@ int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]);
  * requests of the searches; c[9] those index loads counted per lane.
  * Waits for that batch. */
 int sa_probe_counts(const sa_dindex *d, void *hip_stream, int64_t c[10]);
-
-/* Measurement helper, not part of the matching path: the rate (loads per
- * second, into *loads_per_s) at which the device serves random 16-byte
- * loads from a table of 2^log2_entries 16-byte entries (8 <= log2_entries
- * <= 28), the access pattern of the search kernels' probes.  Every lane
- * follows two independent chains of 16 dependent loads at hashed positions,
- * 16 waves per compute unit; the best of five timed launches.  Allocates and
- * frees the table; runs on the null stream and waits for it.  SA_EINVAL for a
- * size out of range, SA_EDEVICE / SA_ENOMEM on device failures. */
-int sa_random_read_rate(int device, int log2_entries, double *loads_per_s);
 
 /* Autotuner: time candidate configurations (tile depth, workgroups per CU,
  * block size, bucket edges) on the given device batch, keep the fastest as

@@ -7,6 +7,7 @@
 
 #include "device_state.h"
 #include "internal.h"
+#include "samatch_measure.h"
 
 using namespace samatch;
 
