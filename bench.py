@@ -212,8 +212,8 @@ def main():
     def probe_bytes(cnt):
         # per global probe a 4-byte SA entry plus the 8-byte words it
         # compares (row-record words and text words); per prefix-table
-        # lookup its two 4-byte entries
-        return 4 * cnt["global_probes"] + 8 * (cnt["text_words"] + cnt["key_words"]) + 8 * cnt["table_lookups"]
+        # lookup its 16-byte entry
+        return 4 * cnt["global_probes"] + 8 * (cnt["text_words"] + cnt["key_words"]) + 16 * cnt["table_lookups"]
 
     def alg_bytes(cnt, c, ingest=False):
         # per read: the 2-bit packed read (ceil(m/4) bytes) + the 16-byte

@@ -105,8 +105,9 @@ void sa_free(sa_index *ix);                           /* NULL is a no-op        
  * implicit binary-search tree that the tuned kernel stages in LDS (the tile
  * of Section IV), and, for n >= 4096, a prefix table: for every string v of
  * k = round(log4 n) bases (4 <= k <= 14), the first SA row whose suffix is
- * not below v, with the first pivot suffix of the bracket it opens (4^k + 1
- * entries of 16 bytes; see sa_set_prefix_table).  The host index may be
+ * not below v with the bracket of rows that start with v, or the result of
+ * the reads that start with v when there are none (4^k + 1 entries of 16
+ * bytes; see sa_set_prefix_table).  The host index may be
  * freed afterwards.  Released with sa_dfree (NULL is a no-op). */
 int sa_upload(const sa_index *ix, int device, sa_dindex **out);
 void sa_dfree(sa_dindex *d);
@@ -130,9 +131,12 @@ int sa_dindex_bytes(const sa_dindex *d, int64_t bytes[5]);
 
 /* Rebuild the prefix table of a resident index for strings of k bases
  * (4 <= k <= 14, texts of at least 4096 bases), or drop it (k = 0).  The
- * default is k = round(log4 n), at most 14.  Entries are 16 bytes: the
- * first SA row not below the k-base string, and the position and first 32
- * bases of the suffix at the first pivot of the search bracket it opens.
+ * default is k = round(log4 n), at most 14.  Entries are 16 bytes, one per
+ * k-base string v (4^k + 1 in all): the first SA row not below v, and either
+ * the size of the bracket of rows that start with v with the position and
+ * bases k .. k+15 of the suffix at its first search pivot, or, when no
+ * suffix starts with v, the result every read starting with v gets (its
+ * longest matched prefix is shorter than k and depends on v alone).
  * Resets the index's default search start and sort (prefix table and input
  * order with a table, tile and prefix sort without); results never change.
  * Not to be called while batches on this index are in flight. */
@@ -246,7 +250,7 @@ int sa_stage_times(const sa_dindex *d, void *hip_stream, double ms[4]);
  * those probes compare, c[2] probes answered from the LDS tile, c[3] reads
  * searched, c[4] packed query words loaded, c[5] 8-byte words loaded from
  * row records (the first 32 bases of each probe included), c[6]
- * prefix-table lookups (two adjacent 4-byte entries each), c[7] bytes
+ * prefix-table lookups (one 16-byte entry each), c[7] bytes
  * touched by the search kernels: for every global load or store of a wave,
  * the distinct 64-byte segments its active lanes address, times 64; c[8]
  * the part of c[7] / 64 that the loads from the index make (prefix table,

@@ -48,16 +48,22 @@ struct alignas(16) StNode {
     int32_t child[4];
 };
 
-// Prefix-table entry of a k-base string v: T[v], the first SA row whose
-// suffix is not below v, then the text position and first 32 bases of the
-// suffix at the first pivot row of the search bracket (T[v] - 1, T[v+1]),
-// or at row T[v] when the bracket is empty (pos = -1 when that row is n).
-// One 16-byte load answers the lookup and the bracket's first probe.
+// Prefix-table entry of a k-base string v, 16 bytes, so that one load
+// answers a lookup.  row = T[v], the first SA row whose suffix is not below
+// v.  When some suffix starts with v, its rows are the bracket [T[v],
+// T[v+1]): size = T[v+1] - T[v] (>= 1), pos = text position of the suffix
+// at the bracket's first pivot row, midpoint(T[v] - 1, T[v+1]), and next =
+// that suffix's bases k .. k+15 (its first k are v).  When none does, every
+// read that starts with v has the same result, fixed by v alone: size =
+// kPtabAnswer | l, with l < k the longest prefix of v that occurs, and
+// [pos, next) the row interval of v[0..l).
 struct alignas(16) PrefixEntry {
     uint32_t row;
+    uint32_t size;
     int32_t pos;
-    uint64_t key0;
+    uint32_t next;
 };
+constexpr uint32_t kPtabAnswer = 0x80000000u;
 
 // Device view of a resident index, passed to kernels by value.
 struct DevIndex {

@@ -207,15 +207,17 @@ __device__ __forceinline__ RowHead row_head(const RowRec *__restrict__ rows, int
     return h;
 }
 
-// Probe of one suffix (text position p) whose first 32 bases (key0) are in
-// hand, with h bases known to match: like compare_from, but word 0 comes
-// from key0 and words 1 .. kRecWords-1 from the row record (rec; NULL for
-// a node of the LDS tile), loaded only while the words before them tie;
-// later words come from the text.
+// Probe of one suffix (text position p) whose first key_bases bases (key0,
+// the rest of its first word zero) are in hand, with h bases known to
+// match: like compare_from, but word 0 comes from key0 and words 1 ..
+// kRecWords-1 from the row record (rec; NULL for a node of the LDS tile or
+// a prefix-table pivot), loaded only while the words before them tie; later
+// words come from the text, and so does word 0 when key0 holds fewer than
+// 32 bases, ties on them, and the comparison reaches past them.
 template <int W, class Q, class Cnt>
 __device__ __forceinline__ int compare_row(const DevIndex &ix, const Q &q, int plen,
                                            const RowRec *__restrict__ rec, int32_t p, uint64_t key0, int h,
-                                           int &lcp, Cnt &cnt) {
+                                           int &lcp, Cnt &cnt, int key_bases = 32) {
     const int lim = min_i(plen, ix.n - p);
     const int k0 = h >> 5;
     int res = lim;
@@ -227,9 +229,10 @@ __device__ __forceinline__ int compare_row(const DevIndex &ix, const Q &q, int p
     for (int k = 0; k < W; ++k) {
         if (!done && k >= k0 && (k << 5) < lim) {
             uint64_t t;
-            if (k == 0) {
+            if (k == 0 && (key_bases >= 32 || lim <= key_bases ||
+                           ((q[0] ^ key0) & (~0ull << (64 - 2 * key_bases))) != 0)) {
                 t = key0;
-            } else if (rec != nullptr && k < kRecWords) {
+            } else if (k > 0 && rec != nullptr && k < kRecWords) {
                 t = reinterpret_cast<const uint64_t *>(rec)[1 + k];  // word k of the record
                 cnt.rec_word();
                 cnt.index_touch(reinterpret_cast<const uint64_t *>(rec) + 1 + k, 8);
@@ -356,50 +359,40 @@ __device__ __forceinline__ int short_at(const DevIndex &ix, int row) {
     return at;
 }
 
-// LB search of P[0..plen) inside the table bracket.  Returns false when the
-// bracket holds a short suffix (the caller then searches from the root).
-// Rows inside the bracket share k bases with P, so when the search moves a
-// bound inside, the other bound's common-prefix length (below k) never
-// decides anything and starts as 0; when the bracket is empty, both
-// neighbours are probed for their exact common-prefix lengths.
-// The table entry also holds the bracket's first pivot suffix (position
-// and first 32 bases), so the first probe needs no load of its own; for an
-// empty bracket it holds the right neighbour.
+// What the prefix-table step of a search did.
+enum class TableStep { kSearched, kAnswered, kFallback };
+
+// LB search of P[0..plen) inside the table bracket of its first k bases v.
+// kAnswered: no suffix starts with v, and the entry holds the read's result
+// (ans).  kFallback: the bracket holds a short suffix (the caller searches
+// from the root).  kSearched: st holds the LB search's final state.  Rows
+// inside the bracket share k bases with P, so when the search moves a bound
+// inside, the other bound's common-prefix length (below k) never decides
+// anything and starts as 0.  The first probe takes its pivot suffix's
+// position and first k + 16 bases from the entry, with no load of its own.
 template <int W, class Q, class Cnt>
-__device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, int plen, LbState &st,
-                                                Cnt &cnt) {
+__device__ __forceinline__ TableStep lb_search_table(const DevIndex &ix, const Q &q, int plen, LbState &st,
+                                                     int4 &ans, Cnt &cnt) {
     const int K = ix.ptab_k;
     const uint32_t v = (uint32_t)(q[0] >> (64 - 2 * K));
     const PrefixEntry ent = ix.ptab[v];
-    const int hi_k = (int)ix.ptab[v + 1].row;
-    const int lo_k = (int)ent.row;
     cnt.index_touch(ix.ptab + v, 16);
-    cnt.index_touch(&ix.ptab[v + 1].row, 4);
     cnt.table_probe();
-    if (short_rows_in(ix, lo_k, hi_k)) return false;
+    if (ent.size & kPtabAnswer) {
+        ans = make_int4(ent.pos, (int)ent.next, (int)(ent.size & ~kPtabAnswer), 0);
+        return TableStep::kAnswered;
+    }
+    const int lo_k = (int)ent.row;
+    const int hi_k = lo_k + (int)ent.size;
+    if (short_rows_in(ix, lo_k, hi_k)) return TableStep::kFallback;
     st.L = lo_k - 1; st.R = hi_k; st.lcpL = 0; st.lcpR = 0;
     st.Llt = -1; st.lcpLlt = 0; st.Rlt = ix.n; st.lcpRlt = 0;
-    if (hi_k == lo_k) {
-        int a = 0, c = 0;
-        if (st.L >= 0) {
-            const RowHead xl = row_head(ix.rows, st.L);
-            cnt.index_touch(ix.rows + st.L, 16);
-            cnt.key_probe();
-            compare_row<W>(ix, q, plen, ix.rows + st.L, xl.pos, xl.key0, 0, a, cnt);
-        }
-        if (st.R < ix.n) {
-            cnt.key_probe();
-            compare_row<W>(ix, q, plen, ix.rows + st.R, ent.pos, ent.key0, 0, c, cnt);
-        }
-        st.lcpL = a;
-        st.lcpR = c;
-        return true;
-    }
     {
         const int piv = midpoint(st.L, st.R);
+        const uint64_t key = (q[0] & ~(~0ull >> (2 * K))) | ((uint64_t)ent.next << (32 - 2 * K));
         int lcp;
-        cnt.key_probe();
-        const int sign = compare_row<W>(ix, q, plen, ix.rows + piv, ent.pos, ent.key0, 0, lcp, cnt);
+        cnt.global_probe();  // its position and bases came with the entry, not from a record
+        const int sign = compare_row<W>(ix, q, plen, nullptr, ent.pos, key, 0, lcp, cnt, K + 16);
         lb_update(st, sign, piv, lcp);
     }
     while (st.R > st.L + 1) {
@@ -412,41 +405,7 @@ __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, 
             compare_row<W>(ix, q, plen, ix.rows + piv, row.pos, row.key0, min_i(st.lcpL, st.lcpR), lcp, cnt);
         lb_update(st, sign, piv, lcp);
     }
-    return true;
-}
-
-// Row interval [lo, hi) of u = P[0..l), 1 <= l < k, from the table: lo is
-// T[u A..A] less the short suffixes u, uA, uAA... sorting right before it;
-// hi is T[successor of u T..T] less the short suffixes that are proper
-// prefixes of that successor and sort after u (right before it).
-template <class Cnt>
-__device__ __forceinline__ void table_interval(const DevIndex &ix, uint64_t q0, int l, int &lo, int &hi, Cnt &cnt) {
-    const int K = ix.ptab_k;
-    const uint32_t u = (uint32_t)(q0 >> (64 - 2 * l));
-    const uint32_t ulo = u << (2 * (K - l));
-    const uint32_t w = ulo + (1u << (2 * (K - l)));
-    lo = (int)ix.ptab[ulo].row;
-    hi = (int)ix.ptab[w].row;
-    cnt.index_touch(&ix.ptab[ulo].row, 4);
-    cnt.index_touch(&ix.ptab[w].row, 4);
-    cnt.table_probe();
-    for (;;) {
-        const int si = lo > 0 ? short_at(ix, lo - 1) : -1;
-        if (si < 0) break;
-        const int len = ix.short_len[si];
-        if (len >= l && (uint32_t)(ix.short_key[si] >> (64 - 2 * l)) == u) lo--;
-        else break;
-    }
-    for (;;) {
-        const int si = hi > lo ? short_at(ix, hi - 1) : -1;
-        if (si < 0) break;
-        const int len = ix.short_len[si];
-        const int c = len < l ? len : l;
-        const uint32_t kp = (uint32_t)(ix.short_key[si] >> (64 - 2 * c));
-        const uint32_t up = u >> (2 * (l - c));
-        if (kp > up) hi--;
-        else break;
-    }
+    return TableStep::kSearched;
 }
 
 // One read: LB search of its ACGT prefix; exact reads finish with an RB
@@ -457,19 +416,21 @@ template <int W, class Q, class Cnt>
 __device__ __forceinline__ int4 match_read(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
                            bool use_table, const Q &q, int m, int mv, Cnt &cnt) {
     LbState st;
-    const bool via_table = use_table && ix.ptab_k > 0 && mv >= ix.ptab_k && lb_search_table<W>(ix, q, mv, st, cnt);
-    if (!via_table) lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, cnt);
+    TableStep step = TableStep::kFallback;
+    if (use_table && ix.ptab_k > 0 && mv >= ix.ptab_k) {
+        int4 ans;
+        step = lb_search_table<W>(ix, q, mv, st, ans, cnt);
+        if (step == TableStep::kAnswered) return ans;
+    }
+    if (step != TableStep::kSearched) lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, cnt);
     if (mv == m && st.lcpR == m) {
         const int hi = bounded_search<W, true>(ix, q, m, st.R, st.Rlt, m, st.lcpRlt, cnt);
         return make_int4(st.R, hi, m, (int)kHitExact);
     }
+    // (after a search inside a table bracket l >= k: one of the final
+    // bounds is a probed row of the bracket, which shares the k bases)
     const int l = max_i(st.lcpL, st.lcpR);
     if (l == 0) return make_int4(0, ix.n, 0, 0);
-    if (via_table && l < ix.ptab_k) {
-        int lo, hi;
-        table_interval(ix, q[0], l, lo, hi, cnt);
-        return make_int4(lo, hi, l, 0);
-    }
     const int lo = (st.lcpL == l) ? bounded_search<W, false>(ix, q, l, st.Llt, st.L, st.lcpLlt, l, cnt) : st.R;
     const int hi = (st.lcpR == l) ? bounded_search<W, true>(ix, q, l, st.R, st.Rlt, l, st.lcpRlt, cnt) : st.R;
     return make_int4(lo, hi, l, 0);
@@ -526,22 +487,33 @@ __global__ void build_prefix_table_kernel(DevIndex ix, int k, int64_t entries, P
     tab[v].row = (uint32_t)lo;
 }
 
-// Second pass: each entry's first pivot row of its bracket (T[v] - 1,
-// T[v+1]), or T[v] for an empty bracket, and that row's position and first
-// 32 bases from its record.
-__global__ void fill_prefix_pivots_kernel(DevIndex ix, int64_t entries, PrefixEntry *__restrict__ tab) {
+// Second pass (after every T[v] is written): each entry's bracket size
+// and first pivot suffix, or, for a string v no suffix starts with, the
+// result of a search for v itself from the root (any read starting with v
+// has it: its longest matched prefix is shorter than v).
+__global__ void fill_prefix_entries_kernel(DevIndex ix, int k, int64_t entries, PrefixEntry *__restrict__ tab) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= entries) return;
+    if (v == entries - 1) {  // T[4^k] = n closes the last bracket; it is never looked up
+        tab[v].size = 0;
+        tab[v].pos = 0;
+        tab[v].next = 0;
+        return;
+    }
     const int lo = (int)tab[v].row;
-    const int hi = v + 1 < entries ? (int)tab[v + 1].row : lo;
-    const int piv = hi > lo ? midpoint(lo - 1, hi) : lo;
-    if (piv < ix.n) {
-        const RowHead h = row_head(ix.rows, piv);
+    const int hi = (int)tab[v + 1].row;
+    if (hi > lo) {
+        const RowHead h = row_head(ix.rows, midpoint(lo - 1, hi));
+        tab[v].size = (uint32_t)(hi - lo);
         tab[v].pos = h.pos;
-        tab[v].key0 = h.key0;
+        tab[v].next = (uint32_t)(h.key0 >> (32 - 2 * k));
     } else {
-        tab[v].pos = -1;
-        tab[v].key0 = 0;
+        const uint64_t q[1] = {(uint64_t)v << (64 - 2 * k)};
+        NoCount none;
+        const int4 r = match_read<1>(ix, nullptr, nullptr, 0, false, q, k, k, none);
+        tab[v].size = kPtabAnswer | (uint32_t)r.z;
+        tab[v].pos = r.x;
+        tab[v].next = (uint32_t)r.y;
     }
 }
 
@@ -1690,7 +1662,7 @@ hipError_t launch_build_prefix_table(const DevIndex &ix, int k, PrefixEntry *tab
     const int64_t entries = ((int64_t)1 << (2 * k)) + 1;
     hipLaunchKernelGGL(build_prefix_table_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix, k,
                        entries, tab);
-    hipLaunchKernelGGL(fill_prefix_pivots_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix,
+    hipLaunchKernelGGL(fill_prefix_entries_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix, k,
                        entries, tab);
     return hipGetLastError();
 }
