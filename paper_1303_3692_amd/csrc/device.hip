@@ -382,29 +382,12 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
         return hip_fail(e, "index allocation");
     if ((e = hipMemcpy(d->d_text, packed.data(), text_bytes, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "index upload");
-    // rows of the shortest suffixes (the last kShort text positions), as (row, length)
-    std::vector<std::pair<int32_t, int32_t>> short_rows;
-    const int64_t cut = n - kShort;
     if (host_sa) {
         if ((e = hipMemcpy(d->d_sa, host_sa, sa_bytes, hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "index upload");
-        for (int64_t r = 0; r < n; r++)
-            if (host_sa[r] >= cut) short_rows.emplace_back((int32_t)r, (int32_t)(n - host_sa[r]));
     } else {
-        uint32_t *rank = nullptr;
-        if ((e = hipMalloc((void **)&rank, sizeof(uint32_t) * (size_t)n)) != hipSuccess)
-            return hip_fail(e, "rank allocation");
-        int rc = build_sa_device(d->d_text, n, d->d_sa, rank, nullptr, &d->built);
-        const int64_t first = std::max<int64_t>(0, cut);
-        std::vector<uint32_t> tail((size_t)(n - first));
-        if (rc == SA_OK &&
-            (e = hipMemcpy(tail.data(), rank + first, sizeof(uint32_t) * tail.size(), hipMemcpyDeviceToHost)) !=
-                hipSuccess)
-            rc = hip_fail(e, "rank download");
-        (void)hipFree(rank);
+        int rc = build_sa_device(d->d_text, n, d->d_sa, nullptr, nullptr, &d->built);
         if (rc) return rc;
-        for (int64_t p = first; p < n; p++)
-            short_rows.emplace_back((int32_t)(tail[(size_t)(p - first)] - 1u), (int32_t)(n - p));
     }
     if ((e = launch_build_rows(d->d_text, d->d_sa, (int32_t)n, d->d_rows, nullptr)) != hipSuccess ||
         (e = launch_build_tile(d->d_text, d->d_sa, (int32_t)n, d->tile_levels, d->d_tile_key, d->d_tile_sa,
@@ -418,25 +401,16 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
     v.tile_sa = d->d_tile_sa;
     v.rows = d->d_rows;
     v.n = (int32_t)n;
-    std::sort(short_rows.begin(), short_rows.end());
-    v.nshort = (int32_t)short_rows.size();
-    for (size_t i = 0; i < short_rows.size(); i++) {
-        v.short_row[i] = short_rows[i].first;
-        v.short_len[i] = short_rows[i].second;
-        // first 32 bases of the suffix, zero past the end
-        const int64_t p = n - short_rows[i].second;
-        const uint64_t lo = packed[(size_t)(p >> 5)], hi = packed[(size_t)(p >> 5) + 1];
-        const unsigned sh = (unsigned)(p & 31) * 2u;
-        v.short_key[i] = sh ? (lo << sh) | (hi >> (64u - sh)) : lo;
-    }
     d->view = v;
     if (int rc = set_prefix_table(d.get(), default_prefix_bases(n))) return rc;
     sa_match_cfg &c = d->defaults;
     std::memset(&c, 0, sizeof c);
     c.kernel = SA_KERNEL_TUNED;
-    c.tile_levels = std::min(12, d->tile_levels);
-    c.block = 256;
-    c.blocks_per_cu = 8;
+    // one workgroup of 16 waves per compute unit; with a prefix table the
+    // tile serves only reads with fewer than k leading bases
+    c.tile_levels = std::min(d->view.ptab_k > 0 ? 8 : 12, d->tile_levels);
+    c.block = 1024;
+    c.blocks_per_cu = 1;
     c.nbuckets = 1;
     c.bucket_edge[0] = SA_MAX_READ;
     // with the prefix table, reads in input order search as fast as sorted

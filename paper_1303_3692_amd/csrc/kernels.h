@@ -51,8 +51,9 @@ struct alignas(16) StNode {
 // Prefix-table entry of a k-base string v, 16 bytes, so that one load
 // answers a lookup.  row = T[v], the first SA row whose suffix is not below
 // v.  When some suffix starts with v, its rows are the bracket [T[v],
-// T[v+1]): size = T[v+1] - T[v] (>= 1), pos = text position of the suffix
-// at the bracket's first pivot row, midpoint(T[v] - 1, T[v+1]), and next =
+// T[v] + size), size >= 1 (the suffixes shorter than k that sort right
+// after them are left out), pos = text position of the suffix at the
+// bracket's first pivot row, midpoint(T[v] - 1, T[v] + size), and next =
 // that suffix's bases k .. k+15 (its first k are v).  When none does, every
 // read that starts with v has the same result, fixed by v alone: size =
 // kPtabAnswer | l, with l < k the longest prefix of v that occurs, and
@@ -75,14 +76,7 @@ struct DevIndex {
     const PrefixEntry *ptab;   // prefix table, 4^ptab_k + 1 entries (NULL when ptab_k == 0)
     int32_t n;
     int32_t ptab_k;            // bases indexed by the prefix table (0: no table)
-    // the rows of the kShort shortest suffixes (lengths 1..kShort), ascending
-    // by row, with their lengths and first bases (zero past the text end)
-    int32_t nshort;
-    int32_t short_row[15];
-    int32_t short_len[15];
-    uint64_t short_key[15];
 };
-constexpr int kShort = 15;
 constexpr int kMaxPrefixBases = 14;
 
 struct BucketTable {

@@ -336,43 +336,21 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
 // ---- prefix table
 // The table T[v] (v a k-base string) is the first SA row whose suffix is not
 // below v.  For a query P with at least k leading ACGT bases and first k
-// bases v, every row before T[v] is below P and every row from T[v+1] on
-// is above it, so the LB search of P runs inside (T[v] - 1, T[v+1]).  Rows
-// in that bracket start with v, except suffixes shorter than k (only the
-// last k - 1 text positions), whose rows are passed in the index view.
-
-// Short suffix (length < k) whose row lies in [lo, hi), if any.
-__device__ __forceinline__ bool short_rows_in(const DevIndex &ix, int lo, int hi) {
-    bool any = false;
-#pragma unroll
-    for (int i = 0; i < kShort; ++i)
-        any |= i < ix.nshort && ix.short_len[i] < ix.ptab_k && ix.short_row[i] >= lo && ix.short_row[i] < hi;
-    return any;
-}
-
-// Index of the short suffix (length < k) at `row`, or -1.
-__device__ __forceinline__ int short_at(const DevIndex &ix, int row) {
-    int at = -1;
-#pragma unroll
-    for (int i = 0; i < kShort; ++i)
-        if (i < ix.nshort && ix.short_len[i] < ix.ptab_k && ix.short_row[i] == row) at = i;
-    return at;
-}
-
-// What the prefix-table step of a search did.
-enum class TableStep { kSearched, kAnswered, kFallback };
+// bases v, every row before T[v] is below P and every row of a suffix that
+// does not start with v after them is above it, so the LB search of P runs
+// inside the bracket of rows that start with v (see PrefixEntry).
 
 // LB search of P[0..plen) inside the table bracket of its first k bases v.
-// kAnswered: no suffix starts with v, and the entry holds the read's result
-// (ans).  kFallback: the bracket holds a short suffix (the caller searches
-// from the root).  kSearched: st holds the LB search's final state.  Rows
-// inside the bracket share k bases with P, so when the search moves a bound
-// inside, the other bound's common-prefix length (below k) never decides
-// anything and starts as 0.  The first probe takes its pivot suffix's
-// position and first k + 16 bases from the entry, with no load of its own.
+// Returns false when no suffix starts with v: the entry then holds the
+// read's result (ans).  Otherwise st holds the LB search's final state.
+// Rows inside the bracket share k bases with P, so when the search moves a
+// bound inside, the other bound's common-prefix length (below k) never
+// decides anything and starts as 0.  The first probe takes its pivot
+// suffix's position and first k + 16 bases from the entry, with no load of
+// its own.
 template <int W, class Q, class Cnt>
-__device__ __forceinline__ TableStep lb_search_table(const DevIndex &ix, const Q &q, int plen, LbState &st,
-                                                     int4 &ans, Cnt &cnt) {
+__device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, int plen, LbState &st,
+                                                int4 &ans, Cnt &cnt) {
     const int K = ix.ptab_k;
     const uint32_t v = (uint32_t)(q[0] >> (64 - 2 * K));
     const PrefixEntry ent = ix.ptab[v];
@@ -380,11 +358,10 @@ __device__ __forceinline__ TableStep lb_search_table(const DevIndex &ix, const Q
     cnt.table_probe();
     if (ent.size & kPtabAnswer) {
         ans = make_int4(ent.pos, (int)ent.next, (int)(ent.size & ~kPtabAnswer), 0);
-        return TableStep::kAnswered;
+        return false;
     }
     const int lo_k = (int)ent.row;
     const int hi_k = lo_k + (int)ent.size;
-    if (short_rows_in(ix, lo_k, hi_k)) return TableStep::kFallback;
     st.L = lo_k - 1; st.R = hi_k; st.lcpL = 0; st.lcpR = 0;
     st.Llt = -1; st.lcpLlt = 0; st.Rlt = ix.n; st.lcpRlt = 0;
     {
@@ -405,7 +382,7 @@ __device__ __forceinline__ TableStep lb_search_table(const DevIndex &ix, const Q
             compare_row<W>(ix, q, plen, ix.rows + piv, row.pos, row.key0, min_i(st.lcpL, st.lcpR), lcp, cnt);
         lb_update(st, sign, piv, lcp);
     }
-    return TableStep::kSearched;
+    return true;
 }
 
 // One read: LB search of its ACGT prefix; exact reads finish with an RB
@@ -416,13 +393,12 @@ template <int W, class Q, class Cnt>
 __device__ __forceinline__ int4 match_read(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
                            bool use_table, const Q &q, int m, int mv, Cnt &cnt) {
     LbState st;
-    TableStep step = TableStep::kFallback;
     if (use_table && ix.ptab_k > 0 && mv >= ix.ptab_k) {
         int4 ans;
-        step = lb_search_table<W>(ix, q, mv, st, ans, cnt);
-        if (step == TableStep::kAnswered) return ans;
+        if (!lb_search_table<W>(ix, q, mv, st, ans, cnt)) return ans;
+    } else {
+        lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, cnt);
     }
-    if (step != TableStep::kSearched) lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, cnt);
     if (mv == m && st.lcpR == m) {
         const int hi = bounded_search<W, true>(ix, q, m, st.R, st.Rlt, m, st.lcpRlt, cnt);
         return make_int4(st.R, hi, m, (int)kHitExact);
@@ -501,7 +477,11 @@ __global__ void fill_prefix_entries_kernel(DevIndex ix, int k, int64_t entries, 
         return;
     }
     const int lo = (int)tab[v].row;
-    const int hi = (int)tab[v + 1].row;
+    // rows [lo, T[v+1]) have order key 2v + 1 (suffixes that start with v),
+    // then 2v + 2 (suffixes shorter than k, at most k - 1, that are proper
+    // prefixes of v + 1 padded with a's); the bracket ends before the latter
+    int hi = (int)tab[v + 1].row;
+    while (hi > lo && row_head(ix.rows, hi - 1).len < k) --hi;
     if (hi > lo) {
         const RowHead h = row_head(ix.rows, midpoint(lo - 1, hi));
         tab[v].size = (uint32_t)(hi - lo);
@@ -664,6 +644,48 @@ __device__ __forceinline__ uint32_t bad_nibble(uint32_t bad) {
     return ((bad >> 7) & 1u) | ((bad >> 14) & 2u) | ((bad >> 21) & 4u) | ((bad >> 28) & 8u);
 }
 
+// 16 bytes of ASCII (four little-endian dwords, the first byte lowest) to
+// 16 two-bit codes, the first base in the top bits of codes[c], and a flag
+// bit per byte that is not a base in badm[c] (bit i for byte i), with the
+// code of such a byte 0.  When every byte is a base (either case) -- a
+// byte-wise compare with "ACGT"[code] -- the codes of each dword are
+// gathered into a byte with two shift-ors and the sixteen pairs are put in
+// order by one bit reversal and a swap within each pair; otherwise the
+// flags are worked out byte by byte.  Returns whether a byte was not a base.
+__device__ __forceinline__ uint32_t gather4(uint32_t cd) {
+    const uint32_t x = cd | (cd >> 6);  // bits 0-3: codes of bytes 0, 1; bits 16-19: bytes 2, 3
+    return (x | (x >> 12)) & 0xFFu;     // byte i's code at bits 2i, 2i+1
+}
+
+__device__ __forceinline__ bool convert_piece(const uint4 &v, uint32_t *codes, uint16_t *badm, int c) {
+    const uint32_t k0 = ((v.x >> 1) ^ (v.x >> 2)) & 0x03030303u, k1 = ((v.y >> 1) ^ (v.y >> 2)) & 0x03030303u;
+    const uint32_t k2 = ((v.z >> 1) ^ (v.z >> 2)) & 0x03030303u, k3 = ((v.w >> 1) ^ (v.w >> 2)) & 0x03030303u;
+    const uint32_t d0 = (v.x & 0xDFDFDFDFu) ^ __builtin_amdgcn_perm(0u, 0x54474341u, k0);
+    const uint32_t d1 = (v.y & 0xDFDFDFDFu) ^ __builtin_amdgcn_perm(0u, 0x54474341u, k1);
+    const uint32_t d2 = (v.z & 0xDFDFDFDFu) ^ __builtin_amdgcn_perm(0u, 0x54474341u, k2);
+    const uint32_t d3 = (v.w & 0xDFDFDFDFu) ^ __builtin_amdgcn_perm(0u, 0x54474341u, k3);
+    if ((d0 | d1 | d2 | d3) == 0) {
+        uint32_t w = gather4(k0) | (gather4(k1) << 8) | (gather4(k2) << 16) | (gather4(k3) << 24);
+        w = __builtin_bitreverse32(w);                          // base i's pair at bits 30-2i, 31-2i, swapped
+        w = ((w >> 1) & 0x55555555u) | ((w & 0x55555555u) << 1);  // base 0 in the top two bits
+        codes[c] = w;
+        badm[c] = 0;
+        return false;
+    }
+    uint32_t bad, code, bits;
+    code = pack4_fast(v.x, 0xFFFFFFFFu, bad);
+    bits = bad_nibble(bad);
+    code = (code << 8) | pack4_fast(v.y, 0xFFFFFFFFu, bad);
+    bits |= bad_nibble(bad) << 4;
+    code = (code << 8) | pack4_fast(v.z, 0xFFFFFFFFu, bad);
+    bits |= bad_nibble(bad) << 8;
+    code = (code << 8) | pack4_fast(v.w, 0xFFFFFFFFu, bad);
+    bits |= bad_nibble(bad) << 12;
+    codes[c] = code;
+    badm[c] = (uint16_t)bits;
+    return true;
+}
+
 __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restrict__ reads,
                                                           const int64_t *__restrict__ offs,
                                                           const int64_t *__restrict__ ends, int64_t nreads,
@@ -691,20 +713,7 @@ __global__ __launch_bounds__(kPackBlock) void pack_kernel(const uint8_t *__restr
         // coalesced loads, converted on the way into LDS
         const int nvec = (int)((A1 - A0) >> 4);
         const uint4 *src = reinterpret_cast<const uint4 *>(A0);
-        for (int c = threadIdx.x; c < nvec; c += kPackBlock) {
-            const uint4 v = src[c];
-            uint32_t bad, code, bits;
-            code = pack4_fast(v.x, 0xFFFFFFFFu, bad);
-            bits = bad_nibble(bad);
-            code = (code << 8) | pack4_fast(v.y, 0xFFFFFFFFu, bad);
-            bits |= bad_nibble(bad) << 4;
-            code = (code << 8) | pack4_fast(v.z, 0xFFFFFFFFu, bad);
-            bits |= bad_nibble(bad) << 8;
-            code = (code << 8) | pack4_fast(v.w, 0xFFFFFFFFu, bad);
-            bits |= bad_nibble(bad) << 12;
-            codes[c] = code;
-            badm[c] = (uint16_t)bits;
-        }
+        for (int c = threadIdx.x; c < nvec; c += kPackBlock) convert_piece(src[c], codes, badm, c);
     }
     __syncthreads();
     uint64_t w[kWMax];
@@ -892,7 +901,7 @@ __device__ __forceinline__ Span chunk_span(const uint8_t *__restrict__ reads, bo
 // holds pieces l, l + 64, ...); the rest of a longer span is loaded when it
 // is converted.
 #ifndef SAMATCH_INLINE_AHEAD
-#define SAMATCH_INLINE_AHEAD 6
+#define SAMATCH_INLINE_AHEAD 4
 #endif
 constexpr int kInlineAhead = SAMATCH_INLINE_AHEAD;
 
@@ -909,29 +918,17 @@ __device__ __forceinline__ void span_prefetch(const Span &sp, int lane, uint4 (&
     }
 }
 
-__device__ __forceinline__ void convert_piece(const uint4 &v, uint32_t *codes, uint16_t *badm, int c) {
-    uint32_t bad, code, bits;
-    code = pack4_fast(v.x, 0xFFFFFFFFu, bad);
-    bits = bad_nibble(bad);
-    code = (code << 8) | pack4_fast(v.y, 0xFFFFFFFFu, bad);
-    bits |= bad_nibble(bad) << 4;
-    code = (code << 8) | pack4_fast(v.z, 0xFFFFFFFFu, bad);
-    bits |= bad_nibble(bad) << 8;
-    code = (code << 8) | pack4_fast(v.w, 0xFFFFFFFFu, bad);
-    bits |= bad_nibble(bad) << 12;
-    codes[c] = code;
-    badm[c] = (uint16_t)bits;
-}
-
 // The staged span as codes and flags in the wave's area: the prefetched
-// pieces, then the rest (four loads in flight per lane).
+// pieces, then the rest (four loads in flight per lane).  Returns, the same
+// for every lane, whether any byte of the span was not a base.
 template <class Cnt>
-__device__ __forceinline__ void span_convert(const Span &sp, const uint4 (&v)[kInlineAhead], uint32_t *codes,
+__device__ __forceinline__ bool span_convert(const Span &sp, const uint4 (&v)[kInlineAhead], uint32_t *codes,
                                              uint16_t *badm, int lane, Cnt &cnt) {
+    bool bad = false;
 #pragma unroll
     for (int u = 0; u < kInlineAhead; ++u) {
         const int c = 64 * u + lane;
-        if (c < sp.nvec) convert_piece(v[u], codes, badm, c);
+        if (c < sp.nvec) bad |= convert_piece(v[u], codes, badm, c);
     }
     const uint4 *src = reinterpret_cast<const uint4 *>(sp.A0);
     for (int c0 = 64 * kInlineAhead; c0 < sp.nvec; c0 += 4 * 64) {
@@ -947,9 +944,10 @@ __device__ __forceinline__ void span_convert(const Span &sp, const uint4 (&v)[kI
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = c0 + 64 * u + lane;
-            if (c < sp.nvec) convert_piece(r[u], codes, badm, c);
+            if (c < sp.nvec) bad |= convert_piece(r[u], codes, badm, c);
         }
     }
+    return __any(bad);
 }
 
 // LDS written by this wave's lanes is visible to its other lanes.
@@ -960,9 +958,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Words and first non-base of a read of m bases starting st0 bytes into a
-// staged code stream.
+// staged code stream (scan = false: the span has no non-base byte).
 __device__ __forceinline__ void inline_extract(const uint32_t *codes, const uint16_t *badm, uint32_t st0, int m,
-                                               uint64_t (&w)[kWMax], int &mv) {
+                                               uint64_t (&w)[kWMax], int &mv, bool scan) {
 #pragma unroll
     for (int k = 0; k < kWMax; ++k) {
         if (32 * k < m) {
@@ -975,7 +973,7 @@ __device__ __forceinline__ void inline_extract(const uint32_t *codes, const uint
         }
     }
     mv = m;
-    if (m > 0) {
+    if (scan && m > 0) {
         const uint32_t q0 = st0 >> 4, q1 = (st0 + (uint32_t)m - 1) >> 4;
         for (uint32_t q = q0; q <= q1; ++q) {
             uint32_t bits = badm[q];
@@ -1089,8 +1087,9 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
             const int m = (m64 >= 0 && m64 <= kShortMax) ? (int)m64 : -1;
             if (long_read) b.stats[kLongFlag] = 1ull;
             const bool short_read = active && !long_read;
+            bool scan = false;
             if (sp0.staged) {
-                span_convert(sp0, v, w_codes, w_badm, lane, cnt);
+                scan = span_convert(sp0, v, w_codes, w_badm, lane, cnt);
                 wave_lds_sync();
             }
             uint64_t w[kWMax];
@@ -1099,7 +1098,7 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
             int mv = m;
             if (short_read && m > 0) {
                 if (sp0.staged && a0 >= sp0.s0 && e0 <= sp0.s1) {
-                    inline_extract(w_codes, w_badm, (uint32_t)((uintptr_t)(reads + a0) - sp0.A0), m, w, mv);
+                    inline_extract(w_codes, w_badm, (uint32_t)((uintptr_t)(reads + a0) - sp0.A0), m, w, mv, scan);
                 } else {
                     uint64_t g[kWMax + 1];
                     pack_from_global(reads, a0, m, g, mv, g[kWMax]);
@@ -1599,6 +1598,7 @@ hipError_t prepare_kernels() {
 }
 
 size_t inline_lds_limit() { return g_inline_lds.load(); }
+
 
 hipError_t launch_search_st(const uint64_t *text, const int32_t *sa, int32_t n, const StNode *nodes, int32_t root,
                             const uint8_t *reads, const int64_t *offs, int64_t nreads, void *out, int grid,
