@@ -157,8 +157,8 @@ enum { SA_KERNEL_TUNED = 0, SA_KERNEL_PLAIN = 1 };
 
 /* Launch configuration.  A NULL configuration means the index's defaults
  * (sa_tune's choice once it has run, else built-in ones).  In a given one,
- * a zero tile_levels, block, blocks_per_cu, group or nbuckets takes the
- * index's default; every other field is used as given. */
+ * a zero tile_levels, block, blocks_per_cu, group, nbuckets or max_words
+ * takes the index's default; every other field is used as given. */
 typedef struct {
     int kernel;          /* SA_KERNEL_TUNED or SA_KERNEL_PLAIN                     */
     int tile_levels;     /* tuned: levels of the search tree held in LDS (1..13)   */
@@ -188,6 +188,12 @@ typedef struct {
                             from ASCII itself (no separate pack pass), when its
                             tile and packing areas fit in LDS (160 KB);
                             0 = a pack pass first                               */
+    int max_words;       /* tuned, with inline_pack: 64-bit words of a read the
+                            search kernel holds in registers, 5 or 10 (reads of
+                            up to 160 or 320 bases; longer ones go to the
+                            long-read kernel).  5 keeps fewer registers live so
+                            that more waves fit a compute unit; 0 = the
+                            index's default                                     */
 } sa_match_cfg;
 
 /* Fill cfg with the index's current defaults. */

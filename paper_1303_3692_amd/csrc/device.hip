@@ -145,6 +145,8 @@ int check_cfg(const sa_dindex *d, const sa_match_cfg &c) {
     if (c.sort != 0 && c.sort != 1 && c.sort != 8 && c.sort != 16 && c.sort != 24)
         return fail(SA_EINVAL, "sort must be 0, 1, 8, 16 or 24");
     if (c.inline_pack != 0 && c.inline_pack != 1) return fail(SA_EINVAL, "inline_pack must be 0 or 1");
+    if (c.max_words != kShortWords && c.max_words != kWMax)
+        return fail(SA_EINVAL, "max_words must be " + std::to_string(kShortWords) + " or " + std::to_string(kWMax));
     for (int i = 0; i + 1 < c.nbuckets; i++)
         if (c.bucket_edge[i] < 1 || (i > 0 && c.bucket_edge[i] <= c.bucket_edge[i - 1]))
             return fail(SA_EINVAL, "bucket edges must ascend");
@@ -159,6 +161,7 @@ sa_match_cfg resolve_cfg(const sa_dindex *d, const sa_match_cfg *cfg) {
         if (c.block == 0) c.block = def.block;
         if (c.blocks_per_cu == 0) c.blocks_per_cu = def.blocks_per_cu;
         if (c.group == 0) c.group = def.group;
+        if (c.max_words == 0) c.max_words = def.max_words;
         if (c.nbuckets == 0) {
             c.nbuckets = def.nbuckets;
             std::memcpy(c.bucket_edge, def.bucket_edge, sizeof c.bucket_edge);
@@ -239,14 +242,14 @@ int enqueue_pipeline(sa_dindex *d, const BatchBuffers &b, const hipEvent_t *ev, 
         const int group = (int)std::max<int64_t>(1, std::min<int64_t>(c.group, chunks / gmax));
         const int grid = (int)std::min<int64_t>(gmax, (chunks + group - 1) / group);
         e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, group, b, order,
-                                inl ? d_reads : nullptr, inl ? d_offs : nullptr, inl ? d_ends : nullptr, nreads, d_out,
-                                c.count != 0, s);
+                                inl ? d_reads : nullptr, inl ? d_offs : nullptr, inl ? d_ends : nullptr, nreads,
+                                inl ? c.max_words : kWMax, d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
     }
     // reads longer than kShortMax: their own kernel, over the tail of the sorted order
     const uint32_t long_field = (long_read_key(c.nbuckets) >> key_shift) & key_mask;
     e = launch_search_long(d->view, d_reads, d_offs, b, order, sorted_key, key_shift, key_mask, long_field,
-                           c.prefix_table, inl, inl ? d_ends : nullptr,
+                           c.prefix_table, inl, 32 * (inl ? c.max_words : kWMax), inl ? d_ends : nullptr,
                            (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)d->cu_count * 8, (nreads + 63) / 64)),
                            nreads, d_out, c.count != 0, s);
     if (e != hipSuccess) return hip_fail(e, "long-read search launch");
@@ -420,6 +423,7 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
     c.group = 4;
     c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
     c.inline_pack = 1;
+    c.max_words = kWMax;
     *out = d.release();
     return SA_OK;
 }

@@ -9,6 +9,7 @@
 namespace samatch {
 
 constexpr int kWMax = 10;                 // packed words per read slot of the short-read path
+constexpr int kShortWords = 5;            // query words of the search kernel's register-light instance
 constexpr int kShortMax = kWMax * 32;     // longest read of the short-read path (320 bases)
 constexpr int kLongWords = SA_MAX_READ / 32;  // words of a read on the long-read path
 constexpr int kStatWords = 11;
@@ -129,10 +130,12 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi
 // cleared before, see launch_clear_stats); the dynamic LDS is then
 // tuned_lds_bytes(tile_levels, block, true), which must not exceed
 // inline_lds_limit().
+// words: query words a read may hold (kShortWords or kWMax); with offs,
+// longer reads are left to launch_search_long (long_min = 32 * words).
 hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int use_table, int block, int grid,
                                int group, const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
-                               const int64_t *offs, const int64_t *ends, int64_t nreads, void *out, bool count,
-                               hipStream_t s);
+                               const int64_t *offs, const int64_t *ends, int64_t nreads, int words, void *out,
+                               bool count, hipStream_t s);
 
 // Most dynamic LDS an inline-packing tuned kernel may take on the device
 // that prepare_kernels last ran on (0 before).
@@ -152,11 +155,11 @@ hipError_t launch_search_plain(const DevIndex &ix, const BatchBuffers &b, int64_
 // Read i starts at reads[offs[i]] (offs holds the start array in gather mode).
 // lengths_from_offs: take each read's length from offs (and ends, when not
 // NULL) instead of the pack kernel's record (when the search kernel packed
-// its reads).
+// its reads); a read is then long when it has more than long_min bases.
 hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b,
                               const uint32_t *order, const uint32_t *sorted_key, int key_shift, uint32_t key_mask,
-                              uint32_t long_field, int use_table, bool lengths_from_offs, const int64_t *ends,
-                              int grid, int64_t nreads, void *out, bool count, hipStream_t s);
+                              uint32_t long_field, int use_table, bool lengths_from_offs, int long_min,
+                              const int64_t *ends, int grid, int64_t nreads, void *out, bool count, hipStream_t s);
 
 // Suffix-tree search, one read per lane, reads in input order, each packed
 // into LDS by its wave (reads of up to SA_MAX_READ bases).

@@ -827,9 +827,9 @@ __device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_
 }
 
 // tuned_one for a read whose packed words are already in registers.
-template <int W, class Cnt>
+template <int W, int N, class Cnt>
 __device__ __forceinline__ void tuned_regs(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa,
-                                           int levels, bool use_table, const uint64_t (&w)[kWMax], int rid, int m,
+                                           int levels, bool use_table, const uint64_t (&w)[N], int rid, int m,
                                            int mv, int4 *out, Cnt &cnt) {
     if (m < 0) {
         out[rid] = make_int4(0, 0, 0, (int)kHitTooLong);
@@ -905,11 +905,11 @@ __device__ __forceinline__ Span chunk_span(const uint8_t *__restrict__ reads, bo
 #endif
 constexpr int kInlineAhead = SAMATCH_INLINE_AHEAD;
 
-template <class Cnt>
-__device__ __forceinline__ void span_prefetch(const Span &sp, int lane, uint4 (&v)[kInlineAhead], Cnt &cnt) {
+template <int AHEAD, class Cnt>
+__device__ __forceinline__ void span_prefetch(const Span &sp, int lane, uint4 (&v)[AHEAD], Cnt &cnt) {
     const uint4 *src = reinterpret_cast<const uint4 *>(sp.A0);
 #pragma unroll
-    for (int u = 0; u < kInlineAhead; ++u) {
+    for (int u = 0; u < AHEAD; ++u) {
         const int c = 64 * u + lane;
         if (c < sp.nvec) {
             v[u] = src[c];
@@ -921,17 +921,17 @@ __device__ __forceinline__ void span_prefetch(const Span &sp, int lane, uint4 (&
 // The staged span as codes and flags in the wave's area: the prefetched
 // pieces, then the rest (four loads in flight per lane).  Returns, the same
 // for every lane, whether any byte of the span was not a base.
-template <class Cnt>
-__device__ __forceinline__ bool span_convert(const Span &sp, const uint4 (&v)[kInlineAhead], uint32_t *codes,
+template <int AHEAD, class Cnt>
+__device__ __forceinline__ bool span_convert(const Span &sp, const uint4 (&v)[AHEAD], uint32_t *codes,
                                              uint16_t *badm, int lane, Cnt &cnt) {
     bool bad = false;
 #pragma unroll
-    for (int u = 0; u < kInlineAhead; ++u) {
+    for (int u = 0; u < AHEAD; ++u) {
         const int c = 64 * u + lane;
         if (c < sp.nvec) bad |= convert_piece(v[u], codes, badm, c);
     }
     const uint4 *src = reinterpret_cast<const uint4 *>(sp.A0);
-    for (int c0 = 64 * kInlineAhead; c0 < sp.nvec; c0 += 4 * 64) {
+    for (int c0 = 64 * AHEAD; c0 < sp.nvec; c0 += 4 * 64) {
         uint4 r[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -959,10 +959,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Words and first non-base of a read of m bases starting st0 bytes into a
 // staged code stream (scan = false: the span has no non-base byte).
+template <int N>
 __device__ __forceinline__ void inline_extract(const uint32_t *codes, const uint16_t *badm, uint32_t st0, int m,
-                                               uint64_t (&w)[kWMax], int &mv, bool scan) {
+                                               uint64_t (&w)[N], int &mv, bool scan) {
 #pragma unroll
-    for (int k = 0; k < kWMax; ++k) {
+    for (int k = 0; k < N; ++k) {
         if (32 * k < m) {
             const uint32_t bpos = st0 + 32u * (uint32_t)k, q = bpos >> 4, r = bpos & 15u;
             const uint64_t hi = ((uint64_t)codes[q] << 32) | codes[q + 1];
@@ -1023,9 +1024,13 @@ __device__ __forceinline__ int64_t workgroup_rank() {
 //
 // INLINE: the kernel packs its reads itself from the ASCII buffer and CSR
 // offsets (reads in input order; no pack kernel ran), each wave in its own
-// LDS area after the tile.
-template <int BLOCK, bool COUNT, bool INLINE>
-__global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group,
+// LDS area after the tile.  WQ: query words a read may hold in registers
+// (reads of up to 32 * WQ bases; longer ones are the long-read kernel's).
+// The 5-word instance keeps fewer registers live (and prefetches less of
+// the next chunk), so that six waves fit each SIMD (the counting instance is
+// not held to that).
+template <int BLOCK, bool COUNT, bool INLINE, int WQ>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WQ < kWMax && !COUNT ? 6 : 1))) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group,
                                                              BatchBuffers b, const uint32_t *__restrict__ order,
                                                              const uint8_t *__restrict__ reads,
                                                              const int64_t *__restrict__ offs,
@@ -1070,7 +1075,9 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
         int64_t c0 = take(), a0, e0;
         chunk_offsets(offs, ends, c0, nreads, lane, a0, e0);
         Span sp0 = chunk_span(reads, ends != nullptr, c0, nreads, lane, a0, e0);
-        uint4 v[kInlineAhead];
+        constexpr int AHEAD = WQ < kWMax ? 2 : kInlineAhead;
+        constexpr int kMaxM = 32 * WQ;  // longest read searched here
+        uint4 v[AHEAD];
         span_prefetch(sp0, lane, v, cnt);
         int64_t c1 = c0 >= 0 ? take() : -1, a1, e1;
         chunk_offsets(offs, ends, c1, nreads, lane, a1, e1);
@@ -1083,8 +1090,8 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
             }
             const int64_t m64 = e0 - a0;
             // m = -1: length out of range (the too-long result); long reads are the long kernel's
-            const bool long_read = active && m64 > kShortMax && m64 <= SA_MAX_READ;
-            const int m = (m64 >= 0 && m64 <= kShortMax) ? (int)m64 : -1;
+            const bool long_read = active && m64 > kMaxM && m64 <= SA_MAX_READ;
+            const int m = (m64 >= 0 && m64 <= kMaxM) ? (int)m64 : -1;
             if (long_read) b.stats[kLongFlag] = 1ull;
             const bool short_read = active && !long_read;
             bool scan = false;
@@ -1092,9 +1099,9 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
                 scan = span_convert(sp0, v, w_codes, w_badm, lane, cnt);
                 wave_lds_sync();
             }
-            uint64_t w[kWMax];
+            uint64_t w[WQ];
 #pragma unroll
-            for (int t = 0; t < kWMax; ++t) w[t] = 0;
+            for (int t = 0; t < WQ; ++t) w[t] = 0;
             int mv = m;
             if (short_read && m > 0) {
                 if (sp0.staged && a0 >= sp0.s0 && e0 <= sp0.s1) {
@@ -1103,7 +1110,7 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
                     uint64_t g[kWMax + 1];
                     pack_from_global(reads, a0, m, g, mv, g[kWMax]);
 #pragma unroll
-                    for (int t = 0; t < kWMax; ++t) w[t] = (32 * t < m) ? g[t] : 0;
+                    for (int t = 0; t < WQ; ++t) w[t] = (32 * t < m) ? g[t] : 0;
                 }
             }
             if (sp0.staged) wave_lds_sync();  // every lane has its words before the area is reused
@@ -1116,7 +1123,7 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
             const int wn = max_i(1, (m + 31) >> 5);
             int wc = 1;
 #pragma unroll
-            for (int t = 2; t <= kWMax; ++t)
+            for (int t = 2; t <= WQ; ++t)
                 if (wave_ballot(short_read && wn >= t)) wc = t;
             if (short_read) {
                 if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
@@ -1127,11 +1134,17 @@ __global__ __launch_bounds__(BLOCK) void search_tuned_kernel(DevIndex ix, int le
                     case 3: tuned_regs<3>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
                     case 4: tuned_regs<4>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
                     case 5: tuned_regs<5>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                    case 6: tuned_regs<6>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                    case 7: tuned_regs<7>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                    case 8: tuned_regs<8>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                    case 9: tuned_regs<9>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                    default: tuned_regs<10>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    default:
+                        if constexpr (WQ >= 10) {
+                            switch (wc) {
+                                case 6: tuned_regs<6>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                                case 7: tuned_regs<7>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                                case 8: tuned_regs<8>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                                case 9: tuned_regs<9>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                                default: tuned_regs<10>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                            }
+                        }
+                        break;
                 }
             }
             c0 = c1;
@@ -1273,9 +1286,9 @@ __global__ __launch_bounds__(256) void search_plain_kernel(DevIndex ix, BatchBuf
 // from the device's limit per workgroup).
 std::atomic<size_t> g_inline_lds{0};
 
-template <int BLOCK, bool COUNT, bool INLINE>
+template <int BLOCK, bool COUNT, bool INLINE, int WQ = kWMax>
 hipError_t allow_tile_lds(size_t inline_lds) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&search_tuned_kernel<BLOCK, COUNT, INLINE>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&search_tuned_kernel<BLOCK, COUNT, INLINE, WQ>),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                INLINE ? (int)inline_lds : (int)tile_lds_bytes(kMaxTileLevels));
 }
@@ -1283,14 +1296,18 @@ hipError_t allow_tile_lds(size_t inline_lds) {
 template <int BLOCK, bool COUNT>
 hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int group, int grid, const BatchBuffers &b,
                               const uint32_t *order, const uint8_t *reads, const int64_t *offs, const int64_t *ends,
-                              int64_t nreads, int4 *out, hipStream_t s) {
+                              int64_t nreads, int words, int4 *out, hipStream_t s) {
     if (offs) {
         const size_t lds = tuned_lds_bytes(levels, BLOCK, true);
         if (lds > g_inline_lds.load()) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, true>), dim3(grid), dim3(BLOCK), lds, s, ix, levels,
-                           use_table, group, b, order, reads, offs, ends, nreads, out);
+        if (words == kShortWords)
+            hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, true, kShortWords>), dim3(grid), dim3(BLOCK), lds, s,
+                               ix, levels, use_table, group, b, order, reads, offs, ends, nreads, out);
+        else
+            hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, true, kWMax>), dim3(grid), dim3(BLOCK), lds, s, ix,
+                               levels, use_table, group, b, order, reads, offs, ends, nreads, out);
     } else {
-        hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, false>), dim3(grid), dim3(BLOCK),
+        hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, false, kWMax>), dim3(grid), dim3(BLOCK),
                            tile_lds_bytes(levels), s, ix, levels, use_table, group, b, order, reads, offs, ends,
                            nreads, out);
     }
@@ -1406,8 +1423,9 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
                                                          const uint32_t *__restrict__ order,
                                                          const uint32_t *__restrict__ sorted_key, int key_shift,
                                                          uint32_t key_mask, uint32_t long_field, int use_table_i,
-                                                         int lengths_from_offs, const int64_t *__restrict__ ends,
-                                                         int64_t nreads, int4 *__restrict__ out) {
+                                                         int lengths_from_offs, int long_min,
+                                                         const int64_t *__restrict__ ends, int64_t nreads,
+                                                         int4 *__restrict__ out) {
     __shared__ uint64_t slot[64][kLongWords];
     __shared__ int64_t s_first;
     const int lane = threadIdx.x;
@@ -1436,9 +1454,9 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         const bool act = j < nreads;
         const int rid = act ? (order ? (int)order[j] : (int)j) : 0;
         ReadLen lm;
-        if (lengths_from_offs) {  // input order, CSR offsets: a read of kShortMax+1 .. SA_MAX_READ bases is long
+        if (lengths_from_offs) {  // input order, CSR offsets: a read of long_min+1 .. SA_MAX_READ bases is long
             const int64_t m64 = act ? (ends ? ends[rid] : offs[rid + 1]) - offs[rid] : -1;
-            const bool lng = m64 > kShortMax && m64 <= SA_MAX_READ;
+            const bool lng = m64 > long_min && m64 <= SA_MAX_READ;
             lm = decode_len(encode_len(lng ? (int)m64 : -1, lng ? -1 : 0, 0));
             if (COUNT && act) cnt.touch(offs + rid, 16);
         } else {
@@ -1591,7 +1609,11 @@ hipError_t prepare_kernels() {
         (e = allow_tile_lds<256, false, true>(inline_lds)) != hipSuccess ||
         (e = allow_tile_lds<512, false, true>(inline_lds)) != hipSuccess ||
         (e = allow_tile_lds<1024, false, true>(inline_lds)) != hipSuccess ||
-        (e = allow_tile_lds<256, true, true>(inline_lds)) != hipSuccess)
+        (e = allow_tile_lds<256, true, true>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<256, false, true, kShortWords>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<512, false, true, kShortWords>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<1024, false, true, kShortWords>(inline_lds)) != hipSuccess ||
+        (e = allow_tile_lds<256, true, true, kShortWords>(inline_lds)) != hipSuccess)
         return e;
     g_inline_lds.store(inline_lds);
     return hipSuccess;
@@ -1637,23 +1659,24 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi
 
 hipError_t launch_search_tuned(const DevIndex &ix, int levels, int use_table, int block, int grid, int group,
                                const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
-                               const int64_t *offs, const int64_t *ends, int64_t nreads, void *out, bool count,
-                               hipStream_t s) {
+                               const int64_t *offs, const int64_t *ends, int64_t nreads, int words, void *out,
+                               bool count, hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
     if (group < 1 || (offs && order)) return hipErrorInvalidValue;
+    if (words != kShortWords && words != kWMax) return hipErrorInvalidValue;
     if (count)  // counts do not depend on the workgroup shape or the work split
         return launch_tuned_block<256, true>(ix, levels, use_table, group, grid * (block / 256), b, order, reads, offs,
-                                             ends, nreads, o, s);
+                                             ends, nreads, words, o, s);
     switch (block) {
         case 256:
             return launch_tuned_block<256, false>(ix, levels, use_table, group, grid, b, order, reads, offs, ends, nreads,
-                                                   o, s);
+                                                   words, o, s);
         case 512:
             return launch_tuned_block<512, false>(ix, levels, use_table, group, grid, b, order, reads, offs, ends, nreads,
-                                                   o, s);
+                                                   words, o, s);
         case 1024:
             return launch_tuned_block<1024, false>(ix, levels, use_table, group, grid, b, order, reads, offs, ends, nreads,
-                                                   o, s);
+                                                   words, o, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1669,18 +1692,18 @@ hipError_t launch_build_prefix_table(const DevIndex &ix, int k, PrefixEntry *tab
 
 hipError_t launch_search_long(const DevIndex &ix, const uint8_t *reads, const int64_t *offs, const BatchBuffers &b,
                               const uint32_t *order, const uint32_t *sorted_key, int key_shift, uint32_t key_mask,
-                              uint32_t long_field, int use_table, bool lengths_from_offs, const int64_t *ends,
-                              int grid, int64_t nreads, void *out, bool count, hipStream_t s) {
+                              uint32_t long_field, int use_table, bool lengths_from_offs, int long_min,
+                              const int64_t *ends, int grid, int64_t nreads, void *out, bool count, hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
     const dim3 g((unsigned)(grid > 0 ? grid : 1));
     if (lengths_from_offs && order) return hipErrorInvalidValue;
     const int lfo = lengths_from_offs ? 1 : 0;
     if (count)
         hipLaunchKernelGGL(search_long_kernel<true>, g, dim3(64), 0, s, ix, reads, offs, b, order, sorted_key,
-                           key_shift, key_mask, long_field, use_table, lfo, ends, nreads, o);
+                           key_shift, key_mask, long_field, use_table, lfo, long_min, ends, nreads, o);
     else
         hipLaunchKernelGGL(search_long_kernel<false>, g, dim3(64), 0, s, ix, reads, offs, b, order, sorted_key,
-                           key_shift, key_mask, long_field, use_table, lfo, ends, nreads, o);
+                           key_shift, key_mask, long_field, use_table, lfo, long_min, ends, nreads, o);
     return hipGetLastError();
 }
 

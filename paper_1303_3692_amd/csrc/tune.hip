@@ -52,7 +52,7 @@ std::string cfg_json(const sa_match_cfg &c) {
     std::ostringstream o;
     o << "\"tile_levels\":" << c.tile_levels << ",\"block\":" << c.block << ",\"blocks_per_cu\":" << c.blocks_per_cu
       << ",\"group\":" << c.group << ",\"prefix_table\":" << c.prefix_table << ",\"sort\":" << c.sort
-      << ",\"inline_pack\":" << c.inline_pack
+      << ",\"inline_pack\":" << c.inline_pack << ",\"max_words\":" << c.max_words
       << ",\"nbuckets\":" << c.nbuckets << ",\"bucket_edge\":[";
     for (int i = 0; i < c.nbuckets; i++) o << (i ? "," : "") << c.bucket_edge[i];
     o << "]";
@@ -83,6 +83,7 @@ bool parse_cached(const std::string &path, const std::string &key, sa_match_cfg 
         c.prefix_table = json_int(line, "prefix_table", 0);
         c.sort = json_int(line, "sort", 1);
         c.inline_pack = json_int(line, "inline_pack", 1);
+        c.max_words = json_int(line, "max_words", kWMax);
         c.nbuckets = std::max(1, std::min(8, json_int(line, "nbuckets", 1)));
         const size_t p = line.find("\"bucket_edge\":[");
         if (p != std::string::npos) {
@@ -156,6 +157,7 @@ sa_match_cfg base_cfg(const sa_dindex *d) {
     c.inline_pack = 1;
     c.group = 4;
     c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
+    c.max_words = kWMax;
     return c;
 }
 
@@ -214,6 +216,31 @@ std::vector<sa_match_cfg> stage1b_candidates(const sa_dindex *d, const sa_match_
     return out;
 }
 
+// Stage 1c, when nearly every read of the batch fits kShortWords words
+// (the rest go to the long-read kernel): the register-light search kernel
+// in the workgroup shapes that fill its six waves per SIMD, around the best
+// so far, with a tile of at most 8 levels when the index has a prefix
+// table (so that the workgroups' LDS lets that many waves in).
+std::vector<sa_match_cfg> stage1c_candidates(const sa_dindex *d, const sa_match_cfg &top,
+                                             const std::vector<int64_t> &hist) {
+    std::vector<sa_match_cfg> out;
+    int64_t total = 0, fit = 0;
+    for (size_t i = 0; i < hist.size(); i++) {
+        total += hist[i];
+        if ((int)i <= kShortWords) fit += hist[i];
+    }
+    if (top.sort != 0 || !top.inline_pack || fit * 100 < total * 99) return out;
+    for (const auto &shape : std::vector<std::pair<int, int>>{{512, 3}, {256, 6}, {256, 5}, {1024, 1}}) {
+        sa_match_cfg c = top;
+        c.max_words = kShortWords;
+        if (d->view.ptab_k > 0) c.tile_levels = std::min(c.tile_levels, 8);
+        c.block = shape.first;
+        c.blocks_per_cu = shape.second;
+        out.push_back(c);
+    }
+    return out;
+}
+
 // Stage 2, around the best so far: bucket layouts.  Buckets only order the
 // reads through the sort keys, so they are tried only when the reads are
 // sorted.
@@ -245,6 +272,7 @@ extern "C" int sa_tune_candidates(const sa_dindex *d, const int64_t *d_offs, int
     const sa_match_cfg top = resolve_cfg(d, around);
     std::vector<sa_match_cfg> all = stage1_candidates(d);
     for (const auto &c : stage1b_candidates(d, top)) all.push_back(c);
+    for (const auto &c : stage1c_candidates(d, top, hist)) all.push_back(c);
     sa_match_cfg sorted = top;
     if (sorted.sort == 0) sorted.sort = 1;
     for (const auto &c : stage2_candidates(sorted, hist)) all.push_back(c);
@@ -333,9 +361,10 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
         ms = best_rep;
         if (std::getenv("SAMATCH_TUNE_LOG"))
             std::fprintf(stderr,
-                         "tune: levels=%d block=%d per_cu=%d group=%d table=%d sort=%d inline=%d buckets=%d -> %.4f ms\n",
+                         "tune: levels=%d block=%d per_cu=%d group=%d table=%d sort=%d inline=%d words=%d buckets=%d -> "
+                         "%.4f ms\n",
                          c.tile_levels, c.block, c.blocks_per_cu, c.group, c.prefix_table, c.sort, c.inline_pack,
-                         c.nbuckets, ms);
+                         c.max_words, c.nbuckets, ms);
         return SA_OK;
     };
     auto try_all = [&](const std::vector<sa_match_cfg> &cands) -> int {
@@ -350,6 +379,7 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
     };
     rc = try_all(stage1_candidates(d));
     if (rc == SA_OK) rc = try_all(stage1b_candidates(d, top));
+    if (rc == SA_OK) rc = try_all(stage1c_candidates(d, top, hist));
     if (rc == SA_OK) rc = try_all(stage2_candidates(top, hist));
     if (rc == SA_OK && top_ms >= 1e30) rc = fail(SA_EINVAL, "tuner: no valid candidate");
     if (rc == SA_OK) {

@@ -60,6 +60,9 @@ CONFIGS = [
     ("tuned-pack-pass", dict(sort=0, inline_pack=0)),
     ("tuned-inline-t12-b1024", dict(tile_levels=12, block=1024, blocks_per_cu=1, sort=0, inline_pack=1)),
     ("tuned-inline-no-table", dict(prefix_table=0, sort=0, inline_pack=1, group=1)),
+    ("tuned-words5-b512", dict(max_words=5, sort=0, inline_pack=1, block=512, blocks_per_cu=3)),
+    ("tuned-words5-b256-no-table", dict(max_words=5, sort=0, inline_pack=1, prefix_table=0, block=256,
+                                        blocks_per_cu=6, group=1)),
 ]
 
 
@@ -283,9 +286,9 @@ def test_inline_pack_spans(device):
     sa = oracle.sa_build(text)
     data, offs = oracle.pack_reads(reads)
     want = oracle.match(text, sa, data, offs)
-    variants = [S.cfg(d, sort=0, inline_pack=v) for v in (1, 0)]
+    variants = [S.cfg(d, sort=0, inline_pack=v) for v in (1, 0)] + [S.cfg(d, sort=0, inline_pack=1, max_words=5)]
     for c in variants:
-        assert_same(run_dev(d, data[:-1], offs, device, c), want, f"inline={c.inline_pack}")
+        assert_same(run_dev(d, data[:-1], offs, device, c), want, f"inline={c.inline_pack}/{c.max_words}")
         # the same reads 5 bytes into the buffer
         shifted = np.concatenate([np.frombuffer(b"NNNNN", np.uint8), data[:-1]])
         assert_same(run_dev(d, shifted, offs + 5, device, c), want, f"shifted inline={c.inline_pack}")

@@ -77,3 +77,36 @@ def test_tuner_run_keeps_a_matching_configuration(device, workload):
     S.match_batch_dev(d, d_reads, d_offs, d_out)
     torch.cuda.synchronize()
     assert_same(d_out.cpu().numpy(), want, f"tuned {best.as_dict()}")
+
+
+def test_short_read_candidates(device):
+    """A batch of 150-base reads (the 250 Mbp recipe's reads, on a 2 Mbp
+    text of that recipe) adds the register-light 5-word kernel to the
+    candidates; each gives the oracle's bits, and so do reads longer than
+    160 bases mixed in, which that kernel leaves to the long-read kernel."""
+    ref = gen.make_reference("c4", n=2_000_000)
+    reads = gen.make_reads(ref, gen.READ_SPECS["c4"], 50_000)
+    text = ref.ascii()
+    sa = oracle.sa_build(text)
+    want = oracle.match(text, sa, reads.data, reads.offs)
+    d = S.sa_build_device(text, 0)
+    d_reads = torch.from_numpy(reads.data).to(device)
+    d_offs = torch.from_numpy(reads.offs).to(device)
+    cands = [c for c in S.sa_tune_candidates(d, d_offs) if c.max_words == 5]
+    say(f"case: {len(cands)} five-word candidates")
+    assert len(cands) >= 3
+    for i, c in enumerate(cands):
+        d_out = torch.full((reads.count, 4), -7, dtype=torch.int32, device=device)
+        S.match_batch_dev(d, d_reads, d_offs, d_out, config=c)
+        torch.cuda.synchronize()
+        assert_same(d_out.cpu().numpy(), want, f"candidate {i}: {c.as_dict()}")
+    # 150-base reads with one read of 161-320 bases in every 7: the latter take the long-read kernel
+    mixed = gen.make_reads(ref, gen.ReadSpec(4, 7_000, 161, 320, 0.2, 0.01, 0.01))
+    data = np.concatenate([reads.data, mixed.data])
+    offs = np.concatenate([reads.offs, reads.offs[-1] + mixed.offs[1:]])
+    want2 = oracle.match(text, sa, data, offs)
+    d_out = torch.full((len(offs) - 1, 4), -7, dtype=torch.int32, device=device)
+    S.match_batch_dev(d, torch.from_numpy(data).to(device), torch.from_numpy(offs).to(device), d_out,
+                      config=cands[0])
+    torch.cuda.synchronize()
+    assert_same(d_out.cpu().numpy(), want2, "five words, longer reads mixed in")
