@@ -200,11 +200,13 @@ def main():
 
     def packs_inline(c):
         # the search kernel packs the reads itself (no pack pass) when the
-        # batch is in input order and its tile plus one 4640-byte packing
-        # area per wave fit in LDS (160 KB less room for static variables)
+        # batch is in input order and its tile plus one packing area per
+        # wave fit in LDS (160 KB less room for static variables); an area
+        # holds the span of 64 reads of 32 * max_words bases (kernels.h)
         tile = ((1 << c.tile_levels) - 1) * 12
+        area = (((128 * c.max_words + 1 + 4) * 6 + 8) + 15) // 16 * 16
         return (c.kernel == S.SA_KERNEL_TUNED and c.inline_pack == 1 and c.sort == 0 and
-                ((tile + 15) // 16 * 16 + (c.block // 64) * 4640) <= 160 * 1024 - 256)
+                ((tile + 15) // 16 * 16 + (c.block // 64) * area) <= 160 * 1024 - 256)
 
     packed_bytes = int(((lens + 3) // 4).sum())
     ascii_bytes = int(lens.sum()) + 8 * N
@@ -294,6 +296,33 @@ def main():
         per_length = {"calls_per_step": len(groups), "ms_per_step": round(1000.0 * pel / pk, 3),
                       "reads_per_s": round(N * pk / pel, 1)}
         log(f"per-length: {per_length}")
+        del groups
+        # each 32-base length class as a batch of its own, in the batched
+        # configuration: what every class costs, against the whole batch
+        words = np.maximum(1, (lens + 31) // 32)
+        per_class = []
+        for w in np.unique(words):
+            idx = np.nonzero(words == w)[0]
+            ln = lens[idx]
+            offs_w = np.zeros(len(idx) + 1, dtype=np.int64)
+            np.cumsum(ln, out=offs_w[1:])
+            src = np.repeat(reads.offs[idx] - offs_w[:-1], ln) + np.arange(int(offs_w[-1]), dtype=np.int64)
+            cr = torch.from_numpy(np.ascontiguousarray(reads.data[src])).to(dev)
+            co = torch.from_numpy(offs_w).to(dev)
+            cout = torch.zeros((len(idx), 4), dtype=torch.int32, device=dev)
+            S.match_batch_dev(d, cr, co, cout, stream=stream, config=lc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(pk):
+                S.match_batch_dev(d, cr, co, cout, stream=stream, config=lc)
+            torch.cuda.synchronize()
+            ms_c = 1000.0 * (time.perf_counter() - t0) / pk
+            per_class.append({"bases": f"{32 * int(w) - 31}-{32 * int(w)}", "reads": int(len(idx)),
+                              "ms": round(ms_c, 4), "reads_per_s": round(len(idx) / (ms_c * 1e-3), 1)})
+            del cr, co, cout
+        per_length["per_class"] = per_class
+        per_length["per_class_ms_total"] = round(sum(c["ms"] for c in per_class), 3)
+        log(f"per length class: {per_class}")
 
     # ---- locate (positions of exact reads, at most 16 per read) on this step's hits
     loc_offs = torch.zeros(N + 1, dtype=torch.int64, device=dev)

@@ -172,7 +172,7 @@ sa_match_cfg resolve_cfg(const sa_dindex *d, const sa_match_cfg *cfg) {
 
 bool packs_inline(const sa_match_cfg &c) {
     return c.kernel == SA_KERNEL_TUNED && c.inline_pack && c.sort == 0 &&
-           tuned_lds_bytes(c.tile_levels, c.count ? 256 : c.block, true) <= inline_lds_limit();
+           tuned_lds_bytes(c.tile_levels, c.count ? 256 : c.block, true, c.max_words) <= inline_lds_limit();
 }
 
 // Enqueue the whole device pipeline for one batch: pack, optional prefix
@@ -411,7 +411,7 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
     c.kernel = SA_KERNEL_TUNED;
     // one workgroup of 16 waves per compute unit; with a prefix table the
     // tile serves only reads with fewer than k leading bases
-    c.tile_levels = std::min(d->view.ptab_k > 0 ? 8 : 12, d->tile_levels);
+    c.tile_levels = std::min(d->view.ptab_k > 0 ? 8 : 10, d->tile_levels);
     c.block = 1024;
     c.blocks_per_cu = 1;
     c.nbuckets = 1;

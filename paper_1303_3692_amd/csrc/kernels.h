@@ -16,8 +16,6 @@ constexpr int kStatWords = 11;
 constexpr int kLongFlag = 10;
 constexpr int kMaxTileLevels = 13;        // 8191 nodes x 12 B = 96 KiB of LDS
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS of a gfx950 compute unit
-constexpr int kInlineVec = 768;           // 16-byte pieces of ASCII a wave packs in the search kernel (12 KB)
-constexpr int kInlineWaveBytes = (kInlineVec + 4) * 6 + 8;  // its codes (4 B) and flags (2 B) per piece
 constexpr int kSortBlock = 256;           // radix sort: threads per workgroup
 constexpr int kSortItems = 16;            // keys per thread per pass
 constexpr int kSortTile = kSortBlock * kSortItems;
@@ -180,10 +178,22 @@ __host__ __device__ inline size_t tile_lds_bytes(int levels) {
 // Start of the per-wave packing areas after the tile (16-byte aligned).
 __host__ __device__ inline size_t inline_area_offset(int levels) { return (tile_lds_bytes(levels) + 15) & ~(size_t)15; }
 
+// 16-byte pieces of ASCII a wave's packing area holds in the search kernel
+// whose reads hold up to `words` query words: the span of 64 reads of up to
+// 32 * words bases, and one piece more for its alignment.
+__host__ __device__ constexpr int inline_vec(int words) { return 128 * words + 1; }
+
+// LDS bytes of such an area: a 4-byte code word and a 2-byte flag word per
+// piece (with four pieces of slack), rounded up to 16 bytes.
+__host__ __device__ constexpr int inline_wave_bytes(int words) {
+    return (((inline_vec(words) + 4) * 6 + 8) + 15) & ~15;
+}
+
 // Dynamic LDS of the tuned kernel: the tile, plus one packing area per wave
 // when it packs its reads itself.
-inline size_t tuned_lds_bytes(int levels, int block, bool inline_pack) {
-    return inline_pack ? inline_area_offset(levels) + (size_t)(block / 64) * kInlineWaveBytes : tile_lds_bytes(levels);
+inline size_t tuned_lds_bytes(int levels, int block, bool inline_pack, int words = kWMax) {
+    return inline_pack ? inline_area_offset(levels) + (size_t)(block / 64) * inline_wave_bytes(words)
+                       : tile_lds_bytes(levels);
 }
 
 }  // namespace samatch

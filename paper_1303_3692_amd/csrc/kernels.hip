@@ -879,7 +879,7 @@ __device__ __forceinline__ void chunk_offsets(const int64_t *__restrict__ offs, 
 // byte belongs to one of them; with CSR offsets the span lies between two
 // offsets of the one buffer.
 __device__ __forceinline__ Span chunk_span(const uint8_t *__restrict__ reads, bool gathered, int64_t chunk,
-                                           int64_t nreads, int lane, int64_t a, int64_t e) {
+                                           int64_t nreads, int lane, int64_t a, int64_t e, int max_vec) {
     Span sp{0, 0, 0, 0, false};
     if (chunk < 0) return sp;
     const int last = (int)min_i(63, (int)(nreads - 1 - (chunk << 6)));
@@ -892,7 +892,7 @@ __device__ __forceinline__ Span chunk_span(const uint8_t *__restrict__ reads, bo
     }
     sp.A0 = (uintptr_t)(reads + sp.s0) & ~(uintptr_t)15;
     const uintptr_t A1 = ((uintptr_t)(reads + sp.s1) + 15) & ~(uintptr_t)15;
-    sp.staged = joined && sp.s1 > sp.s0 && A1 - sp.A0 <= (uintptr_t)kInlineVec * 16u;
+    sp.staged = joined && sp.s1 > sp.s0 && A1 - sp.A0 <= (uintptr_t)max_vec * 16u;
     sp.nvec = sp.staged ? (int)((A1 - sp.A0) >> 4) : 0;
     return sp;
 }
@@ -1026,9 +1026,10 @@ __device__ __forceinline__ int64_t workgroup_rank() {
 // offsets (reads in input order; no pack kernel ran), each wave in its own
 // LDS area after the tile.  WQ: query words a read may hold in registers
 // (reads of up to 32 * WQ bases; longer ones are the long-read kernel's).
-// The 5-word instance keeps fewer registers live (and prefetches less of
-// the next chunk), so that six waves fit each SIMD (the counting instance is
-// not held to that).
+// The 5-word instance keeps fewer registers live (and prefetches one piece
+// of the next chunk per lane), so that six waves fit each SIMD (the
+// counting instance is not held to that).  Each instance's packing area
+// holds the span of 64 reads of its longest length.
 template <int BLOCK, bool COUNT, bool INLINE, int WQ>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WQ < kWMax && !COUNT ? 6 : 1))) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group,
                                                              BatchBuffers b, const uint32_t *__restrict__ order,
@@ -1045,9 +1046,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WQ < kWMa
     uint16_t *w_badm = nullptr;
     if constexpr (INLINE) {
         uint8_t *area = reinterpret_cast<uint8_t *>(smem) + inline_area_offset(levels) +
-                        (size_t)(threadIdx.x >> 6) * kInlineWaveBytes;
+                        (size_t)(threadIdx.x >> 6) * inline_wave_bytes(WQ);
         w_codes = reinterpret_cast<uint32_t *>(area);
-        w_badm = reinterpret_cast<uint16_t *>(w_codes + kInlineVec + 4);
+        w_badm = reinterpret_cast<uint16_t *>(w_codes + inline_vec(WQ) + 4);
     }
     if (threadIdx.x == 0) s_next = 0u;
     for (int i = threadIdx.x; i < nodes; i += BLOCK) {
@@ -1074,8 +1075,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WQ < kWMa
     if constexpr (INLINE) {
         int64_t c0 = take(), a0, e0;
         chunk_offsets(offs, ends, c0, nreads, lane, a0, e0);
-        Span sp0 = chunk_span(reads, ends != nullptr, c0, nreads, lane, a0, e0);
-        constexpr int AHEAD = WQ < kWMax ? 2 : kInlineAhead;
+        Span sp0 = chunk_span(reads, ends != nullptr, c0, nreads, lane, a0, e0, inline_vec(WQ));
+        constexpr int AHEAD = WQ < kWMax ? 1 : kInlineAhead;
         constexpr int kMaxM = 32 * WQ;  // longest read searched here
         uint4 v[AHEAD];
         span_prefetch(sp0, lane, v, cnt);
@@ -1115,7 +1116,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WQ < kWMa
             }
             if (sp0.staged) wave_lds_sync();  // every lane has its words before the area is reused
             // loads for the chunks ahead, in flight during this chunk's searches
-            const Span sp1 = chunk_span(reads, ends != nullptr, c1, nreads, lane, a1, e1);
+            const Span sp1 = chunk_span(reads, ends != nullptr, c1, nreads, lane, a1, e1, inline_vec(WQ));
             span_prefetch(sp1, lane, v, cnt);
             const int64_t c2 = c1 >= 0 ? take() : -1;
             int64_t a2, e2;
@@ -1298,7 +1299,7 @@ hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int
                               const uint32_t *order, const uint8_t *reads, const int64_t *offs, const int64_t *ends,
                               int64_t nreads, int words, int4 *out, hipStream_t s) {
     if (offs) {
-        const size_t lds = tuned_lds_bytes(levels, BLOCK, true);
+        const size_t lds = tuned_lds_bytes(levels, BLOCK, true, words);
         if (lds > g_inline_lds.load()) return hipErrorInvalidValue;
         if (words == kShortWords)
             hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, true, kShortWords>), dim3(grid), dim3(BLOCK), lds, s,

@@ -445,7 +445,8 @@ bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
     if (c.kernel == SA_KERNEL_TUNED) {
         c.sort = 0;
         c.inline_pack = 1;
-        while (c.tile_levels > 1 && tuned_lds_bytes(c.tile_levels, c.block, true) > inline_lds_limit()) c.tile_levels--;
+        while (c.tile_levels > 1 && tuned_lds_bytes(c.tile_levels, c.block, true, c.max_words) > inline_lds_limit())
+            c.tile_levels--;
     }
     c.use_graph = 0;
     c.profile = o.measure >= 1 ? 1 : 0;  // stage events, read when the batch is reaped

@@ -258,8 +258,10 @@ def test_prefix_table_edges(device, kind):
 
 def test_inline_pack_spans(device):
     """The search kernel's own packing against the pack pass and the oracle:
-    waves whose 64 reads span more than its 12 KB packing area (300-base
-    reads, long reads among short ones), offsets that go backwards (a
+    waves whose 64 reads fill its packing area exactly (320-base reads: 20 KB
+    for the kernel that holds 10 query words) or span more than it (300-base
+    reads for the 5-word kernel's 10 KB, long reads among short ones),
+    offsets that go backwards (a
     negative length is too long; the reads after it lie before the wave's
     span), and the whole batch moved 5 bytes into its buffer."""
     say("case: inline pack spans")
@@ -280,6 +282,8 @@ def test_inline_pack_spans(device):
         return r
 
     reads = [sample(300) for _ in range(200)]                                  # 19 KB per wave
+    reads += [sample(320) for _ in range(128)]                                 # 20 KB: a full area
+    reads += [sample(1000) if k % 4 == 0 else sample(300) for k in range(128)] # 30 KB per wave
     reads += [sample(900) if k % 10 == 3 else sample(100) for k in range(300)]  # long reads among short ones
     reads += [sample(int(rng.integers(1, 200))) for _ in range(300)]
     d = S.sa_upload(S.sa_build(text), 0)
