@@ -104,7 +104,7 @@ void sa_free(sa_index *ix);                           /* NULL is a no-op        
  * never touch the text), the table of the top levels of the
  * implicit binary-search tree that the tuned kernel stages in LDS (the tile
  * of Section IV), and, for n >= 4096, a prefix table: for every string v of
- * k = round(log4 n) bases (4 <= k <= 14), the first SA row whose suffix is
+ * k = round(log4 n) + 1 bases (4 <= k <= 15), the first SA row whose suffix is
  * not below v with the bracket of rows that start with v, or the result of
  * the reads that start with v when there are none (4^k + 1 entries of 16
  * bytes; see sa_set_prefix_table).  The host index may be
@@ -130,8 +130,8 @@ int sa_build_device(const char *text, int64_t n, int device, sa_dindex **out);
 int sa_dindex_bytes(const sa_dindex *d, int64_t bytes[5]);
 
 /* Rebuild the prefix table of a resident index for strings of k bases
- * (4 <= k <= 14, texts of at least 4096 bases), or drop it (k = 0).  The
- * default is k = round(log4 n), at most 14.  Entries are 16 bytes, one per
+ * (4 <= k <= 15, texts of at least 4096 bases), or drop it (k = 0).  The
+ * default is k = round(log4 n) + 1, at most 15.  Entries are 16 bytes, one per
  * k-base string v (4^k + 1 in all): the first SA row not below v, and either
  * the size of the bracket of rows that start with v with the position and
  * bases k .. k+15 of the suffix at its first search pivot, or, when no
@@ -194,6 +194,12 @@ typedef struct {
                             long-read kernel).  5 keeps fewer registers live so
                             that more waves fit a compute unit; 0 = the
                             index's default                                     */
+    int defer;           /* tuned, with inline_pack: a read whose binary searches
+                            take more than this many probes of row records is
+                            set aside and searched again, without a limit,
+                            together with 63 other such reads, so that one long
+                            search does not keep 63 lanes of its wave idle
+                            (0..1024; 0 = never).  Results never change.       */
 } sa_match_cfg;
 
 /* Fill cfg with the index's current defaults. */

@@ -145,6 +145,7 @@ int check_cfg(const sa_dindex *d, const sa_match_cfg &c) {
     if (c.sort != 0 && c.sort != 1 && c.sort != 8 && c.sort != 16 && c.sort != 24)
         return fail(SA_EINVAL, "sort must be 0, 1, 8, 16 or 24");
     if (c.inline_pack != 0 && c.inline_pack != 1) return fail(SA_EINVAL, "inline_pack must be 0 or 1");
+    if (c.defer < 0 || c.defer > 1024) return fail(SA_EINVAL, "defer must be in 0..1024");
     if (c.max_words != kShortWords && c.max_words != kWMax)
         return fail(SA_EINVAL, "max_words must be " + std::to_string(kShortWords) + " or " + std::to_string(kWMax));
     for (int i = 0; i + 1 < c.nbuckets; i++)
@@ -241,7 +242,7 @@ int enqueue_pipeline(sa_dindex *d, const BatchBuffers &b, const hipEvent_t *ev, 
         const int64_t chunks = (nreads + 63) / 64, gmax = std::max<int64_t>(1, (int64_t)d->cu_count * c.blocks_per_cu);
         const int group = (int)std::max<int64_t>(1, std::min<int64_t>(c.group, chunks / gmax));
         const int grid = (int)std::min<int64_t>(gmax, (chunks + group - 1) / group);
-        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, group, b, order,
+        e = launch_search_tuned(d->view, c.tile_levels, c.prefix_table, c.block, grid, group, c.defer, b, order,
                                 inl ? d_reads : nullptr, inl ? d_offs : nullptr, inl ? d_ends : nullptr, nreads,
                                 inl ? c.max_words : kWMax, d_out, c.count != 0, s);
         if (e != hipSuccess) return hip_fail(e, "tuned search launch");
@@ -303,15 +304,16 @@ int run_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t
 
 namespace {
 
-// Prefix-table length of a text of n bases: round(log4 n), so that a
-// table entry's bracket holds about one row, at most kMaxPrefixBases; none
-// below 4096 bases.  (With 4-byte entries, one base more cut the probes per
-// read by a fifth for a 4x larger table; with 16-byte entries that hold the
-// bracket's first pivot, the first probe is free and the table stays near
-// 16 bytes per base.)
+// Prefix-table length of a text of n bases: round(log4 n) + 1, so that a
+// table entry's bracket holds about a quarter of a row (most lookups then
+// need at most the one probe whose suffix travels with the entry), at most
+// kMaxPrefixBases; none below 4096 bases.  The table takes about 64 bytes
+// per base (4^k 16-byte entries).  On MI355X the extra base cut the search
+// by 15 % for a 250 Mbp reference (17 GB table) and by 8 % for a 16 Mbp one
+// against round(log4 n); a base fewer made it 16 % slower.
 int default_prefix_bases(int64_t n) {
     if (n < 4096) return 0;
-    const int k = (int)std::lround(std::log2((double)n) / 2.0);
+    const int k = (int)std::lround(std::log2((double)n) / 2.0) + 1;
     return std::max(4, std::min(kMaxPrefixBases, k));
 }
 
@@ -424,6 +426,7 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
     c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
     c.inline_pack = 1;
     c.max_words = kWMax;
+    c.defer = kDefaultDefer;
     *out = d.release();
     return SA_OK;
 }
@@ -490,7 +493,7 @@ extern "C" int sa_dindex_bytes(const sa_dindex *d, int64_t bytes[5]) {
 extern "C" int sa_set_prefix_table(sa_dindex *d, int k) {
     clear_error();
     if (!d) return fail(SA_EINVAL, "NULL argument");
-    if (k < 0 || (k > 0 && k < 4) || k > kMaxPrefixBases) return fail(SA_EINVAL, "prefix bases must be 0 or 4..14");
+    if (k < 0 || (k > 0 && k < 4) || k > kMaxPrefixBases) return fail(SA_EINVAL, "prefix bases must be 0 or 4.." + std::to_string(kMaxPrefixBases));
     if (k > 0 && d->n < 4096) return fail(SA_EINVAL, "a prefix table needs a text of at least 4096 bases");
     DeviceGuard g(d->device);
     if (!g.ok) return fail(SA_EDEVICE, "hipSetDevice failed");

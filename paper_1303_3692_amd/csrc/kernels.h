@@ -12,6 +12,7 @@ constexpr int kWMax = 10;                 // packed words per read slot of the s
 constexpr int kShortWords = 5;            // query words of the search kernel's register-light instance
 constexpr int kShortMax = kWMax * 32;     // longest read of the short-read path (320 bases)
 constexpr int kLongWords = SA_MAX_READ / 32;  // words of a read on the long-read path
+constexpr int kDefaultDefer = 3;          // probes before a read is set aside (sa_match_cfg.defer)
 constexpr int kStatWords = 11;
 constexpr int kLongFlag = 10;
 constexpr int kMaxTileLevels = 13;        // 8191 nodes x 12 B = 96 KiB of LDS
@@ -76,7 +77,10 @@ struct DevIndex {
     int32_t n;
     int32_t ptab_k;            // bases indexed by the prefix table (0: no table)
 };
-constexpr int kMaxPrefixBases = 14;
+// Longest prefix a table may index: its build launches one work-item per
+// entry, and a dispatch holds fewer than 2^32 work-items (4^15 + 1 entries:
+// 16 GiB).
+constexpr int kMaxPrefixBases = 15;
 
 struct BucketTable {
     int count;     // 1..8
@@ -130,8 +134,11 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi
 // inline_lds_limit().
 // words: query words a read may hold (kShortWords or kWMax); with offs,
 // longer reads are left to launch_search_long (long_min = 32 * words).
+// defer (with offs, > 0): a read whose searches take more than this many
+// probes of row records is set aside and searched again, without a limit,
+// in a chunk of such reads (0: never; the counting variant never does).
 hipError_t launch_search_tuned(const DevIndex &ix, int tile_levels, int use_table, int block, int grid,
-                               int group, const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
+                               int group, int defer, const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
                                const int64_t *offs, const int64_t *ends, int64_t nreads, int words, void *out,
                                bool count, hipStream_t s);
 
@@ -179,15 +186,21 @@ __host__ __device__ inline size_t tile_lds_bytes(int levels) {
 __host__ __device__ inline size_t inline_area_offset(int levels) { return (tile_lds_bytes(levels) + 15) & ~(size_t)15; }
 
 // 16-byte pieces of ASCII a wave's packing area holds in the search kernel
-// whose reads hold up to `words` query words: the span of 64 reads of up to
-// 32 * words bases, and one piece more for its alignment.
-__host__ __device__ constexpr int inline_vec(int words) { return 128 * words + 1; }
+// whose reads hold up to `words` query words: 64 slots of 2 * words + 1
+// pieces, each the most a read of up to 32 * words bases can touch; a span
+// of 64 consecutive such reads fits too.
+__host__ __device__ constexpr int inline_slot(int words) { return 2 * words + 1; }
+__host__ __device__ constexpr int inline_vec(int words) { return 64 * inline_slot(words); }
+
+// Entries of a wave's queue of set-aside reads (it is drained at 64, and a
+// chunk adds at most 64).
+constexpr int kDeferCap = 128;
 
 // LDS bytes of such an area: a 4-byte code word and a 2-byte flag word per
-// piece (with four pieces of slack), rounded up to 16 bytes.
-__host__ __device__ constexpr int inline_wave_bytes(int words) {
-    return (((inline_vec(words) + 4) * 6 + 8) + 15) & ~15;
-}
+// piece (with four pieces of slack), then the queue of set-aside reads (4
+// bytes each), rounded up to 16 bytes.
+__host__ __device__ constexpr int inline_codes_bytes(int words) { return (((inline_vec(words) + 4) * 6 + 8) + 15) & ~15; }
+__host__ __device__ constexpr int inline_wave_bytes(int words) { return inline_codes_bytes(words) + 4 * kDeferCap; }
 
 // Dynamic LDS of the tuned kernel: the tile, plus one packing area per wave
 // when it packs its reads itself.

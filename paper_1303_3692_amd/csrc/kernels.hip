@@ -26,6 +26,10 @@ namespace {
 
 constexpr uint32_t kHitExact = 1u;
 constexpr uint32_t kHitTooLong = 2u;
+// Internal result of a search that ran out of its probe budget (never
+// written out: the read is searched again without a limit).
+constexpr uint32_t kHitDeferred = 0x40000000u;
+constexpr int kNoBudget = 0x7FFFFFFF;
 
 // ------------------------------------------------------------------ helpers
 
@@ -264,10 +268,14 @@ __device__ __forceinline__ int compare_row(const DevIndex &ix, const Q &q, int p
 // starts comparing at that word.  UPPER = false: first row whose suffix is
 // not below P[0..plen) (LB); UPPER = true: first row strictly above every
 // extension of P[0..plen) (RB + 1).
+//
+// left: probes the read may still take; a search that would take one more
+// when none is left stops and returns -1 (every result is >= 0).
 template <int W, bool UPPER, class Q, class Cnt>
 __device__ __forceinline__ int bounded_search(const DevIndex &ix, const Q &q, int plen, int L, int R,
-                              int lcpL, int lcpR, Cnt &cnt) {
+                              int lcpL, int lcpR, int &left, Cnt &cnt) {
     while (R > L + 1) {
+        if (--left < 0) return -1;
         const int piv = midpoint(L, R);
         const RowHead row = row_head(ix.rows, piv);
         cnt.index_touch(ix.rows + piv, 16);
@@ -305,9 +313,10 @@ __device__ __forceinline__ void lb_update(LbState &st, int sign, int piv, int lc
 // from (-1, n) visit nodes of one fixed implicit binary tree; their pivot
 // suffixes (first 32 bases and text position) sit in LDS.  A probe that
 // ties on all 32 staged bases continues in global memory at word 1.
+// Returns false when the global probes ran out of `left`.
 template <int W, class Q, class Cnt>
-__device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
-                          const Q &q, int plen, LbState &st, Cnt &cnt) {
+__device__ __forceinline__ bool lb_search(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
+                          const Q &q, int plen, LbState &st, int &left, Cnt &cnt) {
     st.L = -1; st.R = ix.n; st.lcpL = 0; st.lcpR = 0;
     st.Llt = -1; st.lcpLlt = 0; st.Rlt = ix.n; st.lcpRlt = 0;
     int node = 0;
@@ -322,6 +331,7 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
         node = 2 * node + (sign <= 0 ? 1 : 2);
     }
     while (st.R > st.L + 1) {
+        if (--left < 0) return false;
         const int piv = midpoint(st.L, st.R);
         const RowHead row = row_head(ix.rows, piv);
         cnt.index_touch(ix.rows + piv, 16);
@@ -331,6 +341,7 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
             compare_row<W>(ix, q, plen, ix.rows + piv, row.pos, row.key0, min_i(st.lcpL, st.lcpR), lcp, cnt);
         lb_update(st, sign, piv, lcp);
     }
+    return true;
 }
 
 // ---- prefix table
@@ -342,7 +353,9 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
 
 // LB search of P[0..plen) inside the table bracket of its first k bases v.
 // Returns false when no suffix starts with v: the entry then holds the
-// read's result (ans).  Otherwise st holds the LB search's final state.
+// read's result (ans); also when the record probes ran out of `left` (ans
+// is then flagged kHitDeferred).  Otherwise st holds the LB search's final
+// state.
 // Rows inside the bracket share k bases with P, so when the search moves a
 // bound inside, the other bound's common-prefix length (below k) never
 // decides anything and starts as 0.  The first probe takes its pivot
@@ -350,7 +363,7 @@ __device__ __forceinline__ void lb_search(const DevIndex &ix, const uint64_t *s_
 // its own.
 template <int W, class Q, class Cnt>
 __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, int plen, LbState &st,
-                                                int4 &ans, Cnt &cnt) {
+                                                int4 &ans, int &left, Cnt &cnt) {
     const int K = ix.ptab_k;
     const uint32_t v = (uint32_t)(q[0] >> (64 - 2 * K));
     const PrefixEntry ent = ix.ptab[v];
@@ -373,6 +386,10 @@ __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, 
         lb_update(st, sign, piv, lcp);
     }
     while (st.R > st.L + 1) {
+        if (--left < 0) {
+            ans = make_int4(0, 0, 0, (int)kHitDeferred);
+            return false;
+        }
         const int piv = midpoint(st.L, st.R);
         const RowHead row = row_head(ix.rows, piv);
         cnt.index_touch(ix.rows + piv, 16);
@@ -389,26 +406,36 @@ __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, 
 // search confined to (LB, Rlt]; other reads take the longest matched prefix
 // l = max(lcpL, lcpR) from the two rows around the insertion point and find
 // the interval of P[0..l) inside the bounds the LB search already bracketed.
+// The empty prefix (an empty read, or one that starts with a non-base)
+// matches every suffix.  `budget` bounds the probes of row records and of
+// the global part of the tree; a read that needs more gets a result
+// flagged kHitDeferred instead (kNoBudget: no bound).
 template <int W, class Q, class Cnt>
 __device__ __forceinline__ int4 match_read(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa, int levels,
-                           bool use_table, const Q &q, int m, int mv, Cnt &cnt) {
+                           bool use_table, const Q &q, int m, int mv, int budget, Cnt &cnt) {
+    if (mv == 0) return make_int4(0, ix.n, 0, m == 0 ? (int)kHitExact : 0);
+    const int4 deferred = make_int4(0, 0, 0, (int)kHitDeferred);
+    int left = budget;
     LbState st;
     if (use_table && ix.ptab_k > 0 && mv >= ix.ptab_k) {
         int4 ans;
-        if (!lb_search_table<W>(ix, q, mv, st, ans, cnt)) return ans;
+        if (!lb_search_table<W>(ix, q, mv, st, ans, left, cnt)) return ans;
     } else {
-        lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, cnt);
+        if (!lb_search<W>(ix, s_key, s_sa, levels, q, mv, st, left, cnt)) return deferred;
     }
     if (mv == m && st.lcpR == m) {
-        const int hi = bounded_search<W, true>(ix, q, m, st.R, st.Rlt, m, st.lcpRlt, cnt);
+        const int hi = bounded_search<W, true>(ix, q, m, st.R, st.Rlt, m, st.lcpRlt, left, cnt);
+        if (hi < 0) return deferred;
         return make_int4(st.R, hi, m, (int)kHitExact);
     }
     // (after a search inside a table bracket l >= k: one of the final
     // bounds is a probed row of the bracket, which shares the k bases)
     const int l = max_i(st.lcpL, st.lcpR);
     if (l == 0) return make_int4(0, ix.n, 0, 0);
-    const int lo = (st.lcpL == l) ? bounded_search<W, false>(ix, q, l, st.Llt, st.L, st.lcpLlt, l, cnt) : st.R;
-    const int hi = (st.lcpR == l) ? bounded_search<W, true>(ix, q, l, st.R, st.Rlt, l, st.lcpRlt, cnt) : st.R;
+    const int lo =
+        (st.lcpL == l) ? bounded_search<W, false>(ix, q, l, st.Llt, st.L, st.lcpLlt, l, left, cnt) : st.R;
+    const int hi = (st.lcpR == l) ? bounded_search<W, true>(ix, q, l, st.R, st.Rlt, l, st.lcpRlt, left, cnt) : st.R;
+    if ((lo | hi) < 0) return deferred;
     return make_int4(lo, hi, l, 0);
 }
 
@@ -490,7 +517,7 @@ __global__ void fill_prefix_entries_kernel(DevIndex ix, int k, int64_t entries, 
     } else {
         const uint64_t q[1] = {(uint64_t)v << (64 - 2 * k)};
         NoCount none;
-        const int4 r = match_read<1>(ix, nullptr, nullptr, 0, false, q, k, k, none);
+        const int4 r = match_read<1>(ix, nullptr, nullptr, 0, false, q, k, k, kNoBudget, none);
         tab[v].size = kPtabAnswer | (uint32_t)r.z;
         tab[v].pos = r.x;
         tab[v].next = (uint32_t)r.y;
@@ -822,24 +849,29 @@ __device__ __forceinline__ void tuned_one(const DevIndex &ix, const uint64_t *s_
 #pragma unroll
     for (int k = 0; k < W; ++k)
         if (k < nw) cnt.touch(src + k, 8);
-    out[rid] = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, cnt);
+    out[rid] = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, kNoBudget, cnt);
     cnt.touch(out + rid, 16);
 }
 
-// tuned_one for a read whose packed words are already in registers.
+// tuned_one for a read whose packed words are already in registers, with
+// at most `budget` probes: returns true (and writes nothing) when the read
+// needs more.
 template <int W, int N, class Cnt>
-__device__ __forceinline__ void tuned_regs(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa,
+__device__ __forceinline__ bool tuned_regs(const DevIndex &ix, const uint64_t *s_key, const int32_t *s_sa,
                                            int levels, bool use_table, const uint64_t (&w)[N], int rid, int m,
-                                           int mv, int4 *out, Cnt &cnt) {
+                                           int mv, int budget, int4 *out, Cnt &cnt) {
     if (m < 0) {
         out[rid] = make_int4(0, 0, 0, (int)kHitTooLong);
-        return;
+        return false;
     }
     uint64_t q[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) q[k] = w[k];
-    out[rid] = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, cnt);
+    const int4 r = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, budget, cnt);
+    if (r.w == (int)kHitDeferred) return true;
+    out[rid] = r;
     cnt.touch(out + rid, 16);
+    return false;
 }
 
 // Packing inside the search kernel, for reads in input order with CSR
@@ -950,6 +982,43 @@ __device__ __forceinline__ bool span_convert(const Span &sp, const uint4 (&v)[AH
     return __any(bad);
 }
 
+// The reads of a chunk of set-aside reads (lane l: m bases at reads[a..];
+// m = 0 for a lane without one) as codes and flags in the wave's area:
+// lane l's read takes slot l, pieces [l * S, (l + 1) * S) (S =
+// inline_slot(WQ)), starting (a & 15) bytes into the slot's first piece.
+// The wave loads the slots' pieces with its lanes side by side (pieces of
+// one read are neighbours in memory), four loads in flight per lane.
+// Returns, the same for every lane, whether any byte loaded was not a base.
+template <int WQ, class Cnt>
+__device__ __forceinline__ bool gather_convert(const uint8_t *__restrict__ reads, int64_t a, int m, uint32_t *codes,
+                                               uint16_t *badm, int lane, Cnt &cnt) {
+    constexpr int S = inline_slot(WQ);
+    const uintptr_t A0 = (uintptr_t)(reads + a) & ~(uintptr_t)15;
+    const int np = m > 0 ? (int)(((((uintptr_t)(reads + a) + (uintptr_t)m + 15) & ~(uintptr_t)15) - A0) >> 4) : 0;
+    bool bad = false;
+#pragma unroll 1
+    for (int c0 = 0; c0 < 64 * S; c0 += 4 * 64) {
+        uint4 r[4];
+        bool in[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + 64 * u + lane;
+            const int owner = c / S, k = c - owner * S;
+            const uintptr_t base = (uintptr_t)__shfl((unsigned long long)A0, owner & 63, 64);
+            const int n_owner = __shfl(np, owner & 63, 64);
+            in[u] = c < 64 * S && k < n_owner;
+            if (in[u]) {
+                r[u] = reinterpret_cast<const uint4 *>(base)[k];
+                cnt.touch(reinterpret_cast<const uint4 *>(base) + k, 16);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (in[u]) bad |= convert_piece(r[u], codes, badm, c0 + 64 * u + lane);
+    }
+    return __any(bad);
+}
+
 // LDS written by this wave's lanes is visible to its other lanes.
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1031,7 +1100,7 @@ __device__ __forceinline__ int64_t workgroup_rank() {
 // counting instance is not held to that).  Each instance's packing area
 // holds the span of 64 reads of its longest length.
 template <int BLOCK, bool COUNT, bool INLINE, int WQ>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WQ < kWMax && !COUNT ? 6 : 1))) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WQ < kWMax && !COUNT ? 6 : 1))) void search_tuned_kernel(DevIndex ix, int levels, int use_table_i, int group, int defer,
                                                              BatchBuffers b, const uint32_t *__restrict__ order,
                                                              const uint8_t *__restrict__ reads,
                                                              const int64_t *__restrict__ offs,
@@ -1082,79 +1151,116 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WQ < kWMa
         span_prefetch(sp0, lane, v, cnt);
         int64_t c1 = c0 >= 0 ? take() : -1, a1, e1;
         chunk_offsets(offs, ends, c1, nreads, lane, a1, e1);
-        while (c0 >= 0) {
-            const int64_t j = (c0 << 6) + lane;
-            const bool active = j < nreads;
-            if (COUNT && active) {
-                cnt.touch(offs + j, ends ? 8 : 16);
-                if (ends) cnt.touch(ends + j, 8);
-            }
-            const int64_t m64 = e0 - a0;
-            // m = -1: length out of range (the too-long result); long reads are the long kernel's
-            const bool long_read = active && m64 > kMaxM && m64 <= SA_MAX_READ;
-            const int m = (m64 >= 0 && m64 <= kMaxM) ? (int)m64 : -1;
-            if (long_read) b.stats[kLongFlag] = 1ull;
-            const bool short_read = active && !long_read;
-            bool scan = false;
-            if (sp0.staged) {
-                scan = span_convert(sp0, v, w_codes, w_badm, lane, cnt);
-                wave_lds_sync();
-            }
+        // reads set aside (their searches ran out of `defer` probes) wait in
+        // the wave's queue; when 64 are waiting, or the chunks are done, the
+        // wave takes them as a chunk of its own and searches them without a
+        // limit, so that one long search does not hold up 63 idle lanes
+        uint32_t *w_queue = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(w_codes) + inline_codes_bytes(WQ));
+        const int budget = (defer > 0 && !COUNT) ? defer : kNoBudget;
+        int queued = 0;  // wave-uniform
+        while (c0 >= 0 || queued > 0) {
+            const bool drain = queued >= 64 || c0 < 0;
             uint64_t w[WQ];
 #pragma unroll
             for (int t = 0; t < WQ; ++t) w[t] = 0;
-            int mv = m;
-            if (short_read && m > 0) {
-                if (sp0.staged && a0 >= sp0.s0 && e0 <= sp0.s1) {
-                    inline_extract(w_codes, w_badm, (uint32_t)((uintptr_t)(reads + a0) - sp0.A0), m, w, mv, scan);
-                } else {
-                    uint64_t g[kWMax + 1];
-                    pack_from_global(reads, a0, m, g, mv, g[kWMax]);
-#pragma unroll
-                    for (int t = 0; t < WQ; ++t) w[t] = (32 * t < m) ? g[t] : 0;
+            int rid, m;
+            bool short_read, from_lds, scan, synced;
+            uint32_t st0;
+            if (drain) {
+                const int n = min_i(queued, 64);
+                queued -= n;
+                short_read = lane < n;
+                rid = short_read ? (int)w_queue[queued + lane] : 0;
+                const int64_t a = short_read ? offs[rid] : 0;
+                const int64_t e = short_read ? (ends ? ends[rid] : offs[rid + 1]) : 0;
+                m = (int)(e - a);  // 1 .. kMaxM: the read was searched before
+                scan = gather_convert<WQ>(reads, a, m, w_codes, w_badm, lane, cnt);
+                wave_lds_sync();
+                from_lds = short_read;
+                synced = true;
+                st0 = (uint32_t)(lane * inline_slot(WQ) * 16) + (uint32_t)(a & 15);
+            } else {
+                const int64_t j = (c0 << 6) + lane;
+                const bool active = j < nreads;
+                if (COUNT && active) {
+                    cnt.touch(offs + j, ends ? 8 : 16);
+                    if (ends) cnt.touch(ends + j, 8);
                 }
+                const int64_t m64 = e0 - a0;
+                // m = -1: length out of range (the too-long result); long reads are the long kernel's
+                const bool long_read = active && m64 > kMaxM && m64 <= SA_MAX_READ;
+                m = (m64 >= 0 && m64 <= kMaxM) ? (int)m64 : -1;
+                if (long_read) b.stats[kLongFlag] = 1ull;
+                short_read = active && !long_read;
+                rid = (int)j;
+                scan = false;
+                if (sp0.staged) {
+                    scan = span_convert(sp0, v, w_codes, w_badm, lane, cnt);
+                    wave_lds_sync();
+                }
+                synced = sp0.staged;
+                from_lds = short_read && m > 0 && sp0.staged && a0 >= sp0.s0 && e0 <= sp0.s1;
+                st0 = (uint32_t)((uintptr_t)(reads + a0) - sp0.A0);
             }
-            if (sp0.staged) wave_lds_sync();  // every lane has its words before the area is reused
-            // loads for the chunks ahead, in flight during this chunk's searches
-            const Span sp1 = chunk_span(reads, ends != nullptr, c1, nreads, lane, a1, e1, inline_vec(WQ));
-            span_prefetch(sp1, lane, v, cnt);
-            const int64_t c2 = c1 >= 0 ? take() : -1;
-            int64_t a2, e2;
-            chunk_offsets(offs, ends, c2, nreads, lane, a2, e2);
+            int mv = m;
+            if (from_lds) {
+                inline_extract(w_codes, w_badm, st0, m, w, mv, scan);
+            } else if (short_read && m > 0) {
+                uint64_t g[kWMax + 1];
+                pack_from_global(reads, a0, m, g, mv, g[kWMax]);
+#pragma unroll
+                for (int t = 0; t < WQ; ++t) w[t] = (32 * t < m) ? g[t] : 0;
+            }
+            if (synced) wave_lds_sync();  // every lane has its words before the area is reused
+            if (!drain) {
+                // loads for the chunks ahead, in flight during this chunk's searches
+                const Span sp1 = chunk_span(reads, ends != nullptr, c1, nreads, lane, a1, e1, inline_vec(WQ));
+                span_prefetch(sp1, lane, v, cnt);
+                const int64_t c2 = c1 >= 0 ? take() : -1;
+                int64_t a2, e2;
+                chunk_offsets(offs, ends, c2, nreads, lane, a2, e2);
+                c0 = c1;
+                a0 = a1;
+                e0 = e1;
+                sp0 = sp1;
+                c1 = c2;
+                a1 = a2;
+                e1 = e2;
+            }
             const int wn = max_i(1, (m + 31) >> 5);
             int wc = 1;
 #pragma unroll
             for (int t = 2; t <= WQ; ++t)
                 if (wave_ballot(short_read && wn >= t)) wc = t;
+            const int lim = drain ? kNoBudget : budget;
+            bool later = false;
             if (short_read) {
                 if (COUNT && m >= 0) { nsearched++; nqwords += wc; }
-                const int rid = (int)j;
                 switch (wc) {
-                    case 1: tuned_regs<1>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                    case 2: tuned_regs<2>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                    case 3: tuned_regs<3>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                    case 4: tuned_regs<4>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                    case 5: tuned_regs<5>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                    case 1: later = tuned_regs<1>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
+                    case 2: later = tuned_regs<2>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
+                    case 3: later = tuned_regs<3>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
+                    case 4: later = tuned_regs<4>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
+                    case 5: later = tuned_regs<5>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
                     default:
                         if constexpr (WQ >= 10) {
                             switch (wc) {
-                                case 6: tuned_regs<6>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                                case 7: tuned_regs<7>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                                case 8: tuned_regs<8>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                                case 9: tuned_regs<9>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
-                                default: tuned_regs<10>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, out, cnt); break;
+                                case 6: later = tuned_regs<6>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
+                                case 7: later = tuned_regs<7>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
+                                case 8: later = tuned_regs<8>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
+                                case 9: later = tuned_regs<9>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
+                                default: later = tuned_regs<10>(ix, s_key, s_sa, levels, use_table, w, rid, m, mv, lim, out, cnt); break;
                             }
                         }
                         break;
                 }
             }
-            c0 = c1;
-            a0 = a1;
-            e0 = e1;
-            sp0 = sp1;
-            c1 = c2;
-            a1 = a2;
-            e1 = e2;
+            const uint64_t set_aside = wave_ballot(later);
+            if (set_aside) {
+                if (later) w_queue[queued + __popcll(set_aside & ((1ull << lane) - 1ull))] = (uint32_t)rid;
+                queued += __popcll(set_aside);
+                wave_lds_sync();
+            }
         }
     }
     while (!INLINE) {  // reads packed by the pack kernel
@@ -1295,7 +1401,8 @@ hipError_t allow_tile_lds(size_t inline_lds) {
 }
 
 template <int BLOCK, bool COUNT>
-hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int group, int grid, const BatchBuffers &b,
+hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int group, int defer, int grid,
+                              const BatchBuffers &b,
                               const uint32_t *order, const uint8_t *reads, const int64_t *offs, const int64_t *ends,
                               int64_t nreads, int words, int4 *out, hipStream_t s) {
     if (offs) {
@@ -1303,13 +1410,13 @@ hipError_t launch_tuned_block(const DevIndex &ix, int levels, int use_table, int
         if (lds > g_inline_lds.load()) return hipErrorInvalidValue;
         if (words == kShortWords)
             hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, true, kShortWords>), dim3(grid), dim3(BLOCK), lds, s,
-                               ix, levels, use_table, group, b, order, reads, offs, ends, nreads, out);
+                               ix, levels, use_table, group, defer, b, order, reads, offs, ends, nreads, out);
         else
             hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, true, kWMax>), dim3(grid), dim3(BLOCK), lds, s, ix,
-                               levels, use_table, group, b, order, reads, offs, ends, nreads, out);
+                               levels, use_table, group, defer, b, order, reads, offs, ends, nreads, out);
     } else {
         hipLaunchKernelGGL((search_tuned_kernel<BLOCK, COUNT, false, kWMax>), dim3(grid), dim3(BLOCK),
-                           tile_lds_bytes(levels), s, ix, levels, use_table, group, b, order, reads, offs, ends,
+                           tile_lds_bytes(levels), s, ix, levels, use_table, group, 0, b, order, reads, offs, ends,
                            nreads, out);
     }
     return hipGetLastError();
@@ -1476,7 +1583,7 @@ __global__ __launch_bounds__(64) void search_long_kernel(DevIndex ix, const uint
         if (is_long) {
             const LdsQuery q{slot[lane]};
             if (COUNT) { nsearched++; nqwords += (uint32_t)((lm.m + 31) >> 5); }
-            out[rid] = match_read<kLongWords>(ix, nullptr, nullptr, 0, use_table, q, lm.m, mv_mine, cnt);
+            out[rid] = match_read<kLongWords>(ix, nullptr, nullptr, 0, use_table, q, lm.m, mv_mine, kNoBudget, cnt);
             cnt.touch(out + rid, 16);
         }
         __syncthreads();  // before the next chunk rewrites the slots
@@ -1659,24 +1766,24 @@ hipError_t launch_sort(const BatchBuffers &b, int64_t nreads, int lo_bit, int hi
 }
 
 hipError_t launch_search_tuned(const DevIndex &ix, int levels, int use_table, int block, int grid, int group,
-                               const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
+                               int defer, const BatchBuffers &b, const uint32_t *order, const uint8_t *reads,
                                const int64_t *offs, const int64_t *ends, int64_t nreads, int words, void *out,
                                bool count, hipStream_t s) {
     int4 *o = static_cast<int4 *>(out);
     if (group < 1 || (offs && order)) return hipErrorInvalidValue;
     if (words != kShortWords && words != kWMax) return hipErrorInvalidValue;
     if (count)  // counts do not depend on the workgroup shape or the work split
-        return launch_tuned_block<256, true>(ix, levels, use_table, group, grid * (block / 256), b, order, reads, offs,
+        return launch_tuned_block<256, true>(ix, levels, use_table, group, defer, grid * (block / 256), b, order, reads, offs,
                                              ends, nreads, words, o, s);
     switch (block) {
         case 256:
-            return launch_tuned_block<256, false>(ix, levels, use_table, group, grid, b, order, reads, offs, ends, nreads,
+            return launch_tuned_block<256, false>(ix, levels, use_table, group, defer, grid, b, order, reads, offs, ends, nreads,
                                                    words, o, s);
         case 512:
-            return launch_tuned_block<512, false>(ix, levels, use_table, group, grid, b, order, reads, offs, ends, nreads,
+            return launch_tuned_block<512, false>(ix, levels, use_table, group, defer, grid, b, order, reads, offs, ends, nreads,
                                                    words, o, s);
         case 1024:
-            return launch_tuned_block<1024, false>(ix, levels, use_table, group, grid, b, order, reads, offs, ends, nreads,
+            return launch_tuned_block<1024, false>(ix, levels, use_table, group, defer, grid, b, order, reads, offs, ends, nreads,
                                                    words, o, s);
         default: return hipErrorInvalidValue;
     }

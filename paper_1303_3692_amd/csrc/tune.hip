@@ -52,7 +52,7 @@ std::string cfg_json(const sa_match_cfg &c) {
     std::ostringstream o;
     o << "\"tile_levels\":" << c.tile_levels << ",\"block\":" << c.block << ",\"blocks_per_cu\":" << c.blocks_per_cu
       << ",\"group\":" << c.group << ",\"prefix_table\":" << c.prefix_table << ",\"sort\":" << c.sort
-      << ",\"inline_pack\":" << c.inline_pack << ",\"max_words\":" << c.max_words
+      << ",\"inline_pack\":" << c.inline_pack << ",\"max_words\":" << c.max_words << ",\"defer\":" << c.defer
       << ",\"nbuckets\":" << c.nbuckets << ",\"bucket_edge\":[";
     for (int i = 0; i < c.nbuckets; i++) o << (i ? "," : "") << c.bucket_edge[i];
     o << "]";
@@ -84,6 +84,7 @@ bool parse_cached(const std::string &path, const std::string &key, sa_match_cfg 
         c.sort = json_int(line, "sort", 1);
         c.inline_pack = json_int(line, "inline_pack", 1);
         c.max_words = json_int(line, "max_words", kWMax);
+        c.defer = json_int(line, "defer", 0);
         c.nbuckets = std::max(1, std::min(8, json_int(line, "nbuckets", 1)));
         const size_t p = line.find("\"bucket_edge\":[");
         if (p != std::string::npos) {
@@ -158,6 +159,7 @@ sa_match_cfg base_cfg(const sa_dindex *d) {
     c.group = 4;
     c.prefix_table = d->view.ptab_k > 0 ? 1 : 0;
     c.max_words = kWMax;
+    c.defer = kDefaultDefer;
     return c;
 }
 
@@ -241,6 +243,21 @@ std::vector<sa_match_cfg> stage1c_candidates(const sa_dindex *d, const sa_match_
     return out;
 }
 
+// Stage 1d, around the best so far, when the search kernel packs its reads:
+// the probe budget after which a read is set aside for a chunk of such
+// reads (0 = never).
+std::vector<sa_match_cfg> stage1d_candidates(const sa_match_cfg &top) {
+    std::vector<sa_match_cfg> out;
+    if (top.sort != 0 || !top.inline_pack) return out;
+    for (int b : {0, 2, 3, 4, 6, 8}) {
+        if (b == top.defer) continue;
+        sa_match_cfg c = top;
+        c.defer = b;
+        out.push_back(c);
+    }
+    return out;
+}
+
 // Stage 2, around the best so far: bucket layouts.  Buckets only order the
 // reads through the sort keys, so they are tried only when the reads are
 // sorted.
@@ -273,6 +290,7 @@ extern "C" int sa_tune_candidates(const sa_dindex *d, const int64_t *d_offs, int
     std::vector<sa_match_cfg> all = stage1_candidates(d);
     for (const auto &c : stage1b_candidates(d, top)) all.push_back(c);
     for (const auto &c : stage1c_candidates(d, top, hist)) all.push_back(c);
+    for (const auto &c : stage1d_candidates(top)) all.push_back(c);
     sa_match_cfg sorted = top;
     if (sorted.sort == 0) sorted.sort = 1;
     for (const auto &c : stage2_candidates(sorted, hist)) all.push_back(c);
@@ -361,10 +379,10 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
         ms = best_rep;
         if (std::getenv("SAMATCH_TUNE_LOG"))
             std::fprintf(stderr,
-                         "tune: levels=%d block=%d per_cu=%d group=%d table=%d sort=%d inline=%d words=%d buckets=%d -> "
+                         "tune: levels=%d block=%d per_cu=%d group=%d table=%d sort=%d inline=%d words=%d defer=%d buckets=%d -> "
                          "%.4f ms\n",
                          c.tile_levels, c.block, c.blocks_per_cu, c.group, c.prefix_table, c.sort, c.inline_pack,
-                         c.max_words, c.nbuckets, ms);
+                         c.max_words, c.defer, c.nbuckets, ms);
         return SA_OK;
     };
     auto try_all = [&](const std::vector<sa_match_cfg> &cands) -> int {
@@ -380,6 +398,7 @@ extern "C" int sa_tune(sa_dindex *d, const uint8_t *d_reads, const int64_t *d_of
     rc = try_all(stage1_candidates(d));
     if (rc == SA_OK) rc = try_all(stage1b_candidates(d, top));
     if (rc == SA_OK) rc = try_all(stage1c_candidates(d, top, hist));
+    if (rc == SA_OK) rc = try_all(stage1d_candidates(top));
     if (rc == SA_OK) rc = try_all(stage2_candidates(top, hist));
     if (rc == SA_OK && top_ms >= 1e30) rc = fail(SA_EINVAL, "tuner: no valid candidate");
     if (rc == SA_OK) {

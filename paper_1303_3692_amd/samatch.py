@@ -49,14 +49,14 @@ class MatchCfg(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int), ("nbuckets", ctypes.c_int), ("bucket_edge", ctypes.c_int * 8),
                 ("sort", ctypes.c_int), ("use_graph", ctypes.c_int), ("profile", ctypes.c_int),
                 ("count", ctypes.c_int), ("group", ctypes.c_int), ("prefix_table", ctypes.c_int),
-                ("inline_pack", ctypes.c_int), ("max_words", ctypes.c_int)]
+                ("inline_pack", ctypes.c_int), ("max_words", ctypes.c_int), ("defer", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {"kernel": self.kernel, "tile_levels": self.tile_levels, "block": self.block,
                 "blocks_per_cu": self.blocks_per_cu, "nbuckets": self.nbuckets,
                 "bucket_edge": list(self.bucket_edge)[:max(1, self.nbuckets)], "sort": self.sort,
                 "use_graph": self.use_graph, "group": self.group, "prefix_table": self.prefix_table,
-                "inline_pack": self.inline_pack, "max_words": self.max_words}
+                "inline_pack": self.inline_pack, "max_words": self.max_words, "defer": self.defer}
 
 
 class ServerOpts(ctypes.Structure):

@@ -63,6 +63,11 @@ CONFIGS = [
     ("tuned-words5-b512", dict(max_words=5, sort=0, inline_pack=1, block=512, blocks_per_cu=3)),
     ("tuned-words5-b256-no-table", dict(max_words=5, sort=0, inline_pack=1, prefix_table=0, block=256,
                                         blocks_per_cu=6, group=1)),
+    # reads set aside after 1 probe (most reads with a search), or never
+    ("tuned-defer1-b1024", dict(defer=1, sort=0, inline_pack=1, block=1024, blocks_per_cu=1)),
+    ("tuned-defer1-words5", dict(defer=1, max_words=5, sort=0, inline_pack=1, block=256, blocks_per_cu=6, group=1)),
+    ("tuned-defer1-no-table", dict(defer=1, prefix_table=0, sort=0, inline_pack=1, group=2)),
+    ("tuned-no-defer", dict(defer=0, sort=0, inline_pack=1)),
 ]
 
 
@@ -291,6 +296,7 @@ def test_inline_pack_spans(device):
     data, offs = oracle.pack_reads(reads)
     want = oracle.match(text, sa, data, offs)
     variants = [S.cfg(d, sort=0, inline_pack=v) for v in (1, 0)] + [S.cfg(d, sort=0, inline_pack=1, max_words=5)]
+    variants += [S.cfg(d, sort=0, inline_pack=1, defer=1, max_words=w) for w in (5, 10)]
     for c in variants:
         assert_same(run_dev(d, data[:-1], offs, device, c), want, f"inline={c.inline_pack}/{c.max_words}")
         # the same reads 5 bytes into the buffer
@@ -334,9 +340,10 @@ def test_host_batch_in_chunks(device):
 
 @pytest.mark.parametrize("kind", ["iid", "tandem"])
 def test_prefix_table_lengths(device, kind):
-    """The prefix table rebuilt for every length from 4 to 12 bases (and
+    """The prefix table rebuilt for every length from 4 to 15 bases (and
     dropped): the oracle's bits each time, with the table's first-pivot
-    entries, empty brackets and end suffixes shorter than k exercised."""
+    entries, empty brackets and end suffixes shorter than k exercised.
+    Lengths past 15 are refused."""
     say("case: prefix table lengths", kind)
     rng = random.Random(41 if kind == "iid" else 43)
     n = 60_000
@@ -359,8 +366,11 @@ def test_prefix_table_lengths(device, kind):
     data, offs = oracle.pack_reads(reads)
     want = oracle.match(text, oracle.sa_build(text), data, offs)
     d = S.sa_upload(S.sa_build(text), 0)
-    for k in (4, 5, 6, 7, 8, 9, 10, 11, 12, 0):
+    for k in (4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 0):
         d.set_prefix_table(k)
         assert d.index_bytes()["prefix_table"] == (16 * (4 ** k + 1) if k else 0)
         for name, c in (("default", S.cfg(d)), ("b1024", S.cfg(d, block=1024, blocks_per_cu=1, group=1))):
             assert_same(run_dev(d, data, offs, device, c), want, f"{kind}/k={k}/{name}")
+    for k in (1, 3, 16, 32):
+        with pytest.raises(S.SaError):
+            d.set_prefix_table(k)
