@@ -202,9 +202,10 @@ def main():
         # the search kernel packs the reads itself (no pack pass) when the
         # batch is in input order and its tile plus one packing area per
         # wave fit in LDS (160 KB less room for static variables); an area
-        # holds the span of 64 reads of 32 * max_words bases (kernels.h)
+        # holds 64 slots of 2 * max_words + 1 16-byte pieces (codes and
+        # flags) and a queue of 128 set-aside read ids (kernels.h)
         tile = ((1 << c.tile_levels) - 1) * 12
-        area = (((128 * c.max_words + 1 + 4) * 6 + 8) + 15) // 16 * 16
+        area = (((64 * (2 * c.max_words + 1) + 4) * 6 + 8) + 15) // 16 * 16 + 4 * 128
         return (c.kernel == S.SA_KERNEL_TUNED and c.inline_pack == 1 and c.sort == 0 and
                 ((tile + 15) // 16 * 16 + (c.block // 64) * area) <= 160 * 1024 - 256)
 
