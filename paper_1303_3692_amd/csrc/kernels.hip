@@ -931,9 +931,11 @@ __device__ __forceinline__ Span chunk_span(const uint8_t *__restrict__ reads, bo
 
 // Pieces of a staged span a wave holds in registers between chunks (lane l
 // holds pieces l, l + 64, ...); the rest of a longer span is loaded when it
-// is converted.
+// is converted.  Two for the 10-word kernel (on MI355X, 4 and 3 left it
+// more registers and a mixed 20-300-base batch 9 % and 5 % slower; 1 was
+// 1 % slower), one for the 5-word kernel.
 #ifndef SAMATCH_INLINE_AHEAD
-#define SAMATCH_INLINE_AHEAD 4
+#define SAMATCH_INLINE_AHEAD 2
 #endif
 constexpr int kInlineAhead = SAMATCH_INLINE_AHEAD;
 

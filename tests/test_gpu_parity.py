@@ -178,6 +178,23 @@ def test_long_and_too_long_reads(device):
     assert e.value.code == S.SA_ETOOBIG
 
 
+def test_invalid_settings_refused(device):
+    """Launch settings outside their ranges are refused before any launch,
+    with SA_EINVAL; the largest probe budget is accepted."""
+    say("case: invalid settings")
+    rng = random.Random(5)
+    text = "".join(rng.choice("ACGT") for _ in range(8000))
+    d = S.sa_upload(S.sa_build(text), 0)
+    data, offs = oracle.pack_reads(["ACGT", "GGA", text[100:180]])
+    for kw in (dict(defer=-1), dict(defer=1025), dict(max_words=7), dict(block=128), dict(sort=3),
+               dict(tile_levels=14), dict(group=65), dict(inline_pack=2)):
+        with pytest.raises(S.SaError) as e:
+            run_dev(d, data[:-1], offs, device, S.cfg(d, **kw))
+        assert e.value.code == S.SA_EINVAL, kw
+    want = oracle.match(text, oracle.sa_build(text), data, offs)
+    assert_same(run_dev(d, data[:-1], offs, device, S.cfg(d, defer=1024)), want, "largest budget")
+
+
 @pytest.mark.parametrize("cfg,n,count", [("c1", 1_000_000, 100_000), ("c2", 2_000_000, 200_000),
                                          ("c3", 2_000_000, 150_000), ("c4", 3_000_000, 150_000)])
 def test_generated_workloads(device, cfg, n, count):
