@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark: open-loop Poisson requests over resident references")
     ap.add_argument("--serve-refs", default="c2,c4", help="references kept resident for --serve")
+    ap.add_argument("--serve-linger-us", type=int, default=0,
+                    help="--serve: a batch waits up to this long for max_batch_reads reads (0: starts at once)")
+    ap.add_argument("--serve-batch-reads", type=int, default=1 << 20, help="--serve: reads per device batch")
     ap.add_argument("--serve-requests", type=int, default=4000, help="measured requests per load level")
     ap.add_argument("--serve-warmup", type=int, default=400, help="warm-up requests per load level")
     ap.add_argument("--serve-pool", type=int, default=800, help="distinct requests the streams draw from")
@@ -678,7 +681,8 @@ def serve_bench(args, np, torch, gen, S):
             # at its scheduled time (open loop), so no interpreter lock sits
             # in the measured loop; measure 1 times each batch's search
             # stage with events, measure 2 runs the instrumented kernels
-            srv = S.Server(dix, max_batch_reads=1 << 20, nstreams=args.serve_streams, measure=measure)
+            srv = S.Server(dix, max_batch_reads=args.serve_batch_reads, nstreams=args.serve_streams, measure=measure,
+                           batch_linger_us=args.serve_linger_us)
             res = srv.replay([r.ref for r in stream], [r.reads.data for r in stream], [r.reads.offs for r in stream],
                              [int(r.t_arrival * 1e9) for r in stream], nthreads=32)
             tot = srv.stats()
@@ -720,7 +724,8 @@ def serve_bench(args, np, torch, gen, S):
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic (seeded generators, no external data)",
         "config": {"workload": "c5: open-loop Poisson requests over the " + " and ".join(names) + " references, "
                                "1-100,000 reads each (log-uniform), 30-300 bp", "requests_per_level": args.serve_requests,
-                   "distinct_requests": args.serve_pool},
+                   "distinct_requests": args.serve_pool, "batch_linger_us": args.serve_linger_us,
+                   "max_batch_reads": args.serve_batch_reads},
         "offline_reads_per_s": round(x_off, 1), "levels": levels,
         "served_touched_bytes_per_read": round(touched_per_read, 1),
     }

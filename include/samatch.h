@@ -369,6 +369,12 @@ typedef struct {
     int measure;                 /* 0: off; 1: time each batch's search stage with events;
                                     2: also run the instrumented search kernels and add up
                                     the bytes they touch (slower); see sa_server_get_stats */
+    int64_t batch_linger_us;     /* 0 (default): a free stream starts a batch with whatever
+                                    reads are waiting; > 0 (at most 1,000,000): it waits
+                                    until a reference has max_batch_reads unscheduled reads
+                                    or its oldest one has waited this long, so that batches
+                                    are larger (the device busier per launch) at the price
+                                    of latency */
 } sa_server_opts;
 
 /* Totals of a server since it started.  upload_bytes: request images copied

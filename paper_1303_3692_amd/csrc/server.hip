@@ -16,8 +16,9 @@
 // reads from HBM, and a round's upload overlaps the searches of the batches
 // admitted before it.  Each free stream slot then takes up to
 // max_batch_reads unscheduled reads of one reference, from the admitted
-// requests of that reference in admission order, and runs one pipeline over
-// them (a small kernel expands the batch's pieces into each read's start
+// requests of that reference in admission order (with batch_linger_us, only
+// once it holds max_batch_reads reads or its oldest read has waited that
+// long), and runs one pipeline over them (a small kernel expands the batch's pieces into each read's start
 // and end from the offsets stored with the reads).  A scatter thread copies
 // a finished batch's results into the owners' output arrays while the loop
 // keeps scheduling; a request whose reads are all done is finished and its
@@ -247,6 +248,7 @@ struct sa_server {
     bool admit_locked();
     int upload_locked();
     bool launch(Slot &sl, std::unique_lock<std::mutex> &lk);
+    int64_t linger_left_ns(int ref, int64_t now) const;
     bool reap(Slot &sl);
     void measure_batch(Slot &sl);
     void settle_locked(Slot &sl);
@@ -365,6 +367,22 @@ int sa_server::upload_locked() {
     return rc;
 }
 
+// With batch_linger_us set: how much longer a batch of reference ref waits
+// for more reads (0 when it may start: its oldest unscheduled read has
+// waited long enough, or it holds max_batch_reads reads).
+int64_t sa_server::linger_left_ns(int ref, int64_t now) const {
+    const auto &q = active[(size_t)ref];
+    if (o.batch_linger_us <= 0 || q.empty()) return 0;
+    const int64_t left = q.front()->t_admit + o.batch_linger_us * 1000 - now;
+    if (left <= 0) return 0;
+    int64_t rows = 0;
+    for (const Request *r : q) {
+        rows += r->nreads - r->next;
+        if (rows >= o.max_batch_reads) return 0;
+    }
+    return left;
+}
+
 // Form a batch for a free slot from one reference's admitted requests.
 // The pieces are taken with the lock held; the per-read work (start and end
 // arrays) and the launches run with it released, so that submitters and
@@ -372,10 +390,11 @@ int sa_server::upload_locked() {
 // request with batches in flight keeps its buffers).
 bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
     const int nref = (int)refs.size();
+    const int64_t now = o.batch_linger_us > 0 ? now_ns() : 0;
     int ref = -1;
     for (int k = 0; k < nref; k++) {
         const int cand = (next_ref + k) % nref;
-        if (!active[(size_t)cand].empty()) { ref = cand; break; }
+        if (!active[(size_t)cand].empty() && linger_left_ns(cand, now) == 0) { ref = cand; break; }
     }
     if (ref < 0) return false;
     next_ref = (ref + 1) % nref;
@@ -598,7 +617,16 @@ void sa_server::run() {
             std::this_thread::sleep_for(std::chrono::microseconds(20));
             lk.lock();
         } else {
-            cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            // idle: wake for new work, or when a lingering batch may start
+            int64_t wait_ns = 5000000;
+            if (o.batch_linger_us > 0) {
+                const int64_t now = now_ns();
+                for (int ref = 0; ref < (int)refs.size(); ref++) {
+                    const int64_t left = linger_left_ns(ref, now);
+                    if (left > 0) wait_ns = std::min(wait_ns, left);
+                }
+            }
+            cv_work.wait_for(lk, std::chrono::nanoseconds(wait_ns));
         }
     }
 }
@@ -665,8 +693,11 @@ extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const s
         o.test_echo = opts->test_echo;
         o.test_fail_batch = opts->test_fail_batch;
         o.measure = opts->measure;
+        o.batch_linger_us = opts->batch_linger_us;
     }
     if (o.measure < 0 || o.measure > 2) return fail(SA_EINVAL, "measure must be 0, 1 or 2");
+    if (o.batch_linger_us < 0 || o.batch_linger_us > 1000000)
+        return fail(SA_EINVAL, "batch_linger_us must be in 0..1000000");
     if (o.nstreams > 8) return fail(SA_EINVAL, "nstreams must be at most 8");
     if (o.max_batch_reads > INT32_MAX) return fail(SA_EINVAL, "max_batch_reads too large");
     for (int i = 0; i < nrefs; i++) {

@@ -63,7 +63,7 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_reserve_bytes", ctypes.c_int64), ("max_batch_reads", ctypes.c_int64),
                 ("max_inflight_reads", ctypes.c_int64), ("nstreams", ctypes.c_int),
                 ("test_fake_free_hbm", ctypes.c_int64), ("test_echo", ctypes.c_int), ("test_fail_batch", ctypes.c_int),
-                ("host_pool_bytes", ctypes.c_int64), ("measure", ctypes.c_int)]
+                ("host_pool_bytes", ctypes.c_int64), ("measure", ctypes.c_int), ("batch_linger_us", ctypes.c_int64)]
 
 
 class ServerStats(ctypes.Structure):

@@ -99,10 +99,12 @@ def test_open_loop_stream_and_budget(refs, pool):
     srv.destroy()
 
 
-def test_replayed_stream(refs):
+@pytest.mark.parametrize("linger", [0, 2000])
+def test_replayed_stream(refs, linger):
     """The native load-test client on the device: an open-loop stream over
-    both references, every result identical to the same reads matched alone."""
-    print("case: serving replay", flush=True)
+    both references, every result identical to the same reads matched alone
+    (batches starting at once, or waiting up to 2 ms to fill)."""
+    print("case: serving replay, linger", linger, flush=True)
     rng = np.random.default_rng(14)
     stream = []
     for i in range(80):
@@ -110,7 +112,7 @@ def test_replayed_stream(refs):
         spec = gen.ReadSpec(2900 + i, int(rng.integers(0, 5000)), 30, 300, 0.3, 0.0, 0.02)
         stream.append((which, gen.make_reads(refs[which][0], spec)))
     arrival = np.cumsum(rng.exponential(200_000, size=len(stream))).astype(np.int64)  # ~5,000 requests/s
-    srv = S.Server([r[3] for r in refs], max_batch_reads=1 << 16, nstreams=2)
+    srv = S.Server([r[3] for r in refs], max_batch_reads=1 << 16, nstreams=2, batch_linger_us=linger)
     outs, sched, stats = srv.replay([w for w, _ in stream], [r.data for _, r in stream], [r.offs for _, r in stream],
                                     arrival, nthreads=4)
     srv.destroy()

@@ -155,6 +155,42 @@ def test_submit_validation_and_unknown_ticket():
     srv.destroy()
 
 
+def test_batch_linger_waits_for_a_full_batch_or_its_deadline():
+    """With batch_linger_us, a batch starts once it holds max_batch_reads
+    reads or its oldest read has waited that long; results are unchanged."""
+    rng = np.random.default_rng(11)
+    linger_ns = 300_000_000
+    srv = S.Server([None, None], test_echo=1, max_batch_reads=1000, batch_linger_us=linger_ns // 1000)
+    # a lone small request waits out the deadline
+    data, offs = make_request(rng, 10)
+    t, out = srv.submit(0, data, offs)
+    rc, st = wait_all(srv, [t])[t]
+    assert rc == S.SA_OK and (out == echo_expect(offs, t, 0, data)).all()
+    assert st["t_done_ns"] - st["t_admit_ns"] >= linger_ns
+    # a request that fills a batch by itself starts at once
+    data, offs = make_request(rng, 1000)
+    t, out = srv.submit(1, data, offs)
+    rc, st = wait_all(srv, [t])[t]
+    assert rc == S.SA_OK and (out == echo_expect(offs, t, 1, data)).all()
+    assert st["t_done_ns"] - st["t_admit_ns"] < linger_ns // 2
+    # small requests that fill a batch together start as soon as the last arrives
+    reqs = []
+    for i in range(4):
+        data, offs = make_request(rng, 250)
+        reqs.append((srv.submit(0, data, offs), data, offs))
+    res = wait_all(srv, [r[0][0] for r in reqs])
+    for (t, out), data, offs in reqs:
+        rc, st = res[t]
+        assert rc == S.SA_OK and (out == echo_expect(offs, t, 0, data)).all()
+    last_admit = max(res[r[0][0]][1]["t_admit_ns"] for r in reqs)
+    assert max(res[r[0][0]][1]["t_done_ns"] for r in reqs) - last_admit < linger_ns // 2
+    srv.destroy()
+    for bad in (-1, 1_000_001):
+        with pytest.raises(S.SaError) as e:
+            S.Server([None], test_echo=1, batch_linger_us=bad)
+        assert e.value.code == S.SA_EINVAL
+
+
 def test_destroy_with_pending_requests():
     rng = np.random.default_rng(5)
     srv = S.Server([None, None], test_echo=1, max_inflight_reads=20, max_batch_reads=5)
