@@ -116,6 +116,23 @@ __device__ __forceinline__ uint64_t text_word(const uint64_t *__restrict__ text,
 typedef uint64_t u64x2_a8 __attribute__((ext_vector_type(2), aligned(8)));
 __device__ __forceinline__ u64x2_a8 load_u64x2(const uint64_t *p) { return *reinterpret_cast<const u64x2_a8 *>(p); }
 
+// 16 bytes read once: a non-temporal load, so that the caches keep lines
+// that are used again (the text) rather than prefix-table entries, row
+// records and ASCII reads, which a search touches once (on MI355X this took
+// the 250 Mbp / 64M-read batch from 6.47 to 5.93 ms, results unchanged).
+__device__ __forceinline__ uint4 load_stream16(const void *p) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// A 16-byte result, written once and not read again by the kernels.
+__device__ __forceinline__ void store_stream16(int4 *p, int4 r) {
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    const i32x4 v = {r.x, r.y, r.z, r.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<i32x4 *>(p));
+}
+
 // Two consecutive 32-bit words with one 8-byte load, 4-byte aligned.
 typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 __device__ __forceinline__ u32x2_a4 load_u32x2(const uint32_t *p) { return *reinterpret_cast<const u32x2_a4 *>(p); }
@@ -203,7 +220,7 @@ struct RowHead {
 };
 
 __device__ __forceinline__ RowHead row_head(const RowRec *__restrict__ rows, int r) {
-    const uint4 v = *reinterpret_cast<const uint4 *>(rows + r);
+    const uint4 v = load_stream16(rows + r);
     RowHead h;
     h.pos = (int32_t)v.x;
     h.len = (int32_t)v.y;
@@ -366,7 +383,8 @@ __device__ __forceinline__ bool lb_search_table(const DevIndex &ix, const Q &q, 
                                                 int4 &ans, int &left, Cnt &cnt) {
     const int K = ix.ptab_k;
     const uint32_t v = (uint32_t)(q[0] >> (64 - 2 * K));
-    const PrefixEntry ent = ix.ptab[v];
+    const uint4 e4 = load_stream16(ix.ptab + v);
+    const PrefixEntry ent{e4.x, e4.y, (int32_t)e4.z, e4.w};
     cnt.index_touch(ix.ptab + v, 16);
     cnt.table_probe();
     if (ent.size & kPtabAnswer) {
@@ -869,7 +887,7 @@ __device__ __forceinline__ bool tuned_regs(const DevIndex &ix, const uint64_t *s
     for (int k = 0; k < W; ++k) q[k] = w[k];
     const int4 r = match_read<W>(ix, s_key, s_sa, levels, use_table, q, m, mv, budget, cnt);
     if (r.w == (int)kHitDeferred) return true;
-    out[rid] = r;
+    store_stream16(out + rid, r);
     cnt.touch(out + rid, 16);
     return false;
 }
@@ -946,7 +964,7 @@ __device__ __forceinline__ void span_prefetch(const Span &sp, int lane, uint4 (&
     for (int u = 0; u < AHEAD; ++u) {
         const int c = 64 * u + lane;
         if (c < sp.nvec) {
-            v[u] = src[c];
+            v[u] = load_stream16(src + c);
             cnt.touch(src + c, 16);
         }
     }
@@ -971,7 +989,7 @@ __device__ __forceinline__ bool span_convert(const Span &sp, const uint4 (&v)[AH
         for (int u = 0; u < 4; ++u) {
             const int c = c0 + 64 * u + lane;
             if (c < sp.nvec) {
-                r[u] = src[c];
+                r[u] = load_stream16(src + c);
                 cnt.touch(src + c, 16);
             }
         }
@@ -1010,7 +1028,7 @@ __device__ __forceinline__ bool gather_convert(const uint8_t *__restrict__ reads
             const int n_owner = __shfl(np, owner & 63, 64);
             in[u] = c < 64 * S && k < n_owner;
             if (in[u]) {
-                r[u] = reinterpret_cast<const uint4 *>(base)[k];
+                r[u] = load_stream16(reinterpret_cast<const uint4 *>(base) + k);
                 cnt.touch(reinterpret_cast<const uint4 *>(base) + k, 16);
             }
         }
