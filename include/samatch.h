@@ -199,7 +199,8 @@ typedef struct {
                             set aside and searched again, without a limit,
                             together with 63 other such reads, so that one long
                             search does not keep 63 lanes of its wave idle
-                            (0..1024; 0 = never).  Results never change.       */
+                            (0..1024; 0 = never; the index default is 3).
+                            Results never change.                              */
 } sa_match_cfg;
 
 /* Fill cfg with the index's current defaults. */
