@@ -228,6 +228,7 @@ struct sa_server {
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> queued;                  // not admitted yet, arrival order
     std::vector<std::deque<Request *>> active;     // per reference, admitted with reads left to schedule
+    std::vector<int64_t> unscheduled;              // per reference, reads of `active` not yet in a batch
     std::map<uint64_t, std::unique_ptr<Request>> all;
     uint64_t next_ticket = 1;
     int64_t inflight_reads = 0;
@@ -308,6 +309,7 @@ bool sa_server::admit_locked() {
         } else {
             if (!o.test_echo) to_upload.push_back(r);
             active[(size_t)r->ref].push_back(r);
+            unscheduled[(size_t)r->ref] += r->nreads;
         }
         any = true;
     }
@@ -361,6 +363,7 @@ int sa_server::upload_locked() {
     // none of them is in a batch yet: drop them from scheduling
     for (Request *r : rs) {
         auto &q = active[(size_t)r->ref];
+        if (std::find(q.begin(), q.end(), r) != q.end()) unscheduled[(size_t)r->ref] -= r->nreads - r->next;
         q.erase(std::remove(q.begin(), q.end(), r), q.end());
         finish_locked(r, SA_EDEVICE);
     }
@@ -372,15 +375,9 @@ int sa_server::upload_locked() {
 // waited long enough, or it holds max_batch_reads reads).
 int64_t sa_server::linger_left_ns(int ref, int64_t now) const {
     const auto &q = active[(size_t)ref];
-    if (o.batch_linger_us <= 0 || q.empty()) return 0;
+    if (o.batch_linger_us <= 0 || q.empty() || unscheduled[(size_t)ref] >= o.max_batch_reads) return 0;
     const int64_t left = q.front()->t_admit + o.batch_linger_us * 1000 - now;
-    if (left <= 0) return 0;
-    int64_t rows = 0;
-    for (const Request *r : q) {
-        rows += r->nreads - r->next;
-        if (rows >= o.max_batch_reads) return 0;
-    }
-    return left;
+    return left > 0 ? left : 0;
 }
 
 // Form a batch for a free slot from one reference's admitted requests.
@@ -408,6 +405,7 @@ bool sa_server::launch(Slot &sl, std::unique_lock<std::mutex> &lk) {
         const int64_t take = std::min(r->nreads - r->next, o.max_batch_reads - rows);
         sl.pieces.push_back(Piece{r, r->next, take, rows});
         r->next += take;
+        unscheduled[(size_t)ref] -= take;
         r->inflight_batches++;
         rows += take;
         if (r->next == r->nreads) q.pop_front();
@@ -564,6 +562,7 @@ void sa_server::settle_locked(Slot &sl) {
             if (r->failed) {
                 // drop the rest of a failed request from scheduling
                 auto &q = active[(size_t)r->ref];
+                if (std::find(q.begin(), q.end(), r) != q.end()) unscheduled[(size_t)r->ref] -= r->nreads - r->next;
                 q.erase(std::remove(q.begin(), q.end(), r), q.end());
                 finish_locked(r, r->fail_code);
             } else if (r->done == r->nreads) {
@@ -706,6 +705,7 @@ extern "C" int sa_server_create(const sa_dindex *const *refs, int nrefs, const s
     }
     s->o = o;
     s->active.resize((size_t)nrefs);
+    s->unscheduled.assign((size_t)nrefs, 0);
     s->slots.resize((size_t)o.nstreams);
     auto setup = [&]() -> int {
         if (o.test_echo) {
@@ -919,6 +919,7 @@ extern "C" int sa_server_destroy(sa_server *s) {
             }
             q.clear();
         }
+        std::fill(s->unscheduled.begin(), s->unscheduled.end(), 0);
         s->cv_work.notify_all();
     }
     if (s->loop.joinable()) s->loop.join();
