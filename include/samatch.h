@@ -104,10 +104,11 @@ void sa_free(sa_index *ix);                           /* NULL is a no-op        
  * never touch the text), the table of the top levels of the
  * implicit binary-search tree that the tuned kernel stages in LDS (the tile
  * of Section IV), and, for n >= 4096, a prefix table: for every string v of
- * k = round(log4 n) + 1 bases (4 <= k <= 15), the first SA row whose suffix is
- * not below v with the bracket of rows that start with v, or the result of
- * the reads that start with v when there are none (4^k + 1 entries of 16
- * bytes; see sa_set_prefix_table).  The host index may be
+ * k = round(log4 n) + 2 bases (4 <= k <= 16, fewer while the table would
+ * take more than a quarter of the free device memory), the first SA row
+ * whose suffix is not below v with the bracket of rows that start with v,
+ * or the result of the reads that start with v when there are none (4^k + 1
+ * entries of 16 bytes; see sa_set_prefix_table).  The host index may be
  * freed afterwards.  Released with sa_dfree (NULL is a no-op). */
 int sa_upload(const sa_index *ix, int device, sa_dindex **out);
 void sa_dfree(sa_dindex *d);
@@ -130,10 +131,11 @@ int sa_build_device(const char *text, int64_t n, int device, sa_dindex **out);
 int sa_dindex_bytes(const sa_dindex *d, int64_t bytes[5]);
 
 /* Rebuild the prefix table of a resident index for strings of k bases
- * (4 <= k <= 15, texts of at least 4096 bases), or drop it (k = 0).  The
- * default is k = round(log4 n) + 1, at most 15.  Entries are 16 bytes, one per
- * k-base string v (4^k + 1 in all): the first SA row not below v, and either
- * the size of the bracket of rows that start with v with the position and
+ * (4 <= k <= 16, texts of at least 4096 bases), or drop it (k = 0).  The
+ * default is k = round(log4 n) + 2, at most 16 (see sa_upload).  Entries
+ * are 16 bytes, one per k-base string v (4^k + 1 in all): the first SA row
+ * not below v, and either the size of the bracket of rows that start with v
+ * with the position and
  * bases k .. k+15 of the suffix at its first search pivot, or, when no
  * suffix starts with v, the result every read starting with v gets (its
  * longest matched prefix is shorter than k and depends on v alone).

@@ -304,17 +304,21 @@ int run_batch(sa_dindex *d, Workspace *ws, const uint8_t *d_reads, const int64_t
 
 namespace {
 
-// Prefix-table length of a text of n bases: round(log4 n) + 1, so that a
-// table entry's bracket holds about a quarter of a row (most lookups then
-// need at most the one probe whose suffix travels with the entry), at most
-// kMaxPrefixBases; none below 4096 bases.  The table takes about 64 bytes
-// per base (4^k 16-byte entries).  On MI355X the extra base cut the search
-// by 15 % for a 250 Mbp reference (17 GB table) and by 8 % for a 16 Mbp one
-// against round(log4 n); a base fewer made it 16 % slower.
-int default_prefix_bases(int64_t n) {
+// Prefix-table length of a text of n bases: round(log4 n) + 2, so that a
+// table entry's bracket holds about a sixteenth of a row (most lookups then
+// need at most the one probe whose suffix travels with the entry, and its
+// first 32 bases come with the entry too), at most kMaxPrefixBases, and
+// shorter while the table would take more than a quarter of the device
+// memory free (free_bytes); none below 4096 bases.  The table takes 4^k
+// 16-byte entries, about 256 bytes per base.  On MI355X, for a 250 Mbp
+// reference (k = 16, a 68.7 GB table), each base added cut the search by
+// about 11-15 % (k = 14: 6.47 ms, 15: 6.05, 16: 5.40); for a 16 Mbp
+// reference k = 13 and 14 gained 8 % and 3 %.
+int default_prefix_bases(int64_t n, size_t free_bytes) {
     if (n < 4096) return 0;
-    const int k = (int)std::lround(std::log2((double)n) / 2.0) + 1;
-    return std::max(4, std::min(kMaxPrefixBases, k));
+    int k = std::max(4, std::min(kMaxPrefixBases, (int)std::lround(std::log2((double)n) / 2.0) + 2));
+    while (k > 4 && (((size_t)1 << (2 * k)) + 1) * sizeof(PrefixEntry) > free_bytes / 4) k--;
+    return k;
 }
 
 // (Re)build the prefix table of d with k bases (0: none).  Captured graphs
@@ -407,7 +411,9 @@ int make_dindex(int device, int64_t n, const std::vector<uint64_t> &packed, cons
     v.rows = d->d_rows;
     v.n = (int32_t)n;
     d->view = v;
-    if (int rc = set_prefix_table(d.get(), default_prefix_bases(n))) return rc;
+    size_t free_bytes = 0, total_bytes = 0;
+    if ((e = hipMemGetInfo(&free_bytes, &total_bytes)) != hipSuccess) return hip_fail(e, "device memory query");
+    if (int rc = set_prefix_table(d.get(), default_prefix_bases(n, free_bytes))) return rc;
     sa_match_cfg &c = d->defaults;
     std::memset(&c, 0, sizeof c);
     c.kernel = SA_KERNEL_TUNED;

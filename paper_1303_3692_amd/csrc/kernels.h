@@ -77,10 +77,9 @@ struct DevIndex {
     int32_t n;
     int32_t ptab_k;            // bases indexed by the prefix table (0: no table)
 };
-// Longest prefix a table may index: its build launches one work-item per
-// entry, and a dispatch holds fewer than 2^32 work-items (4^15 + 1 entries:
-// 16 GiB).
-constexpr int kMaxPrefixBases = 15;
+// Longest prefix a table may index: an entry holds the 16 bases after its
+// k, which must lie in the suffix's first 32 (4^16 + 1 entries: 64 GiB).
+constexpr int kMaxPrefixBases = 16;
 
 struct BucketTable {
     int count;     // 1..8

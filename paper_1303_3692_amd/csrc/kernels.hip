@@ -495,9 +495,10 @@ __device__ __forceinline__ uint64_t row_order_key(const DevIndex &ix, int k, int
 }
 
 // T[v] = first row whose order key reaches 2v + 1 (binary search per entry).
-__global__ void build_prefix_table_kernel(DevIndex ix, int k, int64_t entries, PrefixEntry *__restrict__ tab) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= entries) return;
+__global__ void build_prefix_table_kernel(DevIndex ix, int k, int64_t first, int64_t end,
+                                          PrefixEntry *__restrict__ tab) {
+    const int64_t v = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= end) return;
     const uint64_t target = 2 * (uint64_t)v + 1;
     int lo = 0, hi = ix.n;
     while (lo < hi) {
@@ -512,9 +513,10 @@ __global__ void build_prefix_table_kernel(DevIndex ix, int k, int64_t entries, P
 // and first pivot suffix, or, for a string v no suffix starts with, the
 // result of a search for v itself from the root (any read starting with v
 // has it: its longest matched prefix is shorter than v).
-__global__ void fill_prefix_entries_kernel(DevIndex ix, int k, int64_t entries, PrefixEntry *__restrict__ tab) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= entries) return;
+__global__ void fill_prefix_entries_kernel(DevIndex ix, int k, int64_t first, int64_t end, int64_t entries,
+                                           PrefixEntry *__restrict__ tab) {
+    const int64_t v = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= end) return;
     if (v == entries - 1) {  // T[4^k] = n closes the last bracket; it is never looked up
         tab[v].size = 0;
         tab[v].pos = 0;
@@ -1810,11 +1812,21 @@ hipError_t launch_search_tuned(const DevIndex &ix, int levels, int use_table, in
 }
 
 hipError_t launch_build_prefix_table(const DevIndex &ix, int k, PrefixEntry *tab, hipStream_t s) {
+    // one work-item per entry, in slices of 2^30 entries (a dispatch holds
+    // fewer than 2^32 work-items); every T[v] is written before any entry
+    // is filled, since the second pass reads T[v + 1]
     const int64_t entries = ((int64_t)1 << (2 * k)) + 1;
-    hipLaunchKernelGGL(build_prefix_table_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix, k,
-                       entries, tab);
-    hipLaunchKernelGGL(fill_prefix_entries_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, ix, k,
-                       entries, tab);
+    const int64_t slice = (int64_t)1 << 30;
+    for (int64_t first = 0; first < entries; first += slice) {
+        const int64_t end = std::min(entries, first + slice);
+        hipLaunchKernelGGL(build_prefix_table_kernel, dim3((unsigned)((end - first + 255) / 256)), dim3(256), 0, s,
+                           ix, k, first, end, tab);
+    }
+    for (int64_t first = 0; first < entries; first += slice) {
+        const int64_t end = std::min(entries, first + slice);
+        hipLaunchKernelGGL(fill_prefix_entries_kernel, dim3((unsigned)((end - first + 255) / 256)), dim3(256), 0, s,
+                           ix, k, first, end, entries, tab);
+    }
     return hipGetLastError();
 }
 

@@ -357,10 +357,11 @@ def test_host_batch_in_chunks(device):
 
 @pytest.mark.parametrize("kind", ["iid", "tandem"])
 def test_prefix_table_lengths(device, kind):
-    """The prefix table rebuilt for every length from 4 to 15 bases (and
-    dropped): the oracle's bits each time, with the table's first-pivot
-    entries, empty brackets and end suffixes shorter than k exercised.
-    Lengths past 15 are refused."""
+    """The prefix table rebuilt for every length from 4 to 16 bases (and
+    dropped; 16 bases: 4^16 + 1 entries, built in several dispatches): the
+    oracle's bits each time, with the table's first-pivot entries, empty
+    brackets and end suffixes shorter than k exercised.  Lengths past 16 are
+    refused."""
     say("case: prefix table lengths", kind)
     rng = random.Random(41 if kind == "iid" else 43)
     n = 60_000
@@ -383,11 +384,11 @@ def test_prefix_table_lengths(device, kind):
     data, offs = oracle.pack_reads(reads)
     want = oracle.match(text, oracle.sa_build(text), data, offs)
     d = S.sa_upload(S.sa_build(text), 0)
-    for k in (4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 0):
+    for k in (4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 0):
         d.set_prefix_table(k)
         assert d.index_bytes()["prefix_table"] == (16 * (4 ** k + 1) if k else 0)
         for name, c in (("default", S.cfg(d)), ("b1024", S.cfg(d, block=1024, blocks_per_cu=1, group=1))):
             assert_same(run_dev(d, data, offs, device, c), want, f"{kind}/k={k}/{name}")
-    for k in (1, 3, 16, 32):
+    for k in (1, 3, 17, 32):
         with pytest.raises(S.SaError):
             d.set_prefix_table(k)
